@@ -1,0 +1,178 @@
+"""Effective field, Landau-Lifshitz torque and energies (oracle, FP64, CPU).
+
+Material parameters come as a dict of 256-entry region look-up tables
+(paper section "Material Regions"):
+  msat[256] (A/m), aex[256] (J/m), alpha[256], ku1[256], ku2[256] (J/m^3),
+  anis_u[256, 3] (unit vectors), bext[256, 3] (T),
+  exch_scale[256*257//2]: the inter-region scale S(i, j) for i >= j stored at
+  i*(i+1)//2 + j (a lower-triangular matrix indexed by the two regions);
+  S(i, i) is taken as 1 whatever is stored there,
+  gamma_ll (rad/(T s)).
+The region map is a uint8 array [nz, ny, nx]; m is [3, nz, ny, nx].
+"""
+import math
+
+import numpy as np
+
+from . import demag as _demag
+from .constants import GAMMA_LL
+
+
+def _lut(params, key, region):
+    return np.asarray(params[key], dtype=np.float64)[region]
+
+
+def exchange_scale(params, ra, rb):
+    """S(ra, rb) from the packed lower-triangular table; 1 inside a region."""
+    hi = np.maximum(ra, rb).astype(np.int64)
+    lo = np.minimum(ra, rb).astype(np.int64)
+    s = np.asarray(params["exch_scale"], dtype=np.float64)[hi * (hi + 1) // 2 + lo]
+    return np.where(ra == rb, 1.0, s)
+
+
+def exchange_coefficient(params, ra, rb):
+    """2 S 2 l1 l2 / (l1 + l2) with l = Aex/Msat (paper Eq. eqBexch).
+
+    Inside one region this is 2 Aex/Msat (Eq. eqBexch1).  A cell with Msat = 0
+    is not magnetic: the pair then has no coupling (the neighbour counts as
+    missing, which is the Neumann rule of the paper)."""
+    msat = np.asarray(params["msat"], dtype=np.float64)
+    aex = np.asarray(params["aex"], dtype=np.float64)
+    ma, mb = msat[ra], msat[rb]
+    ok = (ma > 0) & (mb > 0)
+    la = np.where(ok, aex[ra] / np.where(ok, ma, 1.0), 0.0)
+    lb = np.where(ok, aex[rb] / np.where(ok, mb, 1.0), 0.0)
+    den = la + lb
+    hm = np.where(ok & (den > 0), 2.0 * la * lb / np.where(den > 0, den, 1.0), 0.0)
+    return 2.0 * exchange_scale(params, ra, rb) * hm
+
+
+def exchange_field(m, region, params, cell):
+    """6-neighbour exchange field (T), paper Eqs. eqBexch1 / eqBexch.
+
+    B(c) = sum over the existing neighbours n of c(r_c, r_n) (m_n - m_c) / D_n^2.
+    A neighbour outside the grid is replaced by the cell itself (Neumann
+    boundary), i.e. it contributes nothing."""
+    m = np.asarray(m, dtype=np.float64)
+    B = np.zeros_like(m)
+    for axis, d in zip((3, 2, 1), cell):       # array axis of x, y, z
+        n = m.shape[axis]
+        if n < 2:
+            continue
+        lo = [slice(None)] * 4
+        hi = [slice(None)] * 4
+        lo[axis] = slice(0, n - 1)
+        hi[axis] = slice(1, n)
+        rlo = region[tuple(lo[1:])]
+        rhi = region[tuple(hi[1:])]
+        coef = exchange_coefficient(params, rlo, rhi) / (d * d)
+        diff = m[tuple(hi)] - m[tuple(lo)]
+        B[tuple(lo)] += coef * diff            # neighbour on the + side
+        B[tuple(hi)] -= coef * diff            # neighbour on the - side
+    return B * (_lut(params, "msat", region) > 0)
+
+
+def anisotropy_field_parts(m, region, params):
+    """Uniaxial anisotropy field split as (Ku1 part, Ku2 part), in tesla.
+
+    B = (2 Ku1 / Msat)(u.m) u + (4 Ku2 / Msat)(u.m)^3 u.  The paper prints
+    B_sat in the denominator; Msat is the reading that has units of tesla
+    and satisfies the paper's energy identity E = -Ku1 (u.m)^2 - Ku2 (u.m)^4."""
+    m = np.asarray(m, dtype=np.float64)
+    msat = _lut(params, "msat", region)
+    u = np.moveaxis(np.asarray(params["anis_u"], dtype=np.float64)[region], -1, 0)
+    inv = np.where(msat > 0, 1.0 / np.where(msat > 0, msat, 1.0), 0.0)
+    um = np.sum(u * m, axis=0)
+    b1 = 2.0 * _lut(params, "ku1", region) * inv * um * u
+    b2 = 4.0 * _lut(params, "ku2", region) * inv * um ** 3 * u
+    return b1, b2
+
+
+def zeeman_field(region, params):
+    """Applied field B_ext of each cell's region (T), paper section "Landau-Lifshitz torque"."""
+    b = np.moveaxis(np.asarray(params["bext"], dtype=np.float64)[region], -1, 0)
+    return b * (_lut(params, "msat", region) > 0)
+
+
+def magnetisation(m, region, params):
+    """M = Msat m (A/m)."""
+    return _lut(params, "msat", region) * np.asarray(m, dtype=np.float64)
+
+
+class Problem:
+    """A grid with its materials: evaluates B_eff, the torque and the energies.
+
+    grid = (nx, ny, nz), cell = (dx, dy, dz) in metres; demag=False drops the
+    magnetostatic term (the paper's EnableDemag = false)."""
+
+    def __init__(self, grid, cell, region, params, demag=True, workers=None):
+        self.grid = tuple(int(v) for v in grid)
+        self.cell = tuple(float(v) for v in cell)
+        self.region = np.asarray(region, dtype=np.uint8).reshape(self.grid[::-1])
+        self.params = params
+        self.demag = demag
+        self.workers = workers
+        self.gamma = float(params.get("gamma_ll", 0.0) or GAMMA_LL)
+        self.octant = _demag.tensor_octant(self.grid, self.cell) if demag else None
+        self.magnetic = _lut(params, "msat", self.region) > 0
+
+    # -- field terms ---------------------------------------------------------
+    def demag_field(self, m):
+        if not self.demag:
+            return np.zeros((3,) + self.region.shape)
+        M = magnetisation(m, self.region, self.params)
+        return _demag.demag_field_fft(M, self.octant, workers=self.workers)
+
+    def terms(self, m):
+        """Dict of the field terms at m: demag, exch, anis1, anis2, zeeman (T)."""
+        b1, b2 = anisotropy_field_parts(m, self.region, self.params)
+        return {
+            "demag": self.demag_field(m),
+            "exch": exchange_field(m, self.region, self.params, self.cell),
+            "anis1": b1,
+            "anis2": b2,
+            "zeeman": zeeman_field(self.region, self.params),
+        }
+
+    def beff(self, m):
+        """Effective field (T); zero in cells with Msat = 0."""
+        t = self.terms(m)
+        b = t["demag"] + t["exch"] + t["anis1"] + t["anis2"] + t["zeeman"]
+        return b * self.magnetic
+
+    def torque(self, m, precess=True):
+        """Landau-Lifshitz torque (1/s), paper Eq. eqLLG with the sign that damps.
+
+        tau = -gamma/(1+alpha^2) [m x B + alpha m x (m x B)]; with precess=False
+        (relax, section "Energy minimization") the m x B term is dropped."""
+        return llg_torque(m, self.beff(m), _lut(self.params, "alpha", self.region),
+                          self.gamma, precess) * self.magnetic
+
+    def energy(self, m):
+        """Energies (J) from the fields, paper Eqs. for E_demag, E_exch, E_anis.
+
+        E = V sum[-1/2 M.B_demag - 1/2 M.B_exch - 1/2 M.B_anis(Ku1)
+                  - 1/4 M.B_anis(Ku2) - M.B_ext], summed with math.fsum."""
+        t = self.terms(m)
+        M = magnetisation(m, self.region, self.params)
+        vol = self.cell[0] * self.cell[1] * self.cell[2]
+        dens = {
+            "demag": -0.5 * np.sum(M * t["demag"], axis=0),
+            "exch": -0.5 * np.sum(M * t["exch"], axis=0),
+            "anis": -0.5 * np.sum(M * t["anis1"], axis=0) - 0.25 * np.sum(M * t["anis2"], axis=0),
+            "zeeman": -np.sum(M * t["zeeman"], axis=0),
+        }
+        e = {k: vol * math.fsum(v[self.magnetic].ravel()) for k, v in dens.items()}
+        e["total"] = math.fsum(e.values())
+        return e
+
+
+def llg_torque(m, B, alpha, gamma=GAMMA_LL, precess=True):
+    """tau = -gamma/(1+alpha^2) [m x B + alpha m x (m x B)] (precession term optional)."""
+    m = np.asarray(m, dtype=np.float64)
+    mxb = np.cross(m, B, axis=0)
+    mxmxb = np.cross(m, mxb, axis=0)
+    pre = -gamma / (1.0 + alpha * alpha)
+    if precess:
+        return pre * (mxb + alpha * mxmxb)
+    return pre * alpha * mxmxb
