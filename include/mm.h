@@ -1,0 +1,251 @@
+/*
+ * mm.h -- C ABI of the MI355X micromagnetic effective-field / torque library.
+ *
+ * The library evaluates, on one AMD MI355X (gfx950), the hot path of the
+ * finite-difference micromagnetic method of Vansteenkiste et al., "The design
+ * and verification of MuMax3" (arXiv:1406.7635):
+ *   - the magnetostatic field as a zero-padded FFT convolution of M = Msat m
+ *     with the cell-averaged demagnetising kernel (section "Magnetostatic
+ *     field"),
+ *   - the 6-neighbour exchange field over region-indexed materials with the
+ *     harmonic-mean inter-region coupling (section "Heisenberg exchange
+ *     interaction", Eqs. eqBexch1 and eqBexch),
+ *   - uniaxial anisotropy (section "Magneto-crystalline anisotropy") and the
+ *     applied (Zeeman) field,
+ *   - the Landau-Lifshitz torque (Eq. eqLLG) and the Runge-Kutta solvers of
+ *     section "Dynamics" with the adaptive step of section "Adaptive time
+ *     step", and relax() of section "Energy minimization".
+ *
+ * Units are SI throughout: m is a unit vector, B in tesla, t in seconds,
+ * Msat in A/m, Aex in J/m, Ku in J/m^3, gamma in rad/(T s).
+ *
+ * Memory and layout.  Every pointer whose name ends in _dev is device memory
+ * owned by the caller (e.g. a torch tensor).  Vector fields are FP32
+ * structure-of-arrays [3][nz][ny][nx] with x fastest (all x components, then
+ * all y, then all z).  The region map is uint8 [nz][ny][nx].  The library never
+ * frees caller memory; the context owns every scratch buffer, allocated in
+ * mm_create and freed in mm_destroy.
+ *
+ * Streams and synchronisation.  All work is enqueued on the HIP stream given
+ * to mm_create (NULL = the legacy default stream).  Calls that return host
+ * scalars (mm_rk45_step, mm_rk23_step, mm_run, mm_relax, mm_energy,
+ * mm_max_torque) synchronise that stream before returning; the others return
+ * as soon as the work is enqueued.  A context is not thread-safe.
+ *
+ * Errors.  Every int-returning call returns an mm_status; no exception or
+ * abort crosses the ABI.  mm_strerror() gives a static description.  After
+ * MM_EDEVICE the context should be destroyed.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MM_OK = 0,
+    MM_EINVAL = -1,          /* bad argument (null pointer, non-positive size, NaN parameter) */
+    MM_ENOMEM = -2,          /* device allocation failed */
+    MM_EDEVICE = -3,         /* a HIP runtime call failed */
+    MM_EUNSUPPORTED = -4,    /* valid but not supported: padded length > 4096, PBC */
+    MM_ENONFINITE = -5,      /* a step produced a non-finite error estimate */
+    MM_ESTEP = -6,           /* the adaptive step fell below dt_min */
+    MM_ENOTCONVERGED = -7,   /* relax hit max_steps before MaxErr reached its floor */
+    MM_ESTATE = -8           /* call order: e.g. demag enabled but kernel not initialised */
+} mm_status;
+
+#define MM_NREGIONS 256
+#define MM_NPAIRS (MM_NREGIONS * (MM_NREGIONS + 1) / 2)
+
+typedef struct mm_ctx mm_ctx;
+
+/* Finite-difference grid (section "Material Regions"): nx*ny*nz orthorhombic
+ * cells of dx*dy*dz metres.  Each axis is zero-padded for the aperiodic
+ * convolution to the power of two >= 2n-1 (no padding when n = 1); padded
+ * lengths above 4096 return MM_EUNSUPPORTED.  pbc must be {0,0,0}. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy, dz;
+    int32_t pbc[3];
+} mm_grid;
+
+/* Region look-up tables (section "Material Regions": a 256-entry table per
+ * parameter indexed by the cell's region; interfacial parameters in a lower
+ * triangular matrix indexed by the two regions).  Msat = 0 marks a
+ * non-magnetic cell: its B_eff and torque are zero and it does not couple by
+ * exchange.  exch_scale[i*(i+1)/2 + j], i >= j, is the inter-region scale S of
+ * Eq. eqBexch; S(i,i) is taken as 1 whatever is stored.  anis_u need not be
+ * normalised by the caller: it is used as given.  gamma_ll = 0 selects the
+ * default 1.7595e11 rad/(T s). */
+typedef struct {
+    double msat[MM_NREGIONS];
+    double aex[MM_NREGIONS];
+    double alpha[MM_NREGIONS];
+    double ku1[MM_NREGIONS];
+    double ku2[MM_NREGIONS];
+    double anis_u[MM_NREGIONS][3];
+    double bext[MM_NREGIONS][3];
+    double exch_scale[MM_NPAIRS];
+    double gamma_ll;
+} mm_params;
+
+/* Adaptive-step options (section "Adaptive time step").  max_err is the
+ * paper's MaxErr (default 1e-5 when <= 0), headroom its 0.8 (default when
+ * <= 0); dt is clamped to [dt_min, dt_max] (dt_max <= 0 means unbounded).
+ * precess = 0 drops the m x B term (relax). */
+typedef struct {
+    double max_err;
+    double headroom;
+    double dt_min;
+    double dt_max;
+    int32_t precess;
+    int32_t reserved;
+} mm_solver_opts;
+
+/* Counters of a multi-step run. */
+typedef struct {
+    int64_t steps;       /* accepted steps */
+    int64_t rejects;     /* rejected attempts */
+    int64_t evals;       /* torque evaluations (B_eff + torque passes) */
+    double t;            /* time reached */
+    double dt;           /* next step size */
+    double err;          /* error estimate of the last attempt */
+} mm_run_stats;
+
+/* Sizes chosen by the context, for callers and tests. */
+typedef struct {
+    int32_t px, py, pz;          /* padded FFT lengths */
+    int32_t kx;                  /* px/2 + 1 spectral columns */
+    int32_t ncomp;               /* demag kernel components stored: 4 (nz == 1) or 6 */
+    int32_t reserved;
+    int64_t ncell;
+    int64_t khat_elems;          /* floats in the FP32 kernel spectrum */
+    int64_t device_bytes;        /* device memory owned by the context */
+} mm_info;
+
+/* Create a context for grid g with parameters p on the given HIP stream
+ * (hipStream_t passed as void*, NULL for the default stream).  region_dev is a
+ * caller-owned uint8 [nz][ny][nx] device array, copied into the context.
+ * Allocates every buffer; derives the FP32 region tables and the exchange
+ * pair table on the device.  Demag is enabled but needs mm_demag_kernel_init
+ * before the first field evaluation.  Returns MM_EINVAL for null pointers,
+ * non-positive sizes or non-finite cell sizes, MM_EUNSUPPORTED for padded
+ * lengths above 4096 or non-zero pbc, MM_ENOMEM if allocation fails. */
+int mm_create(mm_ctx **out, const mm_grid *g, const mm_params *p, const uint8_t *region_dev,
+              void *hip_stream);
+
+/* Build the demagnetising kernel (section "Magnetostatic field", paragraph
+ * "Magnetostatic kernel"): the cell-averaged tensor N(d) for every cell
+ * displacement in FP64 on the GPU -- Newell's closed form near the origin,
+ * Gauss-Legendre quadrature of the dipole tensor far away -- mirrored into the
+ * padded grid using its symmetries, Fourier transformed in FP64, scaled by
+ * -mu0 / (px py pz) and truncated to FP32.  Only the non-redundant octant of
+ * the real spectrum is kept (4 components in 2D, 6 in 3D).  Temporary FP64
+ * buffers are allocated and freed inside the call.  Synchronous. */
+int mm_demag_kernel_init(mm_ctx *c);
+
+/* Replace the material tables (same validation as mm_create).  Invalidates
+ * the solver's cached first-stage torque. */
+int mm_set_params(mm_ctx *c, const mm_params *p);
+
+/* enable = 0 drops the magnetostatic term (the paper's EnableDemag = false). */
+int mm_set_demag(mm_ctx *c, int32_t enable);
+
+/* B_eff = B_demag + B_exch + B_anis + B_ext at m (section "Landau-Lifshitz
+ * torque", list of contributions).  beff_dev: [3][nz][ny][nx] output.
+ * bdemag_dev may be NULL; otherwise it receives the magnetostatic field
+ * alone, in every cell (including Msat = 0 cells, where B_eff is 0). */
+int mm_beff(mm_ctx *c, const float *m_dev, float *beff_dev, float *bdemag_dev);
+
+/* Landau-Lifshitz torque (Eq. eqLLG, damping sign):
+ * tau = -gamma/(1+alpha^2) [m x B + alpha m x (m x B)], m x B dropped when
+ * precess = 0.  Elementwise from a given field; tau_dev in 1/s. */
+int mm_llg_torque(mm_ctx *c, const float *m_dev, const float *beff_dev, float *tau_dev,
+                  int32_t precess);
+
+/* Fused evaluation of B_eff and the torque at m (one "torque evaluation" in
+ * the sense of the paper's throughput, section "Performance"). */
+int mm_torque(mm_ctx *c, const float *m_dev, float *tau_dev, int32_t precess);
+
+/* One classical RK4 step of fixed size dt (not among the paper's solvers;
+ * provided for fixed-step trajectories), then m is renormalised. */
+int mm_rk4_step(mm_ctx *c, float *m_dev, double dt, int32_t precess);
+
+/* One attempt of the Dormand-Prince 5(4) pair (section "Dynamics", RK45)
+ * from (m, *t) with step *dt.  eps = dt max_cells |sum_j (b_j - b*_j) k_j|
+ * (section "Adaptive time step"); accepted when eps <= max_err, in which case
+ * m <- normalise(5th-order solution) and *t += dt.  *dt is replaced by the
+ * next step: dt headroom (max_err/eps)^(1/5) clamped to [0.1, 2] times dt
+ * (2 when eps = 0) and to [dt_min, dt_max].  The torque of the last stage is
+ * cached and reused as the next step's first (first-same-as-last); it is
+ * recomputed after mm_solver_reset, mm_set_params, mm_set_demag, a change of
+ * m pointer or of precess.  Synchronous. */
+int mm_rk45_step(mm_ctx *c, float *m_dev, double *t, double *dt, const mm_solver_opts *o,
+                 int32_t *accepted, double *err);
+
+/* Same for the Bogacki-Shampine 3(2) pair (RK32 of the paper; exponent 1/3). */
+int mm_rk23_step(mm_ctx *c, float *m_dev, double *t, double *dt, const mm_solver_opts *o,
+                 int32_t *accepted, double *err);
+
+/* Advance with solver 45 (Dormand-Prince) or 23 (Bogacki-Shampine) until
+ * t_end (the last step is clipped to land on it) or until max_attempts
+ * attempts, with the step controller running on the device (no host
+ * round trip per step).  *t and *dt are read and updated.  stats may be NULL.
+ * Returns MM_ESTEP / MM_ENONFINITE if the run stopped on those conditions. */
+int mm_run(mm_ctx *c, float *m_dev, int32_t solver, double t_end, int64_t max_attempts,
+           double *t, double *dt, const mm_solver_opts *o, mm_run_stats *stats);
+
+/* relax() of section "Energy minimization": precession off, RK23 steps in
+ * blocks of 3; an energy phase until the total energy stops decreasing, then
+ * torque phases until max|tau| stops decreasing, halving MaxErr (starting
+ * from o->max_err) after each, until MaxErr < min_max_err (1e-9 if <= 0).
+ * Energies are FP64 reductions on the device.  Outputs may be NULL.
+ * MM_ENOTCONVERGED if max_steps attempts were used first. */
+int mm_relax(mm_ctx *c, float *m_dev, const mm_solver_opts *o, double min_max_err,
+             int64_t max_steps, double *energy_out, double *max_torque_out, int64_t *steps_out);
+
+/* Energies in joules (FP64 reduction on the device), in the order demag,
+ * exchange, anisotropy, Zeeman, total: V sum[-1/2 M.B_demag - 1/2 M.B_exch
+ * - 1/2 M.B_anis(Ku1) - 1/4 M.B_anis(Ku2) - M.B_ext]. e_terms5: host double[5]. */
+int mm_energy(mm_ctx *c, const float *m_dev, double *e_terms5);
+
+/* max over cells of |tau| (1/s) at m. */
+int mm_max_torque(mm_ctx *c, const float *m_dev, int32_t precess, double *out);
+
+/* Forget the cached first-stage torque (call after changing m in place). */
+int mm_solver_reset(mm_ctx *c);
+
+int mm_get_info(mm_ctx *c, mm_info *info);
+
+/* Diagnostics.  mm_demag_tensor_dump writes the FP64 real-space tensor N(d)
+ * for d = (i dx, j dy, k dz), 0 <= i < nx etc., as [6][nz][ny][nx] doubles
+ * (component order xx, yy, zz, xy, xz, yz) into out_dev (recomputed on the
+ * device).  mm_demag_kernel_dump copies the FP32 kernel spectrum, layout
+ * [ky_h][kx][kz_h][6] in 3D or [kx][ky_h][4] when nz == 1 (h = folded index
+ * 0..p/2), khat_elems floats.  mm_exchange_dump writes the per-face exchange
+ * coefficient c(r, r_n)/D^2 actually gathered by the field kernels, as
+ * [6][nz][ny][nx] floats in face order -x, +x, -y, +y, -z, +z (0 where the
+ * neighbour is missing). */
+int mm_demag_tensor_dump(mm_ctx *c, double *out_dev);
+int mm_demag_kernel_dump(mm_ctx *c, float *out_dev);
+int mm_exchange_dump(mm_ctx *c, float *out_dev);
+
+/* Kernel timing with HIP events on the context stream.  mm_timing_enable(c,
+ * which, 1) records an event pair around every later launch of kernel class
+ * `which` (0 = x-forward FFT pass, 1 = column (y/z) convolution pass,
+ * 2 = x-inverse FFT + field/torque pass); mm_timing_read returns the number of
+ * launches and the summed milliseconds since enabling (synchronises). */
+int mm_timing_enable(mm_ctx *c, int32_t which, int32_t enable);
+int mm_timing_read(mm_ctx *c, int32_t which, int64_t *launches, double *total_ms);
+
+void mm_destroy(mm_ctx *c);
+const char *mm_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

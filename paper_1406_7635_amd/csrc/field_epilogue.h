@@ -1,0 +1,203 @@
+// field_epilogue.h -- per-cell local field terms, torque and reductions.
+//
+// Everything a cell needs once its magnetostatic field is known:
+//   exchange (Eqs. eqBexch1 / eqBexch: 6 neighbours, harmonic-mean pair
+//   coefficients from the packed lower-triangular table, missing or
+//   non-magnetic neighbours contribute nothing -- the Neumann rule),
+//   uniaxial anisotropy (2 Ku1/Msat (u.m) u + 4 Ku2/Msat (u.m)^3 u),
+//   the applied field, the Landau-Lifshitz torque of Eq. eqLLG with the
+//   damping sign, the embedded Runge-Kutta error norm and FP64 energies.
+#pragma once
+
+#include "mm_internal.h"
+
+namespace mm {
+
+__device__ inline float3 ld3(const float* __restrict__ p, long long n, long long i) {
+    return make_float3(p[i], p[n + i], p[2 * n + i]);
+}
+__device__ inline void st3(float* __restrict__ p, long long n, long long i, float3 v) {
+    p[i] = v.x;
+    p[n + i] = v.y;
+    p[2 * n + i] = v.z;
+}
+__device__ inline float3 f3add(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ inline float3 f3sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ inline float3 f3scale(float s, float3 a) { return make_float3(s * a.x, s * a.y, s * a.z); }
+__device__ inline float f3dot(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline float3 f3cross(float3 a, float3 b) {
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+__device__ inline int pair_index(int a, int b) {
+    const int hi = a > b ? a : b, lo = a > b ? b : a;
+    return hi * (hi + 1) / 2 + lo;
+}
+
+__device__ inline float* kslot(const FieldArgs& a, int logical) {
+    return a.kbuf + (long long)a.st->perm[logical] * 3 * a.ncell;
+}
+
+// Stage state m_s = m0 + dt sum_j a_j k_j of one cell (FP32).
+__device__ inline float3 stage_state(const FieldArgs& a, long long cell, float dt) {
+    float3 m = ld3(a.m0, a.ncell, cell);
+    if (a.sd.nk > 0) {
+        float3 acc = make_float3(0.f, 0.f, 0.f);
+        for (int j = 0; j < a.sd.nk; ++j) {
+            float3 k = ld3(kslot(a, a.sd.kidx[j]), a.ncell, cell);
+            acc = f3add(acc, f3scale(a.sd.a[j], k));
+        }
+        m = f3add(m, f3scale(dt, acc));
+    }
+    return m;
+}
+
+// Exchange field at (x, y, z) from the state array mp.
+__device__ inline float3 exchange_at(const FieldArgs& a, const float* __restrict__ mp, long long cell,
+                                     int x, int y, int z, int r, float3 mc) {
+    float3 b = make_float3(0.f, 0.f, 0.f);
+    const long long n = a.ncell;
+    const long long sxy = (long long)a.nx * a.ny;
+#define MM_NB(cond, off, id2)                                               \
+    if (cond) {                                                            \
+        const long long nc = cell + (off);                                 \
+        const float c = a.ptab[pair_index(r, a.region[nc])] * (id2);       \
+        b = f3add(b, f3scale(c, f3sub(ld3(mp, n, nc), mc)));               \
+    }
+    MM_NB(x > 0, -1, a.idx2)
+    MM_NB(x < a.nx - 1, 1, a.idx2)
+    MM_NB(y > 0, -(long long)a.nx, a.idy2)
+    MM_NB(y < a.ny - 1, (long long)a.nx, a.idy2)
+    MM_NB(z > 0, -sxy, a.idz2)
+    MM_NB(z < a.nz - 1, sxy, a.idz2)
+#undef MM_NB
+    return b;
+}
+
+// Per-thread accumulators of the reductions.
+struct EpiAcc {
+    float errmax;
+    float tqmax;
+    double e[4];  // demag, exchange, anisotropy, Zeeman energy densities (summed)
+};
+
+__device__ inline void epi_init(EpiAcc& acc) {
+    acc.errmax = 0.f;
+    acc.tqmax = 0.f;
+    acc.e[0] = acc.e[1] = acc.e[2] = acc.e[3] = 0.0;
+}
+
+// Everything after the magnetostatic field for one cell.
+__device__ inline void epilogue(const FieldArgs& a, const float* __restrict__ mp, long long cell,
+                                int x, int y, int z, float3 bd, EpiAcc& acc) {
+    const int flags = a.flags;
+    const int r = a.region[cell];
+    const RegionLut L = a.lut[r];
+    const long long n = a.ncell;
+    if (flags & EPI_BDEMAG) st3(a.bdemag, n, cell, bd);
+    float3 tq = make_float3(0.f, 0.f, 0.f);
+    if (L.a.x == 0.f) {  // non-magnetic cell: no field, no torque
+        if (flags & EPI_BEFF) st3(a.beff, n, cell, tq);
+        if (flags & EPI_TORQUE) st3(a.sd.out_k >= 0 ? kslot(a, a.sd.out_k) : a.tau, n, cell, tq);
+        return;
+    }
+    const float3 m = ld3(mp, n, cell);
+    const float3 bex = exchange_at(a, mp, cell, x, y, z, r, m);
+    const float3 u = make_float3(L.b.x, L.b.y, L.b.z);
+    const float um = f3dot(u, m);
+    const float3 ban1 = f3scale(L.a.y * um, u);
+    const float3 ban2 = f3scale(L.a.z * um * um * um, u);
+    const float3 bz = make_float3(L.c.x, L.c.y, L.c.z);
+    const float3 B = f3add(f3add(bd, bex), f3add(f3add(ban1, ban2), bz));
+    if (flags & EPI_BEFF) st3(a.beff, n, cell, B);
+    if (flags & (EPI_TORQUE | EPI_MAXTQ | EPI_ERR)) {
+        const float3 mxb = f3cross(m, B);
+        const float3 mxmxb = f3cross(m, mxb);
+        const float alpha = L.a.w;
+        tq = (flags & EPI_PRECESS) ? f3scale(L.b.w, f3add(mxb, f3scale(alpha, mxmxb)))
+                                   : f3scale(L.b.w * alpha, mxmxb);
+        if (flags & EPI_TORQUE) st3(a.sd.out_k >= 0 ? kslot(a, a.sd.out_k) : a.tau, n, cell, tq);
+        if (flags & EPI_MAXTQ) acc.tqmax = fmaxf(acc.tqmax, sqrtf(f3dot(tq, tq)));
+        if (flags & EPI_ERR) {
+            float3 d = make_float3(0.f, 0.f, 0.f);
+            for (int j = 0; j < a.sd.nerr; ++j) {
+                const float3 k = (a.sd.eidx[j] == a.sd.out_k) ? tq : ld3(kslot(a, a.sd.eidx[j]), n, cell);
+                d = f3add(d, f3scale(a.sd.e[j], k));
+            }
+            acc.errmax = fmaxf(acc.errmax, sqrtf(f3dot(d, d)));
+        }
+    }
+    if (flags & EPI_ENERGY) {
+        const double ms = (double)L.a.x;
+        const double mx = ms * m.x, my = ms * m.y, mz = ms * m.z;
+        auto dot = [&](float3 b) { return mx * (double)b.x + my * (double)b.y + mz * (double)b.z; };
+        acc.e[0] += -0.5 * dot(bd);
+        acc.e[1] += -0.5 * dot(bex);
+        acc.e[2] += -0.5 * dot(ban1) - 0.25 * dot(ban2);
+        acc.e[3] += -dot(bz);
+    }
+}
+
+// Workgroup reductions ------------------------------------------------------
+__device__ inline float wave_max(float v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// red: LDS scratch of at least (NT/64) * 6 doubles.
+__device__ inline void epi_reduce(const FieldArgs& a, EpiAcc& acc, double* red, int blk) {
+    const int flags = a.flags;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = NT / 64;
+    if (flags & (EPI_ERR | EPI_MAXTQ)) {
+        const float e = wave_max(acc.errmax), t = wave_max(acc.tqmax);
+        if (lane == 0) {
+            red[wave * 6 + 4] = e;
+            red[wave * 6 + 5] = t;
+        }
+    }
+    if (flags & EPI_ENERGY) {
+        for (int i = 0; i < 4; ++i) {
+            const double s = wave_sum(acc.e[i]);
+            if (lane == 0) red[wave * 6 + i] = s;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (flags & EPI_ERR) {
+            float e = 0.f;
+            for (int w = 0; w < NW; ++w) e = fmaxf(e, (float)red[w * 6 + 4]);
+            atomicMax(&a.st->err_bits, __float_as_uint(e));
+        }
+        if (flags & EPI_MAXTQ) {
+            float t = 0.f;
+            for (int w = 0; w < NW; ++w) t = fmaxf(t, (float)red[w * 6 + 5]);
+            atomicMax(&a.st->tq_bits, __float_as_uint(t));
+        }
+        if (flags & EPI_ENERGY) {
+            for (int i = 0; i < 4; ++i) {
+                double s = 0.0;
+                for (int w = 0; w < NW; ++w) s += red[w * 6 + i];
+                a.partials[(long long)blk * 4 + i] = s;
+            }
+        }
+    }
+}
+
+// Map a dispatch index to a logical tile so that consecutive tiles land on the
+// same XCD (workgroups are dealt round-robin over the 8 XCDs), keeping
+// neighbouring rows/columns in one L2.
+__device__ inline int xcd_remap(int bid, int nblk) {
+    constexpr int NX = 8;
+    const int per = nblk / NX, rem = nblk % NX;
+    const int xcd = bid % NX, slot = bid / NX;
+    if (slot >= per) return bid;  // the ragged last round keeps its natural index
+    (void)rem;
+    return xcd * per + slot;
+}
+
+}  // namespace mm

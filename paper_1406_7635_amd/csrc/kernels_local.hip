@@ -1,0 +1,322 @@
+// kernels_local.hip -- table preparation, elementwise field pass without
+// demag, stage combine, step controller, finalisation and reductions.
+#include <math.h>
+
+#include "../../include/mm.h"
+#include "field_epilogue.h"
+
+namespace mm {
+
+// ---------------------------------------------------------------------------
+// Region tables (section "Material Regions") from the FP64 parameters.
+// lut: anisotropy prefactors 2 Ku1/Msat and 4 Ku2/Msat (the paper prints
+// B_sat; Msat is the reading with units of tesla), torque prefactor
+// -gamma/(1+alpha^2).  ptab: per region pair (i >= j, packed i(i+1)/2 + j)
+// the exchange coefficient 2 S(i,j) 2 l_i l_j/(l_i + l_j), l = Aex/Msat, of
+// Eq. eqBexch; S(i,i) = 1; 0 when either region is non-magnetic.
+__global__ void k_prepare_tables(const mm_params* __restrict__ p, RegionLut* __restrict__ lut,
+                                 float* __restrict__ ptab) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const double gamma = p->gamma_ll != 0.0 ? p->gamma_ll : GAMMA_DEFAULT;
+    if (i < NREG) {
+        const double ms = p->msat[i];
+        const double inv = ms > 0.0 ? 1.0 / ms : 0.0;
+        const double al = p->alpha[i];
+        RegionLut L;
+        L.a = make_float4((float)ms, (float)(2.0 * p->ku1[i] * inv), (float)(4.0 * p->ku2[i] * inv),
+                          (float)al);
+        L.b = make_float4((float)p->anis_u[i][0], (float)p->anis_u[i][1], (float)p->anis_u[i][2],
+                          (float)(-gamma / (1.0 + al * al)));
+        L.c = make_float4((float)p->bext[i][0], (float)p->bext[i][1], (float)p->bext[i][2], 0.f);
+        lut[i] = L;
+    }
+    if (i < NPAIR) {
+        int hi = (int)floor((sqrt(8.0 * i + 1.0) - 1.0) * 0.5);
+        while (hi * (hi + 1) / 2 > i) --hi;
+        while ((hi + 1) * (hi + 2) / 2 <= i) ++hi;
+        const int lo = i - hi * (hi + 1) / 2;
+        const double m1 = p->msat[hi], m2 = p->msat[lo];
+        double c = 0.0;
+        if (m1 > 0.0 && m2 > 0.0) {
+            const double l1 = p->aex[hi] / m1, l2 = p->aex[lo] / m2;
+            const double s = (hi == lo) ? 1.0 : p->exch_scale[i];
+            if (l1 + l2 > 0.0) c = 2.0 * s * (2.0 * l1 * l2 / (l1 + l2));
+        }
+        ptab[i] = (float)c;
+    }
+}
+
+hipError_t launch_prepare_tables(const double* params64, RegionLut* lut, float* ptab, hipStream_t s) {
+    hipLaunchKernelGGL(k_prepare_tables, dim3((NPAIR + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<const mm_params*>(params64), lut, ptab);
+    return hipGetLastError();
+}
+
+// FFT twiddles exp(-2 pi i m / pt), evaluated in FP64 and rounded once.
+__global__ void k_twiddles(cf* tw, int pt) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < pt) {
+        double s, c;
+        sincospi(-2.0 * (double)m / (double)pt, &s, &c);
+        tw[m] = mkc((float)c, (float)s);
+    }
+}
+
+hipError_t launch_twiddles(cf* tw, int pt, hipStream_t s) {
+    hipLaunchKernelGGL(k_twiddles, dim3((pt + 255) / 256), dim3(256), 0, s, tw, pt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stage combine m_s = m0 + dt sum a_j k_j (used when demag is off; with demag
+// the first FFT pass does it on the fly).
+__global__ void __launch_bounds__(NT) k_combine(const FieldArgs a) {
+    if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    if (i >= a.ncell) return;
+    st3(a.ms, a.ncell, i, stage_state(a, i, (float)a.st->dt));
+}
+
+hipError_t launch_combine(const FieldArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)((a.ncell + NT - 1) / NT)), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+// Field pass without the magnetostatic term: one thread per cell.
+__global__ void __launch_bounds__(NT) k_local(const FieldArgs a) {
+    __shared__ double red[(NT / 64) * 6];
+    if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    EpiAcc acc;
+    epi_init(acc);
+    if (i < a.ncell) {
+        const int x = (int)(i % a.nx);
+        const long long r = i / a.nx;
+        const int y = (int)(r % a.ny), z = (int)(r / a.ny);
+        const float* mp = a.sd.nk > 0 ? a.ms : a.m0;
+        epilogue(a, mp, i, x, y, z, make_float3(0.f, 0.f, 0.f), acc);
+    }
+    if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce(a, acc, red, blockIdx.x);
+}
+
+hipError_t launch_local(const FieldArgs& a, hipStream_t s, int* nblocks_out) {
+    const int nb = (int)((a.ncell + NT - 1) / NT);
+    if (nblocks_out) *nblocks_out = nb;
+    hipLaunchKernelGGL(k_local, dim3(nb), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+// Torque from a given field (Eq. eqLLG, damping sign).
+__global__ void __launch_bounds__(NT) k_llg(const FieldArgs a, const float* __restrict__ beff,
+                                            float* __restrict__ tau, int precess) {
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    if (i >= a.ncell) return;
+    const RegionLut L = a.lut[a.region[i]];
+    float3 t = make_float3(0.f, 0.f, 0.f);
+    if (L.a.x != 0.f) {
+        const float3 m = ld3(a.m0, a.ncell, i), B = ld3(beff, a.ncell, i);
+        const float3 mxb = f3cross(m, B), mxmxb = f3cross(m, mxb);
+        t = precess ? f3scale(L.b.w, f3add(mxb, f3scale(L.a.w, mxmxb))) : f3scale(L.b.w * L.a.w, mxmxb);
+    }
+    st3(tau, a.ncell, i, t);
+}
+
+hipError_t launch_llg(const FieldArgs& a, const float* beff, float* tau, int precess, hipStream_t s) {
+    hipLaunchKernelGGL(k_llg, dim3((unsigned)((a.ncell + NT - 1) / NT)), dim3(NT), 0, s, a, beff, tau,
+                       precess);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Solver state and the adaptive step controller (section "Adaptive time
+// step"): eps = dt max|sum (b - b*) k|; accept when eps <= MaxErr; next dt =
+// dt * clamp(headroom (MaxErr/eps)^(1/(q+1)), 0.1, 2) (2 when eps = 0),
+// clamped to [dt_min, dt_max] and clipped so the run lands on t_end.
+__global__ void k_set_state(DevState* st, double t, double dt, double t_end, double max_err,
+                            double headroom, double dt_min, double dt_max, int order_low,
+                            int reset_counters, int init_perm, long long target_steps) {
+    st->t = t;
+    st->dt = dt;
+    st->t_end = t_end;
+    st->max_err = max_err;
+    st->headroom = headroom;
+    st->dt_min = dt_min;
+    st->dt_max = dt_max;
+    st->order_low = order_low;
+    st->err_bits = 0u;
+    st->tq_bits = 0u;
+    st->accepted = 0;
+    st->done = 0;
+    st->target_steps = target_steps;
+    if (reset_counters) {
+        st->steps = st->rejects = st->evals = 0;
+        st->status = 0;
+        st->err = 0.0;
+    }
+    if (init_perm)
+        for (int i = 0; i < 8; ++i) st->perm[i] = i;
+}
+
+hipError_t launch_set_state(DevState* st, double t, double dt, double t_end, double max_err,
+                            double headroom, double dt_min, double dt_max, int order_low,
+                            int reset_counters, int init_perm, long long target_steps,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_set_state, dim3(1), dim3(1), 0, s, st, t, dt, t_end, max_err, headroom,
+                       dt_min, dt_max, order_low, reset_counters, init_perm, target_steps);
+    return hipGetLastError();
+}
+
+__global__ void k_reset_accum(DevState* st) {
+    st->err_bits = 0u;
+    st->tq_bits = 0u;
+}
+
+hipError_t launch_reset_accum(DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_accum, dim3(1), dim3(1), 0, s, st);
+    return hipGetLastError();
+}
+
+__global__ void k_controller(DevState* st, int last_k, int evals, int check_done) {
+    if (check_done && st->done) {
+        st->accepted = 0;  // a no-op attempt after the run ended: nothing to finalise
+        return;
+    }
+    const double emax = (double)__uint_as_float(st->err_bits);
+    const double dt = st->dt;
+    const double err = dt * emax;
+    st->err = err;
+    st->err_bits = 0u;
+    st->evals += evals;
+    if (!isfinite(err)) {
+        st->accepted = 0;
+        st->rejects += 1;
+        st->status = -5;  // MM_ENONFINITE
+        st->done = 1;
+        return;
+    }
+    const bool acc = err <= st->max_err;
+    double fac = 2.0;
+    if (err > 0.0) {
+        fac = st->headroom * pow(st->max_err / err, 1.0 / (double)(st->order_low + 1));
+        fac = fmin(2.0, fmax(0.1, fac));
+    }
+    const bool clipped = isfinite(st->t_end) && (st->t + dt >= st->t_end);
+    if (acc) {
+        st->t = clipped ? st->t_end : st->t + dt;
+        st->steps += 1;
+        if (last_k > 0) {
+            const int tmp = st->perm[0];
+            st->perm[0] = st->perm[last_k];
+            st->perm[last_k] = tmp;
+        }
+    } else {
+        st->rejects += 1;
+    }
+    st->accepted = acc ? 1 : 0;
+    double dtn = dt * fac;
+    if (st->dt_max > 0.0) dtn = fmin(dtn, st->dt_max);
+    if (dtn < st->dt_min) {
+        st->status = -6;  // MM_ESTEP
+        st->done = 1;
+    }
+    if (acc && clipped) st->done = 1;
+    if (st->target_steps > 0 && st->steps >= st->target_steps) st->done = 1;
+    if (isfinite(st->t_end) && st->t + dtn > st->t_end && st->t < st->t_end) dtn = st->t_end - st->t;
+    st->dt = dtn;
+}
+
+hipError_t launch_controller(DevState* st, int last_k, int evals, int check_done, hipStream_t s) {
+    hipLaunchKernelGGL(k_controller, dim3(1), dim3(1), 0, s, st, last_k, evals, check_done);
+    return hipGetLastError();
+}
+
+// After an accepted embedded step: m0 <- m_s / |m_s| (m_s holds the
+// higher-order solution, the last stage state).  The caller's array is only
+// written when the controller accepted.
+__global__ void __launch_bounds__(NT) k_finalize(const FieldArgs a) {
+    if (!a.st->accepted) return;
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    if (i >= a.ncell) return;
+    const float3 m = ld3(a.ms, a.ncell, i);
+    const float n2 = f3dot(m, m);
+    const float inv = n2 > 0.f ? rsqrtf(n2) : 0.f;
+    st3(const_cast<float*>(a.m0), a.ncell, i, f3scale(inv, m));
+}
+
+hipError_t launch_finalize(const FieldArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((a.ncell + NT - 1) / NT)), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+// Fixed-step update m0 <- normalise(m0 + dt sum b_j k_j) (classical RK4).
+__global__ void __launch_bounds__(NT) k_final_combine(const FieldArgs a) {
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    if (i >= a.ncell) return;
+    const float3 m = stage_state(a, i, (float)a.st->dt);
+    const float n2 = f3dot(m, m);
+    const float inv = n2 > 0.f ? rsqrtf(n2) : 0.f;
+    st3(const_cast<float*>(a.m0), a.ncell, i, f3scale(inv, m));
+}
+
+hipError_t launch_final_combine(const FieldArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_final_combine, dim3((unsigned)((a.ncell + NT - 1) / NT)), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+// Deterministic FP64 sum of the per-workgroup energy partials: every thread
+// sums a fixed strided subset in order, then a fixed-shape tree.
+__global__ void __launch_bounds__(256) k_reduce_energy(const double* __restrict__ partials, int nblocks,
+                                                       DevState* st, double cellvol) {
+    __shared__ double sh[4][256];
+    const int t = threadIdx.x;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = t; b < nblocks; b += 256)
+        for (int i = 0; i < 4; ++i) s[i] += partials[(long long)b * 4 + i];
+    for (int i = 0; i < 4; ++i) sh[i][t] = s[i];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int i = 0; i < 4; ++i) sh[i][t] += sh[i][t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        double tot = 0.0;
+        for (int i = 0; i < 4; ++i) {
+            st->red[i] = sh[i][0] * cellvol;
+            tot += st->red[i];
+        }
+        st->red[4] = tot;
+    }
+}
+
+hipError_t launch_reduce_energy(const double* partials, int nblocks, DevState* st, double cellvol,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_energy, dim3(1), dim3(256), 0, s, partials, nblocks, st, cellvol);
+    return hipGetLastError();
+}
+
+// Per-face exchange coefficients as the field kernels gather them.
+__global__ void __launch_bounds__(NT) k_exchange_dump(const FieldArgs a, float* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    if (i >= a.ncell) return;
+    const int x = (int)(i % a.nx);
+    const long long rr = i / a.nx;
+    const int y = (int)(rr % a.ny), z = (int)(rr / a.ny);
+    const int r = a.region[i];
+    const long long sxy = (long long)a.nx * a.ny;
+    const bool has[6] = {x > 0, x < a.nx - 1, y > 0, y < a.ny - 1, z > 0, z < a.nz - 1};
+    const long long off[6] = {-1, 1, -(long long)a.nx, (long long)a.nx, -sxy, sxy};
+    const float id2[6] = {a.idx2, a.idx2, a.idy2, a.idy2, a.idz2, a.idz2};
+    for (int f = 0; f < 6; ++f) {
+        float c = 0.f;
+        if (has[f]) c = a.ptab[pair_index(r, a.region[i + off[f]])] * id2[f];
+        out[f * a.ncell + i] = c;
+    }
+}
+
+hipError_t launch_exchange_dump(const FieldArgs& a, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_exchange_dump, dim3((unsigned)((a.ncell + NT - 1) / NT)), dim3(NT), 0, s, a, out);
+    return hipGetLastError();
+}
+
+}  // namespace mm

@@ -1,0 +1,787 @@
+// mm_api.cpp -- the C ABI of include/mm.h: context, validation, solver
+// drivers (Runge-Kutta stage sequencing, device-side step control, relax).
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "../../include/mm.h"
+#include "mm_internal.h"
+
+using namespace mm;
+
+namespace {
+
+struct TimingClass {
+    bool enabled = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+};
+
+// Butcher tableaux (section "Dynamics"): row s holds a_{s+1, j}, j <= s.
+struct Tableau {
+    int stages;        // derivatives per step including the first-same-as-last one
+    int order_low;     // order of the embedded (error) solution
+    double a[7][6];
+    double e[7];       // b_j - b*_j
+};
+
+const Tableau DP45 = {
+    7, 4,
+    {{0, 0, 0, 0, 0, 0},
+     {1.0 / 5, 0, 0, 0, 0, 0},
+     {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+     {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+     {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+     {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+     {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}},
+    {35.0 / 384 - 5179.0 / 57600, 0, 500.0 / 1113 - 7571.0 / 16695, 125.0 / 192 - 393.0 / 640,
+     -2187.0 / 6784 + 92097.0 / 339200, 11.0 / 84 - 187.0 / 2100, -1.0 / 40}};
+
+const Tableau BS23 = {
+    4, 2,
+    {{0, 0, 0, 0, 0, 0},
+     {1.0 / 2, 0, 0, 0, 0, 0},
+     {0, 3.0 / 4, 0, 0, 0, 0},
+     {2.0 / 9, 1.0 / 3, 4.0 / 9, 0, 0, 0},
+     {0, 0, 0, 0, 0, 0},
+     {0, 0, 0, 0, 0, 0},
+     {0, 0, 0, 0, 0, 0}},
+    {2.0 / 9 - 7.0 / 24, 1.0 / 3 - 1.0 / 4, 4.0 / 9 - 1.0 / 3, -1.0 / 8, 0, 0, 0}};
+
+int pad_len(int n) {
+    if (n == 1) return 1;
+    int p = 1;
+    while (p < 2 * n - 1) p <<= 1;
+    return p;
+}
+
+int map_err(hipError_t e) {
+    if (e == hipSuccess) return MM_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return MM_ENOMEM;
+    return MM_EDEVICE;
+}
+
+#define MM_TRY(expr)                      \
+    do {                                  \
+        const hipError_t e_ = (expr);     \
+        if (e_ != hipSuccess) return map_err(e_); \
+    } while (0)
+
+#define MM_CHECK(expr)                    \
+    do {                                  \
+        const int s_ = (expr);            \
+        if (s_ != MM_OK) return s_;       \
+    } while (0)
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+int validate_params(const mm_params* p) {
+    if (!p) return MM_EINVAL;
+    for (int i = 0; i < NREG; ++i) {
+        const double v[5] = {p->msat[i], p->aex[i], p->alpha[i], p->ku1[i], p->ku2[i]};
+        for (double x : v)
+            if (!isfinite(x)) return MM_EINVAL;
+        if (p->msat[i] < 0.0 || p->alpha[i] < 0.0 || p->aex[i] < 0.0) return MM_EINVAL;
+        for (int k = 0; k < 3; ++k)
+            if (!isfinite(p->anis_u[i][k]) || !isfinite(p->bext[i][k])) return MM_EINVAL;
+    }
+    for (int i = 0; i < MM_NPAIRS; ++i)
+        if (!isfinite(p->exch_scale[i])) return MM_EINVAL;
+    if (!isfinite(p->gamma_ll) || p->gamma_ll < 0.0) return MM_EINVAL;
+    return MM_OK;
+}
+
+}  // namespace
+
+struct mm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int nx = 0, ny = 0, nz = 0, nrows = 0;
+    double dx = 0, dy = 0, dz = 0;
+    int px = 1, py = 1, pz = 1, kx = 1, ncomp = 4;
+    long long ncell = 0, rowstride = 0, zstride = 0, spec_elems = 0, khat_elems = 0;
+    int pt = 1, twshift = 0;
+    bool demag_on = true, khat_ready = false;
+    uint8_t* region = nullptr;
+    double* params64 = nullptr;
+    RegionLut* lut = nullptr;
+    float* ptab = nullptr;
+    cf* tw = nullptr;
+    cf* spec = nullptr;
+    float* khat = nullptr;
+    float* kbuf = nullptr;
+    float* ms = nullptr;
+    DevState* st = nullptr;
+    double* partials = nullptr;
+    DevState* hst = nullptr;  // pinned host mirror of st
+    long long dev_bytes = 0;
+    bool fsal_valid = false;
+    const float* fsal_m = nullptr;
+    int fsal_precess = -1;
+    int fsal_solver = 0;
+    TimingClass timing[3];
+};
+
+namespace {
+
+hipError_t dalloc(mm_ctx* c, void** p, size_t bytes) {
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) c->dev_bytes += (long long)bytes;
+    return e;
+}
+
+void free_all(mm_ctx* c) {
+    void* ptrs[] = {c->region, c->params64, c->lut, c->ptab, c->tw, c->spec,
+                    c->khat,   c->kbuf,     c->ms,  c->st,   c->partials};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    if (c->hst) hipHostFree(c->hst);
+    for (auto& t : c->timing)
+        for (auto& pr : t.ev) {
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
+}
+
+FieldArgs base_args(mm_ctx* c, const float* m0) {
+    FieldArgs a;
+    memset(&a, 0, sizeof(a));
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.nz = c->nz;
+    a.nrows = c->nrows;
+    a.ncell = c->ncell;
+    a.m0 = m0;
+    a.ms = c->ms;
+    a.region = c->region;
+    a.lut = c->lut;
+    a.ptab = c->ptab;
+    a.idx2 = (float)(1.0 / (c->dx * c->dx));
+    a.idy2 = (float)(1.0 / (c->dy * c->dy));
+    a.idz2 = (float)(1.0 / (c->dz * c->dz));
+    a.kbuf = c->kbuf;
+    a.st = c->st;
+    a.sd.out_k = -1;
+    a.spec = c->spec;
+    a.rowstride = c->rowstride;
+    a.zstride = c->zstride;
+    a.tw = c->tw;
+    a.twshift = c->twshift;
+    a.partials = c->partials;
+    a.cellvol = (float)(c->dx * c->dy * c->dz);
+    return a;
+}
+
+struct Timed {
+    mm_ctx* c;
+    int which;
+    hipEvent_t e1 = nullptr, e2 = nullptr;
+    Timed(mm_ctx* c_, int w) : c(c_), which(w) {
+        if (c->timing[which].enabled) {
+            hipEventCreate(&e1);
+            hipEventCreate(&e2);
+            hipEventRecord(e1, c->stream);
+        }
+    }
+    ~Timed() {
+        if (e1) {
+            hipEventRecord(e2, c->stream);
+            c->timing[which].ev.emplace_back(e1, e2);
+        }
+    }
+};
+
+// One field evaluation (section "Landau-Lifshitz torque": B_eff and torque).
+int run_field(mm_ctx* c, FieldArgs& a, int* nblocks_out) {
+    hipStream_t s = c->stream;
+    if (c->demag_on) {
+        if (!c->khat_ready) return MM_ESTATE;
+        a.flags |= EPI_HAS_DEMAG;
+        {
+            Timed t(c, 0);
+            MM_TRY(launch_xfwd(c->px, a, s));
+        }
+        ColArgs ca;
+        memset(&ca, 0, sizeof(ca));
+        ca.spec = c->spec;
+        ca.ncolx = c->kx;
+        ca.tw = c->tw;
+        ca.twshift = c->twshift;
+        ca.st = c->st;
+        ca.check_done = (a.flags & EPI_CHECK_DONE) ? 1 : 0;
+        ca.khat = c->khat;
+        {
+            Timed t(c, 1);
+            if (c->pz > 1) {
+                if (c->py > 1) {
+                    ca.n_in = c->ny;
+                    ca.n_out = c->py;
+                    ca.stride = c->rowstride;
+                    ca.nouter = c->nz;
+                    ca.outer_stride = c->zstride;
+                    ca.pa = 1;
+                    MM_TRY(launch_col(c->py, COL_FWD, ca, 6, s));
+                }
+                ca.n_in = c->nz;
+                ca.n_out = c->nz;
+                ca.stride = c->zstride;
+                ca.nouter = c->py;
+                ca.outer_stride = c->rowstride;
+                ca.pa = c->py;
+                ca.khq = c->pz / 2 + 1;
+                MM_TRY(launch_col(c->pz, COL_CONV, ca, 6, s));
+                if (c->py > 1) {
+                    ca.n_in = c->py;
+                    ca.n_out = c->ny;
+                    ca.stride = c->rowstride;
+                    ca.nouter = c->nz;
+                    ca.outer_stride = c->zstride;
+                    ca.pa = 1;
+                    MM_TRY(launch_col(c->py, COL_INV, ca, 6, s));
+                }
+            } else {
+                ca.n_in = c->ny;
+                ca.n_out = c->ny;
+                ca.stride = c->rowstride;
+                ca.nouter = 1;
+                ca.outer_stride = 0;
+                ca.pa = 1;
+                ca.khq = c->py / 2 + 1;
+                MM_TRY(launch_col(c->py, COL_CONV, ca, 4, s));
+            }
+        }
+        {
+            Timed t(c, 2);
+            MM_TRY(launch_xinv(c->px, a, s, nblocks_out));
+        }
+    } else {
+        if (a.sd.nk > 0) MM_TRY(launch_combine(a, s));
+        MM_TRY(launch_local(a, s, nblocks_out));
+    }
+    return MM_OK;
+}
+
+int sync_state(mm_ctx* c) {
+    MM_TRY(hipMemcpyAsync(c->hst, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+    MM_TRY(hipStreamSynchronize(c->stream));
+    return MM_OK;
+}
+
+struct Opts {
+    double max_err, headroom, dt_min, dt_max;
+    int precess;
+};
+
+Opts get_opts(const mm_solver_opts* o) {
+    Opts r{1e-5, 0.8, 0.0, 0.0, 1};
+    if (o) {
+        if (o->max_err > 0.0) r.max_err = o->max_err;
+        if (o->headroom > 0.0) r.headroom = o->headroom;
+        if (o->dt_min > 0.0) r.dt_min = o->dt_min;
+        if (o->dt_max > 0.0) r.dt_max = o->dt_max;
+        r.precess = o->precess ? 1 : 0;
+    }
+    return r;
+}
+
+// Torque of the committed state into logical derivative 0 (first stage).
+int eval_first(mm_ctx* c, const float* m, int precess) {
+    FieldArgs a = base_args(c, m);
+    a.sd.nk = 0;
+    a.sd.out_k = 0;
+    a.flags = EPI_TORQUE | (precess ? EPI_PRECESS : 0);
+    return run_field(c, a, nullptr);
+}
+
+// One attempt of an embedded pair: stages 2..S, controller, finalisation.
+int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done) {
+    const int S = tb.stages;
+    for (int s = 1; s < S; ++s) {
+        FieldArgs a = base_args(c, m);
+        StageDesc& sd = a.sd;
+        sd.nk = 0;
+        for (int j = 0; j < s; ++j)
+            if (tb.a[s][j] != 0.0) {
+                sd.kidx[sd.nk] = j;
+                sd.a[sd.nk] = (float)tb.a[s][j];
+                ++sd.nk;
+            }
+        sd.out_k = s;
+        a.flags = EPI_TORQUE | (precess ? EPI_PRECESS : 0) | (check_done ? EPI_CHECK_DONE : 0);
+        if (s == S - 1) {
+            sd.nerr = 0;
+            for (int j = 0; j < S; ++j)
+                if (tb.e[j] != 0.0) {
+                    sd.eidx[sd.nerr] = j;
+                    sd.e[sd.nerr] = (float)tb.e[j];
+                    ++sd.nerr;
+                }
+            a.flags |= EPI_ERR;
+        }
+        MM_CHECK(run_field(c, a, nullptr));
+    }
+    MM_TRY(launch_controller(c->st, S - 1, S - 1, check_done ? 1 : 0, c->stream));
+    FieldArgs f = base_args(c, m);
+    MM_TRY(launch_finalize(f, c->stream));
+    return MM_OK;
+}
+
+bool need_first(mm_ctx* c, const float* m, int precess, int solver) {
+    return !(c->fsal_valid && c->fsal_m == m && c->fsal_precess == precess && c->fsal_solver == solver);
+}
+
+int embedded_step(mm_ctx* c, float* m, const Tableau& tb, int solver, double* t, double* dt,
+                  const mm_solver_opts* o, int32_t* accepted, double* err) {
+    if (!c || !m || !t || !dt) return MM_EINVAL;
+    if (!(isfinite(*t) && finite_pos(*dt))) return MM_EINVAL;
+    const Opts op = get_opts(o);
+    const bool first = need_first(c, m, op.precess, solver);
+    MM_TRY(launch_set_state(c->st, *t, *dt, INFINITY, op.max_err, op.headroom, op.dt_min, op.dt_max,
+                            tb.order_low, 1, first ? 1 : 0, 0, c->stream));
+    if (first) {
+        c->fsal_valid = false;
+        MM_CHECK(eval_first(c, m, op.precess));
+    }
+    MM_CHECK(attempt(c, m, tb, op.precess, false));
+    MM_CHECK(sync_state(c));
+    c->fsal_valid = true;
+    c->fsal_m = m;
+    c->fsal_precess = op.precess;
+    c->fsal_solver = solver;
+    if (accepted) *accepted = c->hst->accepted;
+    if (err) *err = c->hst->err;
+    *t = c->hst->t;
+    *dt = c->hst->dt;
+    if (c->hst->status != 0) return c->hst->status;
+    return MM_OK;
+}
+
+int energy_pass(mm_ctx* c, const float* m, double* out5) {
+    FieldArgs a = base_args(c, m);
+    a.flags = EPI_ENERGY;
+    int nb = 0;
+    MM_CHECK(run_field(c, a, &nb));
+    MM_TRY(launch_reduce_energy(c->partials, nb, c->st, c->dx * c->dy * c->dz, c->stream));
+    MM_CHECK(sync_state(c));
+    for (int i = 0; i < 5; ++i) out5[i] = c->hst->red[i];
+    return MM_OK;
+}
+
+int maxtorque_pass(mm_ctx* c, const float* m, int precess, double* out) {
+    MM_TRY(launch_reset_accum(c->st, c->stream));
+    FieldArgs a = base_args(c, m);
+    a.flags = EPI_MAXTQ | (precess ? EPI_PRECESS : 0);
+    MM_CHECK(run_field(c, a, nullptr));
+    MM_CHECK(sync_state(c));
+    unsigned int bits = c->hst->tq_bits;
+    float f;
+    memcpy(&f, &bits, sizeof(f));
+    *out = (double)f;
+    return MM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mm_strerror(int status) {
+    switch (status) {
+        case MM_OK: return "ok";
+        case MM_EINVAL: return "invalid argument";
+        case MM_ENOMEM: return "device memory allocation failed";
+        case MM_EDEVICE: return "HIP runtime error";
+        case MM_EUNSUPPORTED: return "unsupported configuration (padded length > 4096 or PBC)";
+        case MM_ENONFINITE: return "non-finite error estimate";
+        case MM_ESTEP: return "time step fell below dt_min";
+        case MM_ENOTCONVERGED: return "relax did not reach the MaxErr floor within max_steps";
+        case MM_ESTATE: return "call order: demag kernel not initialised";
+        default: return "unknown status";
+    }
+}
+
+int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t* region_dev,
+              void* hip_stream) {
+    if (!out || !g || !p || !region_dev) return MM_EINVAL;
+    *out = nullptr;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return MM_EINVAL;
+    if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->dz)) return MM_EINVAL;
+    if (g->pbc[0] || g->pbc[1] || g->pbc[2]) return MM_EUNSUPPORTED;
+    if (g->nx > 2048 || g->ny > 2048 || g->nz > 2048) return MM_EUNSUPPORTED;
+    MM_CHECK(validate_params(p));
+    mm_ctx* c = new (std::nothrow) mm_ctx();
+    if (!c) return MM_ENOMEM;
+    c->stream = (hipStream_t)hip_stream;
+    hipGetDevice(&c->device);
+    c->nx = g->nx;
+    c->ny = g->ny;
+    c->nz = g->nz;
+    c->dx = g->dx;
+    c->dy = g->dy;
+    c->dz = g->dz;
+    c->nrows = g->ny * g->nz;
+    c->ncell = (long long)g->nx * g->ny * g->nz;
+    c->px = pad_len(g->nx);
+    c->py = pad_len(g->ny);
+    c->pz = pad_len(g->nz);
+    if (c->px > 4096 || c->py > 4096 || c->pz > 4096) {
+        delete c;
+        return MM_EUNSUPPORTED;
+    }
+    c->kx = c->px / 2 + 1;
+    c->ncomp = (c->pz > 1) ? 6 : 4;
+    c->rowstride = 3LL * c->kx;
+    const long long zrows = (c->pz > 1) ? c->py : c->ny;
+    c->zstride = zrows * c->rowstride;
+    c->spec_elems = c->zstride * c->nz;
+    c->khat_elems = (long long)c->kx * (c->py / 2 + 1) * (c->pz / 2 + 1) * c->ncomp;
+    c->pt = c->px;
+    if (c->py > c->pt) c->pt = c->py;
+    if (c->pz > c->pt) c->pt = c->pz;
+    c->twshift = ilog2(c->pt);
+    const int maxblk_x = xinv_blocks(c->px, c->nrows);
+    const long long maxblk_l = (c->ncell + NT - 1) / NT;
+    const long long maxblk = maxblk_x > maxblk_l ? maxblk_x : maxblk_l;
+
+    int st = MM_OK;
+    auto A = [&](void** ptr, size_t bytes) {
+        if (st != MM_OK) return;
+        const hipError_t e = dalloc(c, ptr, bytes);
+        if (e != hipSuccess) st = map_err(e);
+    };
+    A((void**)&c->region, (size_t)c->ncell);
+    A((void**)&c->params64, sizeof(mm_params));
+    A((void**)&c->lut, NREG * sizeof(RegionLut));
+    A((void**)&c->ptab, NPAIR * sizeof(float));
+    A((void**)&c->tw, (size_t)c->pt * sizeof(cf));
+    A((void**)&c->spec, (size_t)c->spec_elems * sizeof(cf));
+    A((void**)&c->khat, (size_t)c->khat_elems * sizeof(float));
+    A((void**)&c->kbuf, (size_t)MAXK * 3 * c->ncell * sizeof(float));
+    A((void**)&c->ms, (size_t)3 * c->ncell * sizeof(float));
+    A((void**)&c->st, sizeof(DevState));
+    A((void**)&c->partials, (size_t)maxblk * 4 * sizeof(double));
+    if (st == MM_OK && hipHostMalloc((void**)&c->hst, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+        st = MM_ENOMEM;
+    if (st == MM_OK) {
+        hipError_t e = hipMemcpyAsync(c->region, region_dev, (size_t)c->ncell, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->params64, p, sizeof(mm_params), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = launch_prepare_tables(c->params64, c->lut, c->ptab, c->stream);
+        if (e == hipSuccess) e = launch_twiddles(c->tw, c->pt, c->stream);
+        if (e == hipSuccess)
+            e = launch_set_state(c->st, 0.0, 1e-14, INFINITY, 1e-5, 0.8, 0.0, 0.0, 4, 1, 1, 0, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        st = map_err(e);
+    }
+    if (st != MM_OK) {
+        free_all(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return MM_OK;
+}
+
+int mm_demag_kernel_init(mm_ctx* c) {
+    if (!c) return MM_EINVAL;
+    double* oct = nullptr;
+    double2* work = nullptr;
+    hipError_t e = hipMalloc((void**)&oct, (size_t)6 * c->ncell * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMalloc((void**)&work, (size_t)c->px * c->py * c->pz * sizeof(double2));
+    if (e == hipSuccess) e = demag_tensor_octant(c->nx, c->ny, c->nz, c->dx, c->dy, c->dz, oct, c->stream);
+    if (e == hipSuccess)
+        e = demag_kernel_spectrum(c->nx, c->ny, c->nz, c->px, c->py, c->pz, oct, work, c->khat, c->ncomp,
+                                  c->kx, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (oct) hipFree(oct);
+    if (work) hipFree(work);
+    if (e != hipSuccess) return map_err(e);
+    c->khat_ready = true;
+    c->fsal_valid = false;
+    return MM_OK;
+}
+
+int mm_set_params(mm_ctx* c, const mm_params* p) {
+    if (!c) return MM_EINVAL;
+    MM_CHECK(validate_params(p));
+    MM_TRY(hipMemcpyAsync(c->params64, p, sizeof(mm_params), hipMemcpyHostToDevice, c->stream));
+    MM_TRY(launch_prepare_tables(c->params64, c->lut, c->ptab, c->stream));
+    MM_TRY(hipStreamSynchronize(c->stream));
+    c->fsal_valid = false;
+    return MM_OK;
+}
+
+int mm_set_demag(mm_ctx* c, int32_t enable) {
+    if (!c) return MM_EINVAL;
+    c->demag_on = enable != 0;
+    c->fsal_valid = false;
+    return MM_OK;
+}
+
+int mm_beff(mm_ctx* c, const float* m_dev, float* beff_dev, float* bdemag_dev) {
+    if (!c || !m_dev || !beff_dev) return MM_EINVAL;
+    FieldArgs a = base_args(c, m_dev);
+    a.beff = beff_dev;
+    a.bdemag = bdemag_dev;
+    a.flags = EPI_BEFF | (bdemag_dev ? EPI_BDEMAG : 0);
+    return run_field(c, a, nullptr);
+}
+
+int mm_llg_torque(mm_ctx* c, const float* m_dev, const float* beff_dev, float* tau_dev, int32_t precess) {
+    if (!c || !m_dev || !beff_dev || !tau_dev) return MM_EINVAL;
+    FieldArgs a = base_args(c, m_dev);
+    return map_err(launch_llg(a, beff_dev, tau_dev, precess ? 1 : 0, c->stream));
+}
+
+int mm_torque(mm_ctx* c, const float* m_dev, float* tau_dev, int32_t precess) {
+    if (!c || !m_dev || !tau_dev) return MM_EINVAL;
+    FieldArgs a = base_args(c, m_dev);
+    a.tau = tau_dev;
+    a.flags = EPI_TORQUE | (precess ? EPI_PRECESS : 0);
+    return run_field(c, a, nullptr);
+}
+
+int mm_rk4_step(mm_ctx* c, float* m_dev, double dt, int32_t precess) {
+    if (!c || !m_dev || !finite_pos(dt)) return MM_EINVAL;
+    c->fsal_valid = false;
+    MM_TRY(launch_set_state(c->st, 0.0, dt, INFINITY, 1e-5, 0.8, 0.0, 0.0, 4, 0, 1, 0, c->stream));
+    const int pf = precess ? EPI_PRECESS : 0;
+    const float half = 0.5f;
+    for (int s = 0; s < 4; ++s) {
+        FieldArgs a = base_args(c, m_dev);
+        a.sd.nk = s == 0 ? 0 : 1;
+        a.sd.kidx[0] = s - 1;
+        a.sd.a[0] = (s == 3) ? 1.0f : half;
+        a.sd.out_k = s;
+        a.flags = EPI_TORQUE | pf;
+        MM_CHECK(run_field(c, a, nullptr));
+    }
+    FieldArgs f = base_args(c, m_dev);
+    f.sd.nk = 4;
+    const float b[4] = {1.0f / 6, 1.0f / 3, 1.0f / 3, 1.0f / 6};
+    for (int j = 0; j < 4; ++j) {
+        f.sd.kidx[j] = j;
+        f.sd.a[j] = b[j];
+    }
+    MM_TRY(launch_final_combine(f, c->stream));
+    return MM_OK;
+}
+
+int mm_rk45_step(mm_ctx* c, float* m_dev, double* t, double* dt, const mm_solver_opts* o, int32_t* accepted,
+                 double* err) {
+    return embedded_step(c, m_dev, DP45, 45, t, dt, o, accepted, err);
+}
+
+int mm_rk23_step(mm_ctx* c, float* m_dev, double* t, double* dt, const mm_solver_opts* o, int32_t* accepted,
+                 double* err) {
+    return embedded_step(c, m_dev, BS23, 23, t, dt, o, accepted, err);
+}
+
+int mm_run(mm_ctx* c, float* m_dev, int32_t solver, double t_end, int64_t max_attempts, double* t, double* dt,
+           const mm_solver_opts* o, mm_run_stats* stats) {
+    if (!c || !m_dev || !t || !dt || max_attempts < 0) return MM_EINVAL;
+    if (solver != 45 && solver != 23) return MM_EINVAL;
+    if (!(isfinite(*t) && finite_pos(*dt)) || isnan(t_end)) return MM_EINVAL;
+    const Tableau& tb = solver == 45 ? DP45 : BS23;
+    const Opts op = get_opts(o);
+    double dt0 = *dt;
+    if (isfinite(t_end) && *t + dt0 > t_end) dt0 = t_end - *t;
+    if (!(dt0 > 0.0)) {  // nothing to do
+        if (stats) memset(stats, 0, sizeof(*stats));
+        return MM_OK;
+    }
+    const bool first = need_first(c, m_dev, op.precess, solver);
+    MM_TRY(launch_set_state(c->st, *t, dt0, t_end, op.max_err, op.headroom, op.dt_min, op.dt_max, tb.order_low,
+                            1, first ? 1 : 0, 0, c->stream));
+    long long extra = 0;
+    if (first) {
+        c->fsal_valid = false;
+        MM_CHECK(eval_first(c, m_dev, op.precess));
+        extra = 1;
+    }
+    long long per = (long long)(3e7 / (double)c->ncell);
+    if (per < 4) per = 4;
+    if (per > 64) per = 64;
+    long long done_attempts = 0;
+    while (done_attempts < max_attempts) {
+        long long nb = max_attempts - done_attempts;
+        if (nb > per) nb = per;
+        for (long long i = 0; i < nb; ++i) MM_CHECK(attempt(c, m_dev, tb, op.precess, true));
+        done_attempts += nb;
+        MM_CHECK(sync_state(c));
+        if (c->hst->done) break;
+    }
+    c->fsal_valid = true;
+    c->fsal_m = m_dev;
+    c->fsal_precess = op.precess;
+    c->fsal_solver = solver;
+    *t = c->hst->t;
+    *dt = c->hst->dt;
+    if (stats) {
+        stats->steps = c->hst->steps;
+        stats->rejects = c->hst->rejects;
+        stats->evals = c->hst->evals + extra;
+        stats->t = c->hst->t;
+        stats->dt = c->hst->dt;
+        stats->err = c->hst->err;
+    }
+    return c->hst->status != 0 ? c->hst->status : MM_OK;
+}
+
+int mm_energy(mm_ctx* c, const float* m_dev, double* e_terms5) {
+    if (!c || !m_dev || !e_terms5) return MM_EINVAL;
+    return energy_pass(c, m_dev, e_terms5);
+}
+
+int mm_max_torque(mm_ctx* c, const float* m_dev, int32_t precess, double* out) {
+    if (!c || !m_dev || !out) return MM_EINVAL;
+    return maxtorque_pass(c, m_dev, precess ? 1 : 0, out);
+}
+
+int mm_relax(mm_ctx* c, float* m_dev, const mm_solver_opts* o, double min_max_err, int64_t max_steps,
+             double* energy_out, double* max_torque_out, int64_t* steps_out) {
+    if (!c || !m_dev || max_steps < 0) return MM_EINVAL;
+    Opts op = get_opts(o);
+    op.precess = 0;
+    if (!(min_max_err > 0.0)) min_max_err = 1e-9;
+    const Tableau& tb = BS23;
+    double max_err = op.max_err;
+    MM_TRY(launch_set_state(c->st, 0.0, 1e-14, INFINITY, max_err, op.headroom, op.dt_min, op.dt_max, tb.order_low,
+                            1, 1, 0, c->stream));
+    c->fsal_valid = false;
+    MM_CHECK(eval_first(c, m_dev, 0));
+    c->fsal_valid = true;
+    c->fsal_m = m_dev;
+    c->fsal_precess = 0;
+    c->fsal_solver = 23;
+    MM_CHECK(sync_state(c));
+    long long steps = 0, attempts = 0;
+    double t = 0.0, dt = 1e-14;
+    bool hit_cap = false;
+    // advance by `block` accepted steps (device-controlled), at most max_steps attempts overall
+    auto advance = [&](int block) -> int {
+        MM_TRY(launch_set_state(c->st, t, dt, INFINITY, max_err, op.headroom, op.dt_min, op.dt_max, tb.order_low,
+                                0, 0, steps + block, c->stream));
+        while (!hit_cap) {
+            long long nb = 4;
+            if (attempts + nb > max_steps) nb = max_steps - attempts;
+            if (nb <= 0) {
+                hit_cap = true;
+                break;
+            }
+            for (long long i = 0; i < nb; ++i) MM_CHECK(attempt(c, m_dev, tb, 0, true));
+            MM_CHECK(sync_state(c));
+            attempts = c->hst->steps + c->hst->rejects;
+            steps = c->hst->steps;
+            t = c->hst->t;
+            dt = c->hst->dt;
+            if (c->hst->status != 0) return c->hst->status;
+            if (c->hst->done) break;
+        }
+        return MM_OK;
+    };
+    double e5[5];
+    MM_CHECK(energy_pass(c, m_dev, e5));
+    double e0 = e5[4];
+    while (!hit_cap) {
+        MM_CHECK(advance(3));
+        MM_CHECK(energy_pass(c, m_dev, e5));
+        if (e5[4] >= e0) break;
+        e0 = e5[4];
+    }
+    double t0 = 0.0;
+    MM_CHECK(maxtorque_pass(c, m_dev, 0, &t0));
+    while (max_err >= min_max_err && !hit_cap) {
+        while (!hit_cap) {
+            MM_CHECK(advance(3));
+            double t1 = 0.0;
+            MM_CHECK(maxtorque_pass(c, m_dev, 0, &t1));
+            if (t1 >= t0) break;
+            t0 = t1;
+        }
+        max_err *= 0.5;
+    }
+    MM_CHECK(energy_pass(c, m_dev, e5));
+    double tq = 0.0;
+    MM_CHECK(maxtorque_pass(c, m_dev, 0, &tq));
+    if (energy_out) *energy_out = e5[4];
+    if (max_torque_out) *max_torque_out = tq;
+    if (steps_out) *steps_out = steps;
+    return hit_cap ? MM_ENOTCONVERGED : MM_OK;
+}
+
+int mm_solver_reset(mm_ctx* c) {
+    if (!c) return MM_EINVAL;
+    c->fsal_valid = false;
+    return MM_OK;
+}
+
+int mm_get_info(mm_ctx* c, mm_info* info) {
+    if (!c || !info) return MM_EINVAL;
+    memset(info, 0, sizeof(*info));
+    info->px = c->px;
+    info->py = c->py;
+    info->pz = c->pz;
+    info->kx = c->kx;
+    info->ncomp = c->ncomp;
+    info->ncell = c->ncell;
+    info->khat_elems = c->khat_elems;
+    info->device_bytes = c->dev_bytes;
+    return MM_OK;
+}
+
+int mm_demag_tensor_dump(mm_ctx* c, double* out_dev) {
+    if (!c || !out_dev) return MM_EINVAL;
+    return map_err(demag_tensor_octant(c->nx, c->ny, c->nz, c->dx, c->dy, c->dz, out_dev, c->stream));
+}
+
+int mm_demag_kernel_dump(mm_ctx* c, float* out_dev) {
+    if (!c || !out_dev) return MM_EINVAL;
+    if (!c->khat_ready) return MM_ESTATE;
+    MM_TRY(hipMemcpyAsync(out_dev, c->khat, (size_t)c->khat_elems * sizeof(float), hipMemcpyDeviceToDevice,
+                          c->stream));
+    return MM_OK;
+}
+
+int mm_exchange_dump(mm_ctx* c, float* out_dev) {
+    if (!c || !out_dev) return MM_EINVAL;
+    FieldArgs a = base_args(c, nullptr);
+    return map_err(launch_exchange_dump(a, out_dev, c->stream));
+}
+
+int mm_timing_enable(mm_ctx* c, int32_t which, int32_t enable) {
+    if (!c || which < 0 || which > 2) return MM_EINVAL;
+    TimingClass& t = c->timing[which];
+    MM_TRY(hipStreamSynchronize(c->stream));
+    for (auto& pr : t.ev) {
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    t.ev.clear();
+    t.enabled = enable != 0;
+    return MM_OK;
+}
+
+int mm_timing_read(mm_ctx* c, int32_t which, int64_t* launches, double* total_ms) {
+    if (!c || which < 0 || which > 2 || !launches || !total_ms) return MM_EINVAL;
+    MM_TRY(hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (auto& pr : c->timing[which].ev) {
+        float ms = 0.f;
+        MM_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+        tot += ms;
+    }
+    *launches = (int64_t)c->timing[which].ev.size();
+    *total_ms = tot;
+    return MM_OK;
+}
+
+void mm_destroy(mm_ctx* c) {
+    if (!c) return;
+    hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// mm_internal.h -- device-side structures and launch interfaces of libmm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_core.h"
+
+namespace mm {
+
+constexpr int NREG = 256;
+constexpr int NPAIR = NREG * (NREG + 1) / 2;
+constexpr int NT = 256;            // threads per workgroup of every field kernel
+constexpr int MAXK = 7;            // stage-derivative buffers (Dormand-Prince needs 7)
+constexpr double MU0 = 4.0e-7 * 3.14159265358979323846;
+constexpr double GAMMA_DEFAULT = 1.7595e11;
+
+// Per-region FP32 table derived on the device from the FP64 parameters.
+struct RegionLut {
+    float4 a;  // msat, 2 Ku1/Msat, 4 Ku2/Msat, alpha
+    float4 b;  // anisotropy axis u (x, y, z), -gamma/(1+alpha^2)
+    float4 c;  // B_ext (x, y, z), 0
+};
+
+// Solver state that lives on the device so steps need no host round trip.
+struct DevState {
+    double t, dt, t_end;
+    double max_err, headroom, dt_min, dt_max;
+    double err;                 // error estimate of the last attempt
+    unsigned int err_bits;      // max over cells of |sum e_j k_j| (float bits, atomicMax)
+    unsigned int tq_bits;       // max over cells of |tau| (float bits, atomicMax)
+    int perm[8];                // logical stage derivative -> physical k buffer
+    int accepted, done, status, order_low;
+    long long steps, rejects, evals;
+    long long target_steps;     // > 0: the run is done once steps reaches it
+    double red[8];              // results of FP64 reductions (energies)
+};
+
+// One torque evaluation inside a Runge-Kutta step.
+struct StageDesc {
+    int nk;          // stage state m_s = m0 + dt sum_j a[j] k[kidx[j]]; nk = 0: m_s = m0
+    int kidx[6];
+    float a[6];
+    int out_k;       // logical index of the derivative written, -1 = none
+    int nerr;        // error norm |sum_j e[j] k[eidx[j]]| accumulated when > 0
+    int eidx[7];
+    float e[7];
+};
+
+enum EpiFlags {
+    EPI_TORQUE = 1,      // compute the torque (to k[out_k] or tau)
+    EPI_BEFF = 2,        // write B_eff
+    EPI_BDEMAG = 4,      // write B_demag
+    EPI_ERR = 8,         // accumulate the embedded error norm
+    EPI_MAXTQ = 16,      // accumulate max |tau|
+    EPI_ENERGY = 32,     // per-workgroup FP64 energy partial sums
+    EPI_PRECESS = 64,    // keep the m x B term of the torque
+    EPI_HAS_DEMAG = 128, // the pass carries a demag field (else B_demag = 0)
+    EPI_CHECK_DONE = 256 // device-controlled run: skip the work once the run is done
+};
+
+struct FieldArgs {
+    int nx, ny, nz, nrows;        // nrows = ny * nz
+    long long ncell;
+    const float* m0;              // committed state (or the caller's m)
+    float* ms;                    // stage state (written by the first pass when sd.nk > 0)
+    const uint8_t* region;
+    const RegionLut* lut;
+    const float* ptab;            // exchange pair coefficients, packed lower triangle
+    float idx2, idy2, idz2;       // 1/dx^2, 1/dy^2, 1/dz^2
+    float* kbuf;                  // [MAXK][3][ncell]
+    DevState* st;
+    StageDesc sd;
+    cf* spec;                     // interleaved spectrum, 3 complex per (row, kx)
+    long long rowstride, zstride; // in complex elements
+    const cf* tw;                 // exp(-2 pi i m / PT)
+    int twshift;                  // log2 PT
+    float* beff;
+    float* bdemag;
+    float* tau;                   // explicit torque output when sd.out_k < 0
+    double* partials;             // [blocks][4] energy partial sums
+    float cellvol;
+    int flags;
+};
+
+struct ColArgs {
+    cf* spec;
+    int n_in, n_out;              // non-zero input length, kept output length
+    long long stride;             // complex elements between consecutive positions
+    int ncolx;                    // spectral columns kx
+    long long outer_stride;       // between outer columns (z slab or ky row)
+    int nouter;
+    int pa;                       // padded length of the outer axis (1 in 2D)
+    const float* khat;            // conv only
+    int khq;                      // folded conv-axis length p/2 + 1
+    const cf* tw;
+    int twshift;
+    const DevState* st;
+    int check_done;
+};
+
+// ---- launchers (kernels_fft.hip) -------------------------------------------
+hipError_t launch_xfwd(int px, const FieldArgs& a, hipStream_t s);
+hipError_t launch_xinv(int px, const FieldArgs& a, hipStream_t s, int* nblocks_out);
+hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t s);
+int xinv_blocks(int px, int nrows);
+enum ColMode { COL_FWD = 0, COL_INV = 1, COL_CONV = 2 };
+
+// ---- launchers (kernels_local.hip) -----------------------------------------
+hipError_t launch_prepare_tables(const double* params64, RegionLut* lut, float* ptab,
+                                 hipStream_t s);
+hipError_t launch_twiddles(cf* tw, int pt, hipStream_t s);
+hipError_t launch_combine(const FieldArgs& a, hipStream_t s);
+hipError_t launch_local(const FieldArgs& a, hipStream_t s, int* nblocks_out);
+hipError_t launch_llg(const FieldArgs& a, const float* beff, float* tau, int precess,
+                      hipStream_t s);
+hipError_t launch_set_state(DevState* st, double t, double dt, double t_end, double max_err,
+                            double headroom, double dt_min, double dt_max, int order_low,
+                            int reset_counters, int init_perm, long long target_steps,
+                            hipStream_t s);
+hipError_t launch_reset_accum(DevState* st, hipStream_t s);
+hipError_t launch_controller(DevState* st, int last_k, int evals, int check_done, hipStream_t s);
+hipError_t launch_finalize(const FieldArgs& a, hipStream_t s);
+hipError_t launch_final_combine(const FieldArgs& a, hipStream_t s);
+hipError_t launch_reduce_energy(const double* partials, int nblocks, DevState* st, double cellvol,
+                                hipStream_t s);
+hipError_t launch_exchange_dump(const FieldArgs& a, float* out, hipStream_t s);
+
+// ---- demag kernel construction (kernels_demag.hip) -------------------------
+hipError_t demag_tensor_octant(int nx, int ny, int nz, double dx, double dy, double dz,
+                               double* out, hipStream_t s);
+hipError_t demag_kernel_spectrum(int nx, int ny, int nz, int px, int py, int pz,
+                                 const double* octant, double2* work, float* khat, int ncomp,
+                                 int kx, hipStream_t s);
+
+}  // namespace mm

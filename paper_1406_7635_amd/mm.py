@@ -1,0 +1,294 @@
+"""Python binding of libmm (include/mm.h): argument marshalling only.
+
+Every computation happens in the HIP library; this module converts torch
+tensors and Python values into the C ABI's pointers and structs.  Importing it
+does not touch the GPU; creating a Context needs the built libmm.so (it raises
+if the library is missing -- there is no fallback path).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmm.so")
+NREG = 256
+NPAIR = NREG * (NREG + 1) // 2
+
+c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+STATUS = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EDEVICE", -4: "MM_EUNSUPPORTED",
+          -5: "MM_ENONFINITE", -6: "MM_ESTEP", -7: "MM_ENOTCONVERGED", -8: "MM_ESTATE"}
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32),
+                ("dx", c_double), ("dy", c_double), ("dz", c_double), ("pbc", c_int32 * 3)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("msat", c_double * NREG), ("aex", c_double * NREG), ("alpha", c_double * NREG),
+                ("ku1", c_double * NREG), ("ku2", c_double * NREG),
+                ("anis_u", (c_double * 3) * NREG), ("bext", (c_double * 3) * NREG),
+                ("exch_scale", c_double * NPAIR), ("gamma_ll", c_double)]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("max_err", c_double), ("headroom", c_double), ("dt_min", c_double),
+                ("dt_max", c_double), ("precess", c_int32), ("reserved", c_int32)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("steps", c_int64), ("rejects", c_int64), ("evals", c_int64),
+                ("t", c_double), ("dt", c_double), ("err", c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("px", c_int32), ("py", c_int32), ("pz", c_int32), ("kx", c_int32),
+                ("ncomp", c_int32), ("reserved", c_int32), ("ncell", c_int64),
+                ("khat_elems", c_int64), ("device_bytes", c_int64)]
+
+
+EXPORTS = {
+    "mm_create": (c_int32, [ctypes.POINTER(c_void_p), ctypes.POINTER(Grid), ctypes.POINTER(Params), c_void_p, c_void_p]),
+    "mm_demag_kernel_init": (c_int32, [c_void_p]),
+    "mm_set_params": (c_int32, [c_void_p, ctypes.POINTER(Params)]),
+    "mm_set_demag": (c_int32, [c_void_p, c_int32]),
+    "mm_beff": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mm_llg_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32]),
+    "mm_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
+    "mm_rk4_step": (c_int32, [c_void_p, c_void_p, c_double, c_int32]),
+    "mm_rk45_step": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
+                               ctypes.POINTER(SolverOpts), ctypes.POINTER(c_int32), ctypes.POINTER(c_double)]),
+    "mm_rk23_step": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
+                               ctypes.POINTER(SolverOpts), ctypes.POINTER(c_int32), ctypes.POINTER(c_double)]),
+    "mm_run": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_int64, ctypes.POINTER(c_double),
+                         ctypes.POINTER(c_double), ctypes.POINTER(SolverOpts), ctypes.POINTER(RunStats)]),
+    "mm_relax": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(SolverOpts), c_double, c_int64,
+                           ctypes.POINTER(c_double), ctypes.POINTER(c_double), ctypes.POINTER(c_int64)]),
+    "mm_energy": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_double)]),
+    "mm_max_torque": (c_int32, [c_void_p, c_void_p, c_int32, ctypes.POINTER(c_double)]),
+    "mm_solver_reset": (c_int32, [c_void_p]),
+    "mm_get_info": (c_int32, [c_void_p, ctypes.POINTER(Info)]),
+    "mm_demag_tensor_dump": (c_int32, [c_void_p, c_void_p]),
+    "mm_demag_kernel_dump": (c_int32, [c_void_p, c_void_p]),
+    "mm_exchange_dump": (c_int32, [c_void_p, c_void_p]),
+    "mm_timing_enable": (c_int32, [c_void_p, c_int32, c_int32]),
+    "mm_timing_read": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int64), ctypes.POINTER(c_double)]),
+    "mm_destroy": (None, [c_void_p]),
+    "mm_strerror": (ctypes.c_char_p, [c_int32]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmm.so is not built (python -m paper_1406_7635_amd.build)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class MMError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = load().mm_strerror(status).decode()
+        super().__init__("%s: %s (%s)" % (where, STATUS.get(status, status), msg))
+
+
+def _check(status, where):
+    if status != 0:
+        raise MMError(status, where)
+
+
+def params_struct(p):
+    """Fill the C struct from a dict of region tables (see synth.empty_params)."""
+    s = Params()
+    for key in ("msat", "aex", "alpha", "ku1", "ku2"):
+        np.ctypeslib.as_array(getattr(s, key))[:] = np.asarray(p[key], dtype=np.float64)
+    np.ctypeslib.as_array(s.anis_u)[:] = np.asarray(p["anis_u"], dtype=np.float64).reshape(NREG, 3)
+    np.ctypeslib.as_array(s.bext)[:] = np.asarray(p["bext"], dtype=np.float64).reshape(NREG, 3)
+    np.ctypeslib.as_array(s.exch_scale)[:] = np.asarray(p["exch_scale"], dtype=np.float64)
+    s.gamma_ll = float(p.get("gamma_ll", 0.0) or 0.0)
+    return s
+
+
+def solver_opts(max_err=1e-5, headroom=0.8, dt_min=0.0, dt_max=0.0, precess=True):
+    return SolverOpts(max_err, headroom, dt_min, dt_max, 1 if precess else 0, 0)
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr()) if t is not None else c_void_p(0)
+
+
+class Context:
+    """One simulation grid on the current CUDA (HIP) device.
+
+    grid (nx, ny, nz), cell (dx, dy, dz) in m, region uint8 [nz, ny, nx]
+    (numpy or tensor), params dict of region tables."""
+
+    def __init__(self, grid, cell, region, params, demag=True, stream=None):
+        import torch
+
+        self._torch = torch
+        lib = load()
+        self.grid = tuple(int(v) for v in grid)
+        self.cell = tuple(float(v) for v in cell)
+        nx, ny, nz = self.grid
+        self.shape = (3, nz, ny, nx)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        reg = torch.as_tensor(np.ascontiguousarray(region, dtype=np.uint8)
+                              if not isinstance(region, torch.Tensor) else region)
+        if tuple(reg.shape) != (nz, ny, nx):
+            raise ValueError("region must have shape (nz, ny, nx) = %s" % ((nz, ny, nx),))
+        self._region = reg.to(self.device, torch.uint8).contiguous()
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        g = Grid(nx, ny, nz, *self.cell, (c_int32 * 3)(0, 0, 0))
+        self._params = params_struct(params)
+        handle = c_void_p()
+        _check(lib.mm_create(ctypes.byref(handle), ctypes.byref(g), ctypes.byref(self._params),
+                             _ptr(self._region), c_void_p(self._stream.cuda_stream)), "mm_create")
+        self._h = handle
+        self.demag = bool(demag)
+        if self.demag:
+            _check(lib.mm_demag_kernel_init(self._h), "mm_demag_kernel_init")
+        else:
+            _check(lib.mm_set_demag(self._h, 0), "mm_set_demag")
+
+    # -- helpers -----------------------------------------------------------
+    def _vec(self, m, name="m"):
+        t = self._torch
+        if not isinstance(m, t.Tensor) or m.dtype != t.float32 or m.device != self.device \
+                or tuple(m.shape) != self.shape or not m.is_contiguous():
+            raise ValueError("%s must be a contiguous float32 %s tensor on %s" % (name, self.shape, self.device))
+        return m
+
+    def new_field(self):
+        return self._torch.empty(self.shape, dtype=self._torch.float32, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- API -----------------------------------------------------------------
+    def set_params(self, params):
+        self._params = params_struct(params)
+        _check(load().mm_set_params(self._h, ctypes.byref(self._params)), "mm_set_params")
+
+    def set_demag(self, enable):
+        if enable and not self.demag:
+            _check(load().mm_demag_kernel_init(self._h), "mm_demag_kernel_init")
+        self.demag = bool(enable)
+        _check(load().mm_set_demag(self._h, 1 if enable else 0), "mm_set_demag")
+
+    def beff(self, m, want_demag=False):
+        m = self._vec(m)
+        b = self.new_field()
+        bd = self.new_field() if want_demag else None
+        _check(load().mm_beff(self._h, _ptr(m), _ptr(b), _ptr(bd)), "mm_beff")
+        return (b, bd) if want_demag else b
+
+    def llg_torque(self, m, beff, precess=True):
+        tau = self.new_field()
+        _check(load().mm_llg_torque(self._h, _ptr(self._vec(m)), _ptr(self._vec(beff, "beff")), _ptr(tau),
+                                    1 if precess else 0), "mm_llg_torque")
+        return tau
+
+    def torque(self, m, precess=True):
+        tau = self.new_field()
+        _check(load().mm_torque(self._h, _ptr(self._vec(m)), _ptr(tau), 1 if precess else 0), "mm_torque")
+        return tau
+
+    def rk4_step(self, m, dt, precess=True):
+        _check(load().mm_rk4_step(self._h, _ptr(self._vec(m)), float(dt), 1 if precess else 0), "mm_rk4_step")
+
+    def rk45_step(self, m, t, dt, opts=None):
+        return self._embedded(load().mm_rk45_step, "mm_rk45_step", m, t, dt, opts)
+
+    def rk23_step(self, m, t, dt, opts=None):
+        return self._embedded(load().mm_rk23_step, "mm_rk23_step", m, t, dt, opts)
+
+    def _embedded(self, fn, name, m, t, dt, opts):
+        t_, dt_, acc, err = c_double(t), c_double(dt), c_int32(0), c_double(0.0)
+        o = opts if opts is not None else solver_opts()
+        _check(fn(self._h, _ptr(self._vec(m)), ctypes.byref(t_), ctypes.byref(dt_), ctypes.byref(o),
+                  ctypes.byref(acc), ctypes.byref(err)), name)
+        return bool(acc.value), t_.value, dt_.value, err.value
+
+    def run(self, m, t_end, t=0.0, dt=1e-14, solver=45, max_attempts=10 ** 9, opts=None):
+        """Device-controlled adaptive run; returns (t, dt, stats dict)."""
+        t_, dt_ = c_double(t), c_double(dt)
+        st = RunStats()
+        o = opts if opts is not None else solver_opts()
+        _check(load().mm_run(self._h, _ptr(self._vec(m)), int(solver), float(t_end), int(max_attempts),
+                             ctypes.byref(t_), ctypes.byref(dt_), ctypes.byref(o), ctypes.byref(st)), "mm_run")
+        return t_.value, dt_.value, {k: getattr(st, k) for k, _ in RunStats._fields_}
+
+    def relax(self, m, max_err=1e-5, min_max_err=1e-9, max_steps=100000):
+        e, tq, n = c_double(), c_double(), c_int64()
+        o = solver_opts(max_err=max_err, precess=False)
+        st = load().mm_relax(self._h, _ptr(self._vec(m)), ctypes.byref(o), float(min_max_err), int(max_steps),
+                             ctypes.byref(e), ctypes.byref(tq), ctypes.byref(n))
+        if st not in (0, -7):
+            _check(st, "mm_relax")
+        return {"energy": e.value, "max_torque": tq.value, "steps": n.value, "converged": st == 0}
+
+    def energy(self, m):
+        out = (c_double * 5)()
+        _check(load().mm_energy(self._h, _ptr(self._vec(m)), out), "mm_energy")
+        return dict(zip(("demag", "exch", "anis", "zeeman", "total"), list(out)))
+
+    def max_torque(self, m, precess=True):
+        v = c_double()
+        _check(load().mm_max_torque(self._h, _ptr(self._vec(m)), 1 if precess else 0, ctypes.byref(v)),
+               "mm_max_torque")
+        return v.value
+
+    def reset_solver(self):
+        _check(load().mm_solver_reset(self._h), "mm_solver_reset")
+
+    def info(self):
+        inf = Info()
+        _check(load().mm_get_info(self._h, ctypes.byref(inf)), "mm_get_info")
+        return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    def tensor_dump(self):
+        """FP64 real-space tensor octant [6, nz, ny, nx] as the GPU computes it."""
+        nx, ny, nz = self.grid
+        out = self._torch.empty((6, nz, ny, nx), dtype=self._torch.float64, device=self.device)
+        _check(load().mm_demag_tensor_dump(self._h, _ptr(out)), "mm_demag_tensor_dump")
+        return out
+
+    def kernel_dump(self):
+        out = self._torch.empty(self.info()["khat_elems"], dtype=self._torch.float32, device=self.device)
+        _check(load().mm_demag_kernel_dump(self._h, _ptr(out)), "mm_demag_kernel_dump")
+        return out
+
+    def exchange_dump(self):
+        nx, ny, nz = self.grid
+        out = self._torch.empty((6, nz, ny, nx), dtype=self._torch.float32, device=self.device)
+        _check(load().mm_exchange_dump(self._h, _ptr(out)), "mm_exchange_dump")
+        return out
+
+    def timing_enable(self, which, enable=True):
+        _check(load().mm_timing_enable(self._h, int(which), 1 if enable else 0), "mm_timing_enable")
+
+    def timing_read(self, which):
+        n, ms = c_int64(), c_double()
+        _check(load().mm_timing_read(self._h, int(which), ctypes.byref(n), ctypes.byref(ms)), "mm_timing_read")
+        return n.value, ms.value
