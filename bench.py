@@ -1,0 +1,161 @@
+"""Throughput benchmark: B_eff evaluations x cells per second on one MI355X.
+
+Workload: the 1024 x 1024 x 1 film of 2 nm cells (Msat 8e5 A/m, Aex 1.3e-11
+J/m, alpha 0.01, 10 mT along x) starting from a vortex with 1 % noise,
+advanced by Dormand-Prince RK45 steps with MaxErr 1e-5 under device-side step
+control.  One benchmark step = one RK45 attempt = 6 fused B_eff + torque
+evaluations (demag FFT convolution, exchange, anisotropy, Zeeman, torque,
+stage combine, error norm).  Following the paper's protocol (appendix
+"Benchmark: throughput"), throughput = cells x evaluations / wall time.
+
+Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Beff evals·cells/s: plain FP32 vs MFMA/surrogate at ≤1e-4 rel demag error"
+HBM_PEAK_GBS = 8000.0
+
+
+def column_pass_bytes(ctx):
+    """Algorithmic HBM bytes of one launch of the y convolution pass (2D):
+    read + write of the interleaved spectrum (3 complex64 per (y < ny, kx))
+    and one read of the FP32 kernel octant (4 components per (kx, ky <= py/2))."""
+    info = ctx.info()
+    nx, ny, nz = ctx.grid
+    spec = 3 * 8 * info["kx"] * ny * nz
+    khat = 4 * info["khat_elems"]
+    return 2 * spec + khat
+
+
+def xinv_pass_bytes(ctx):
+    """x-inverse + field/torque pass: read spectrum, m_s and region; write torque."""
+    info = ctx.info()
+    nx, ny, nz = ctx.grid
+    return 3 * 8 * info["kx"] * ny * nz + (12 + 1 + 12) * nx * ny * nz
+
+
+def xfwd_pass_bytes(ctx, avg_k_reads):
+    """x-forward pass: read m0, region and the stage derivatives, write m_s and spectrum."""
+    info = ctx.info()
+    nx, ny, nz = ctx.grid
+    n = nx * ny * nz
+    return (12 + 1 + 12 * avg_k_reads + 12) * n + 3 * 8 * info["kx"] * ny * nz
+
+
+def cpu_baseline(case, budget_s=12.0):
+    """The FP64 oracle timed on this host: torque evaluations of the same state."""
+    from oracle import fields as ofields
+
+    prob = ofields.Problem(case["grid"], case["cell"], case["region"], case["params"], workers=-1)
+    m = case["m0"].astype(np.float64)
+    prob.torque(m)  # first call pays scipy's plan setup
+    n, t0 = 0, time.perf_counter()
+    while True:
+        prob.torque(m)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or n >= 50:
+            break
+    ncell = int(np.prod(case["grid"]))
+    return {"value": ncell * n / el, "unit": "Beff evals*cells/s", "cores": os.cpu_count(), "kind": "oracle",
+            "sample": "%d FP64 B_eff+torque evaluations of the %dx%dx%d vortex state (scipy.fft, all cores), "
+                      "%.1f s" % (n, case["grid"][0], case["grid"][1], case["grid"][2], el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=1024, help="film edge in cells")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device copy 10 times (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the work would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1406_7635_amd import mm, synth
+
+    torch.cuda.init()
+    if args.copy_probe:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4,
+                          "launches": 10}))
+        return
+    case = synth.vortex_film(seed=2, n=args.n)
+    ncell = int(np.prod(case["grid"]))
+    ctx = mm.Context(case["grid"], case["cell"], case["region"], case["params"])
+    m = torch.from_numpy(case["m0"]).to("cuda:0")
+    opts = mm.solver_opts(max_err=1e-5)
+    t, dt, _ = ctx.run(m, float("inf"), dt=1e-14, max_attempts=max(1, args.warmup), opts=opts)
+    ctx.timing_enable(0)
+    ctx.timing_enable(1)
+    ctx.timing_enable(2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    w0 = time.perf_counter()
+    t, dt, st = ctx.run(m, float("inf"), t=t, dt=dt, max_attempts=args.steps, opts=opts)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = e0.elapsed_time(e1)
+    evals = st["evals"]
+    value = ncell * evals / wall
+    per = {}
+    for k, name in enumerate(("x_forward", "column_conv", "x_inverse")):
+        n, ms = ctx.timing_read(k)
+        per[name] = {"launches": n, "avg_us": 1e3 * ms / max(n, 1), "total_ms": ms}
+    dominant = max(per, key=lambda k: per[k]["total_ms"])
+    avg_k = 20.0 / 6.0  # stage-derivative reads per evaluation in RK45 (20 over 6 stages)
+    bytes_per_launch = {"x_forward": xfwd_pass_bytes(ctx, avg_k), "column_conv": column_pass_bytes(ctx),
+                        "x_inverse": xinv_pass_bytes(ctx)}
+    for k in per:
+        per[k]["alg_bytes"] = bytes_per_launch[k]
+        per[k]["gbs"] = bytes_per_launch[k] / (per[k]["avg_us"] * 1e-6) / 1e9
+    ach = per[dominant]["gbs"]
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as fh:
+            traffic = json.load(fh).get(dominant)
+    out = {
+        "metric": METRIC, "value": value, "unit": "Beff evals*cells/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "vortex film %dx%dx1, 2 nm cells, Msat 8e5, Aex 1.3e-11, alpha 0.01, "
+                               "B_ext 10 mT x; RK45 MaxErr 1e-5; plain FP32 FFT demag" % (args.n, args.n),
+                   "cells": ncell, "evals": evals, "accepted": st["steps"], "rejected": st["rejects"],
+                   "evals_per_step": 6, "gpu_event_ms": gpu_ms},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant},
+        "kernels": per,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(case)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -224,8 +224,9 @@ int mm_get_info(mm_ctx *c, mm_info *info);
  * for d = (i dx, j dy, k dz), 0 <= i < nx etc., as [6][nz][ny][nx] doubles
  * (component order xx, yy, zz, xy, xz, yz) into out_dev (recomputed on the
  * device).  mm_demag_kernel_dump copies the FP32 kernel spectrum, layout
- * [ky_h][kx][kz_h][6] in 3D or [kx][ky_h][4] when nz == 1 (h = folded index
- * 0..p/2), khat_elems floats.  mm_exchange_dump writes the per-face exchange
+ * [kx][ky_h][kz_h][ncomp] (h = folded index 0..p/2; ncomp = 6 in 3D with
+ * order xx, yy, zz, xy, xz, yz, or 4 when nz == 1: xx, yy, zz, xy),
+ * khat_elems floats.  mm_exchange_dump writes the per-face exchange
  * coefficient c(r, r_n)/D^2 actually gathered by the field kernels, as
  * [6][nz][ny][nx] floats in face order -x, +x, -y, +y, -z, +z (0 where the
  * neighbour is missing). */

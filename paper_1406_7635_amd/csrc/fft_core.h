@@ -1,19 +1,11 @@
-// fft_core.h -- in-LDS Stockham FFT building blocks (FP32) for gfx950.
+// fft_core.h -- register-resident FP32 FFT building blocks for gfx950.
 //
-// A workgroup holds F independent sequences of power-of-two length P in LDS,
-// sequence f at buf[f * seq_len(P) + lds_pad(i)].  The transform runs as a
-// chain of radix-R Stockham stages (autosort, no bit reversal): stage (R, L)
-// reads inputs j + r P/R, applies twiddles w^(r k) with w = exp(-+2 pi i/(L R))
-// and k = j mod L, does an R-point DFT and writes the outputs to
-// (j - k) R + k + r L.  The first stage takes radix 2 or 4 when log2 P is not
-// a multiple of 3; every later stage is radix 8.  Every stage first reads all
-// of its inputs into registers, then (after a barrier) writes, so one LDS
-// buffer suffices.  Forward uses exp(-2 pi i n k / P), inverse exp(+...),
-// both unnormalised.
-//
-// The read and write halves of a stage are separate __host__ __device__
-// functions so that a host program can emulate a whole workgroup and check
-// the index arithmetic against a reference DFT without a GPU.
+// Power-of-two transforms in Stockham (autosort) form: stage (R, L) reads
+// inputs j + r P/R, multiplies them by w^(r k) with w = exp(-+2 pi i/(L R)) and
+// k = j mod L, does an R-point DFT and writes the outputs to (j - k) R + k + r L.
+// Forward uses exp(-2 pi i n k / P), inverse exp(+...), both unnormalised.
+// Each thread keeps its points in registers; LDS is only the exchange medium
+// between stages.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,6 +32,12 @@ __host__ __device__ inline cf rot90(cf a) {
 }
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int ilog2_floor(int n) { return n <= 1 ? 0 : 1 + ilog2_floor(n / 2); }
+__host__ __device__ inline int ilog2_rt(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
 
 // one spare element every 8 spreads stride-8 Stockham writes over the LDS banks
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 3); }
@@ -95,82 +93,165 @@ struct Dft<8, INV> {
     }
 };
 
-// radix of the stage that starts at span L (the first stage absorbs log2 P mod 3)
-__host__ __device__ constexpr int stage_radix(int P, int L) {
-    return (L == 1 && (ilog2(P) % 3) != 0) ? (1 << (ilog2(P) % 3)) : 8;
-}
+template <bool INV>
+struct Dft<16, INV> {
+    // 16 = 4 x 4: DFT-4 over n1 for each n2, twiddle w16^(n2 k1), DFT-4 over n2
+    __host__ __device__ static void run(cf* v) {
+        const float c1 = 0.92387953251128676f, s1 = 0.38268343236508977f, h = 0.70710678118654752f;
+        const float cs[10][2] = {{1.f, 0.f}, {c1, s1}, {h, h}, {s1, c1}, {0.f, 1.f},
+                                 {-s1, c1}, {-h, h}, {-c1, s1}, {-1.f, 0.f}, {-c1, -s1}};
+        cf a[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            cf t[4] = {v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]};
+            Dft<4, INV>::run(t);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) {
+                const int m = n2 * k1;
+                const cf w = mkc(cs[m][0], INV ? cs[m][1] : -cs[m][1]);
+                a[n2][k1] = (m == 0) ? t[k1] : cmul(t[k1], w);
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            cf t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+            Dft<4, INV>::run(t);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+        }
+    }
+};
 
-// Stage read half: gather, twiddle and transform the butterflies of thread tid.
-// tw: table exp(-2 pi i m / PT), m < PT; twshift = log2(PT).
-template <int P, int R, int L, int F, int NT, bool INV>
-struct Stage {
-    static constexpr int NBF = P / R;          // butterflies per sequence
-    static constexpr int TOT = F * NBF;
-    static constexpr int NB = (TOT + NT - 1) / NT;
+// ---------------------------------------------------------------------------
+// Register-resident transform.  A group of TPF threads owns NF sequences of
+// length P; thread t keeps PPT = P/TPF points of each in registers, in
+// natural order v[f][m] = x[t + TPF m] on entry and X[t + TPF m] on exit.
+// Stage 0 has radix R0 (the remainder of log2 P modulo log2 PPT, else PPT) and
+// runs on the loaded registers; every later stage has radix PPT and gets its
+// inputs through one LDS exchange (write the previous stage's outputs at their
+// Stockham positions, barrier, read j + r TPF).  The NF sequences go through a
+// single LDS sequence one after the other, so a group needs seq_len(P)
+// elements of LDS.  The exchange halves are separate __host__ __device__
+// functions so a host program can emulate a group without a GPU.
+template <int P, int TPF, int NF, bool INV>
+struct RegFft {
+    static constexpr int PPT = P / TPF;
+    static constexpr int LP = ilog2(P);
+    static constexpr int LA = ilog2(PPT);
+    static constexpr int REM = LA == 0 ? 0 : LP % LA;
+    static constexpr int R0 = LA == 0 ? 1 : (REM ? (1 << REM) : PPT);
+    static constexpr int NS = LA == 0 ? 0 : (REM ? 1 : 0) + LP / LA;
     static constexpr int SEQ = seq_len(P);
-    static constexpr int TWL = ilog2(L * R);
 
-    __host__ __device__ static void read(const cf* buf, const cf* __restrict__ tw, int twshift,
-                                         int tid, cf (&v)[NB][R]) {
+    // span of stage s (product of the radices before it)
+    __host__ __device__ static int span(int s) { return s == 0 ? 1 : R0 << (LA * (s - 1)); }
+
+    // natural order -> stage-0 order, then the stage-0 butterflies (no twiddles)
+    __host__ __device__ static void stage0(cf (&v)[NF][PPT]) {
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int b = tid + q * NT;
-            if ((TOT % NT) == 0 || b < TOT) {
-                const int f = b / NBF;
-                const int j = b - f * NBF;
-                const int k = j & (L - 1);
-                const cf* src = buf + f * SEQ;
+        for (int f = 0; f < NF; ++f) {
+            cf w[PPT];
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[q][r] = src[lds_pad(j + r * NBF)];
-                if (L > 1) {
-                    const int sh = twshift - TWL;
+            for (int u = 0; u < PPT / R0; ++u)
 #pragma unroll
-                    for (int r = 1; r < R; ++r) {
-                        cf w = tw[(r * k) << sh];
-                        if (INV) w = cconj(w);
-                        v[q][r] = cmul(v[q][r], w);
-                    }
-                }
-                Dft<R, INV>::run(v[q]);
-            }
+                for (int r = 0; r < R0; ++r) w[u * R0 + r] = v[f][u + r * (PPT / R0)];
+#pragma unroll
+            for (int u = 0; u < PPT / R0; ++u) Dft<R0, INV>::run(w + u * R0);
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) v[f][i] = w[i];
         }
     }
 
-    __host__ __device__ static void write(cf* buf, int tid, const cf (&v)[NB][R]) {
+    // twiddles w^(r k), r < PPT, of thread t in stage s >= 1: the powers
+    // w^(2^i k) come from the table (exp(-2 pi i m / PT) rounded once), the
+    // others are products of at most log2(PPT) - 1 of them
+    __host__ __device__ static void twiddles(int s, int t, const cf* __restrict__ tw, int twshift, cf (&wt)[PPT]) {
+        const int L = span(s);
+        int k = t & (L - 1);
+#ifdef __HIP_DEVICE_COMPILE__
+        asm volatile("" : "+v"(k));  // keep the table loads at their stage (short live ranges)
+#endif
+        const int sh = twshift - ilog2_rt(L * PPT);
+        wt[0] = mkc(1.f, 0.f);
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int b = tid + q * NT;
-            if ((TOT % NT) == 0 || b < TOT) {
-                const int f = b / NBF;
-                const int j = b - f * NBF;
-                const int k = j & (L - 1);
-                cf* dst = buf + f * SEQ;
-                const int base = (j - k) * R + k;
+        for (int b = 1; b < PPT; b <<= 1) {
+            const cf w = tw[(b * k) << sh];
+            wt[b] = INV ? cconj(w) : w;
+        }
 #pragma unroll
-                for (int r = 0; r < R; ++r) dst[lds_pad(base + r * L)] = v[q][r];
-            }
+        for (int r = 3; r < PPT; ++r) {
+            if ((r & (r - 1)) == 0) continue;
+            const int hb = 1 << ilog2_floor(r);
+            wt[r] = cmul(wt[hb], wt[r - hb]);
         }
     }
-};
 
-// Whole transform on the device: stages chained at compile time.
-template <int P, int L, int F, int NT, bool INV>
-struct Fft {
-    static constexpr int R = stage_radix(P, L);
-    __device__ static void run(cf* buf, const cf* __restrict__ tw, int twshift, int tid) {
-        using S = Stage<P, R, L, F, NT, INV>;
-        cf v[S::NB][R];
-        S::read(buf, tw, twshift, tid, v);
-        __syncthreads();
-        S::write(buf, tid, v);
-        __syncthreads();
-        Fft<P, L * R, F, NT, INV>::run(buf, tw, twshift, tid);
+    // write the outputs of stage s-1 of sequence f at their positions
+    template <int RP>
+    __host__ __device__ static void write_r(int lp, const cf (&v)[NF][PPT], int f, cf* buf, int t) {
+#pragma unroll
+        for (int uu = 0; uu < PPT / RP; ++uu) {
+            const int j = t + TPF * uu;
+            const int k = j & (lp - 1);
+            const int base = (j - k) * RP + k;
+#pragma unroll
+            for (int r = 0; r < RP; ++r) buf[lds_pad(base + r * lp)] = v[f][uu * RP + r];
+        }
     }
-};
+    __host__ __device__ static void write(int s, const cf (&v)[NF][PPT], int f, cf* buf, int t) {
+        if (s == 1)
+            write_r<R0>(1, v, f, buf, t);
+        else
+            write_r<PPT>(span(s - 1), v, f, buf, t);
+    }
 
-template <int P, int F, int NT, bool INV>
-struct Fft<P, P, F, NT, INV> {
-    __device__ static void run(cf*, const cf* __restrict__, int, int) {}
+    // read the inputs of stage s (>= 1) for sequence f and run its butterfly
+    __host__ __device__ static void read_compute(int s, cf (&v)[NF][PPT], int f, const cf* buf, int t,
+                                                 const cf (&wt)[PPT]) {
+        (void)s;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) v[f][r] = buf[lds_pad(t + r * TPF)];
+#pragma unroll
+        for (int r = 1; r < PPT; ++r) v[f][r] = cmul(v[f][r], wt[r]);
+        Dft<PPT, INV>::run(v[f]);
+    }
+
+    // stage order of the last stage -> natural order
+    __host__ __device__ static void finish(cf (&v)[NF][PPT]) {
+        constexpr int RL = NS == 1 ? R0 : PPT;
+        if (RL == 1) return;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            cf w[PPT];
+#pragma unroll
+            for (int u = 0; u < PPT / RL; ++u)
+#pragma unroll
+                for (int r = 0; r < RL; ++r) w[u + r * (PPT / RL)] = v[f][u * RL + r];
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) v[f][i] = w[i];
+        }
+    }
+
+    __device__ static void run(cf (&v)[NF][PPT], cf* buf, const cf* __restrict__ tw, int twshift, int t) {
+        if (NS == 0) return;
+        stage0(v);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) {
+            cf wt[PPT];
+            twiddles(s, t, tw, twshift, wt);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                __syncthreads();
+                if (s == 1)
+                    write_r<R0>(1, v, f, buf, t);
+                else
+                    write_r<PPT>(span(s - 1), v, f, buf, t);
+                __syncthreads();
+                read_compute(s, v, f, buf, t, wt);
+            }
+        }
+        finish(v);
+    }
 };
 
 }  // namespace mm

@@ -1,108 +1,112 @@
-// Host-side emulation of the LDS Stockham FFT of fft_core.h.
+// Host-side emulation of the register-resident FFT of fft_core.h.
 //
-// Runs every stage's read half for all threads of a workgroup, then every
-// write half, exactly as the barrier-separated device code does, and compares
-// the result with a direct O(P^2) DFT in double precision.  Exit status 0 when
+// Runs every phase (stage 0, then per exchange: the LDS writes of all threads,
+// then their reads and butterflies) for all threads of a group, exactly in the
+// order the barrier-separated device code imposes, and compares the result
+// with a direct O(P^2) DFT in double precision.  Exit status 0 when
 // every size and direction agrees to FP32 accuracy.  Built and run by the CPU
 // test-suite (no GPU needed).
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <array>
 #include <vector>
 
 #include "fft_core.h"
 
 using mm::cf;
 
-template <int P, int L, int F, int NT, bool INV>
-struct HostFft {
-    static void run(cf* buf, const cf* tw, int twshift) {
-        constexpr int R = mm::stage_radix(P, L);
-        using S = mm::Stage<P, R, L, F, NT, INV>;
-        std::vector<cf> regs((size_t)NT * S::NB * R);
-        for (int tid = 0; tid < NT; ++tid) {
-            cf v[S::NB][R];
-            S::read(buf, tw, twshift, tid, v);
-            for (int q = 0; q < S::NB; ++q)
-                for (int r = 0; r < R; ++r) regs[((size_t)tid * S::NB + q) * R + r] = v[q][r];
+// Emulation of RegFft: every phase for all TPF threads, in barrier order.
+template <int P, int TPF, int NF, bool INV>
+static void host_regfft(std::vector<cf>& data /* NF * P natural */, const cf* tw, int twshift) {
+    using R = mm::RegFft<P, TPF, NF, INV>;
+    constexpr int PPT = R::PPT;
+    std::vector<std::array<std::array<cf, PPT>, NF>> regs(TPF);
+    for (int t = 0; t < TPF; ++t)
+        for (int f = 0; f < NF; ++f)
+            for (int m = 0; m < PPT; ++m) regs[t][f][m] = data[(size_t)f * P + t + TPF * m];
+    auto as_arr = [](std::array<std::array<cf, PPT>, NF>& a) -> cf(&)[NF][PPT] {
+        return *reinterpret_cast<cf(*)[NF][PPT]>(&a);
+    };
+    if (R::NS > 0) {
+        for (int t = 0; t < TPF; ++t) R::stage0(as_arr(regs[t]));
+        std::vector<cf> buf(mm::seq_len(P), mm::mkc(NAN, NAN));
+        for (int s = 1; s < R::NS; ++s) {
+            for (int f = 0; f < NF; ++f) {
+                for (int t = 0; t < TPF; ++t) R::write(s, as_arr(regs[t]), f, buf.data(), t);
+                for (int t = 0; t < TPF; ++t) {
+                    cf wt[PPT];
+                    R::twiddles(s, t, tw, twshift, wt);
+                    R::read_compute(s, as_arr(regs[t]), f, buf.data(), t, wt);
+                }
+            }
         }
-        for (int tid = 0; tid < NT; ++tid) {
-            cf v[S::NB][R];
-            for (int q = 0; q < S::NB; ++q)
-                for (int r = 0; r < R; ++r) v[q][r] = regs[((size_t)tid * S::NB + q) * R + r];
-            S::write(buf, tid, v);
-        }
-        HostFft<P, L * R, F, NT, INV>::run(buf, tw, twshift);
+        for (int t = 0; t < TPF; ++t) R::finish(as_arr(regs[t]));
     }
-};
+    for (int t = 0; t < TPF; ++t)
+        for (int f = 0; f < NF; ++f)
+            for (int m = 0; m < PPT; ++m) data[(size_t)f * P + t + TPF * m] = regs[t][f][m];
+}
 
-template <int P, int F, int NT, bool INV>
-struct HostFft<P, P, F, NT, INV> {
-    static void run(cf*, const cf*, int) {}
-};
-
-template <int P, int F, int NT>
-static int check(int PT) {
+template <int P, int TPF>
+static int check_reg(int PT) {
+    constexpr int NF = 3;
     std::vector<cf> tw(PT);
     for (int m = 0; m < PT; ++m) {
         double a = -2.0 * M_PI * m / PT;
         tw[m] = mm::mkc((float)cos(a), (float)sin(a));
     }
-    const int twshift = mm::ilog2(PT);
     int bad = 0;
     for (int dir = 0; dir < 2; ++dir) {
-        std::vector<cf> buf((size_t)F * mm::seq_len(P), mm::mkc(NAN, NAN));
-        std::vector<double> re((size_t)F * P), im((size_t)F * P);
-        srand(P * 7 + F + dir);
-        for (int f = 0; f < F; ++f)
-            for (int i = 0; i < P; ++i) {
-                double a = rand() / (double)RAND_MAX - 0.5, b = rand() / (double)RAND_MAX - 0.5;
-                re[(size_t)f * P + i] = (float)a;
-                im[(size_t)f * P + i] = (float)b;
-                buf[(size_t)f * mm::seq_len(P) + mm::lds_pad(i)] = mm::mkc((float)a, (float)b);
-            }
-        if (dir == 0)
-            HostFft<P, 1, F, NT, false>::run(buf.data(), tw.data(), twshift);
-        else
-            HostFft<P, 1, F, NT, true>::run(buf.data(), tw.data(), twshift);
+        std::vector<cf> data((size_t)NF * P);
+        std::vector<double> re(data.size()), im(data.size());
+        srand(P * 13 + TPF + dir);
+        for (size_t i = 0; i < data.size(); ++i) {
+            re[i] = (float)(rand() / (double)RAND_MAX - 0.5);
+            im[i] = (float)(rand() / (double)RAND_MAX - 0.5);
+            data[i] = mm::mkc((float)re[i], (float)im[i]);
+        }
+        if (dir == 0) host_regfft<P, TPF, NF, false>(data, tw.data(), mm::ilog2(PT));
+        else host_regfft<P, TPF, NF, true>(data, tw.data(), mm::ilog2(PT));
         double maxerr = 0, maxref = 0;
-        for (int f = 0; f < F; ++f)
+        for (int f = 0; f < NF; ++f)
             for (int k = 0; k < P; ++k) {
                 double sr = 0, si = 0;
                 for (int n = 0; n < P; ++n) {
                     double a = (dir == 0 ? -2.0 : 2.0) * M_PI * (double)((long)n * k % P) / P;
-                    double xr = re[(size_t)f * P + n], xi = im[(size_t)f * P + n];
-                    sr += xr * cos(a) - xi * sin(a);
-                    si += xr * sin(a) + xi * cos(a);
+                    sr += re[(size_t)f * P + n] * cos(a) - im[(size_t)f * P + n] * sin(a);
+                    si += re[(size_t)f * P + n] * sin(a) + im[(size_t)f * P + n] * cos(a);
                 }
-                cf g = buf[(size_t)f * mm::seq_len(P) + mm::lds_pad(k)];
+                cf g = data[(size_t)f * P + k];
                 maxerr = fmax(maxerr, fmax(fabs(g.x - sr), fabs(g.y - si)));
                 maxref = fmax(maxref, fmax(fabs(sr), fabs(si)));
             }
         const double tol = 2e-6 * (mm::ilog2(P) + 1) * maxref + 1e-6;
         const bool ok = maxerr <= tol;
         if (!ok) ++bad;
-        printf("P=%5d F=%2d NT=%3d %s max_err=%.3e ref=%.3e %s\n", P, F, NT, dir ? "inv" : "fwd",
-               maxerr, maxref, ok ? "ok" : "FAIL");
+        printf("reg P=%5d TPF=%3d %s max_err=%.3e ref=%.3e %s\n", P, TPF, dir ? "inv" : "fwd", maxerr, maxref,
+               ok ? "ok" : "FAIL");
     }
     return bad;
 }
 
 int main() {
     int bad = 0;
-    bad += check<1, 3, 256>(4096);
-    bad += check<2, 3, 256>(4096);
-    bad += check<4, 6, 256>(4096);
-    bad += check<8, 3, 256>(4096);
-    bad += check<16, 5, 256>(1024);
-    bad += check<32, 3, 64>(4096);
-    bad += check<64, 48, 256>(4096);
-    bad += check<128, 48, 256>(4096);
-    bad += check<256, 24, 256>(4096);
-    bad += check<512, 12, 256>(512);
-    bad += check<1024, 6, 256>(4096);
-    bad += check<2048, 3, 256>(2048);
-    bad += check<4096, 3, 256>(4096);
+    bad += check_reg<1, 1>(4096);
+    bad += check_reg<2, 1>(4096);
+    bad += check_reg<4, 1>(4096);
+    bad += check_reg<8, 1>(4096);
+    bad += check_reg<16, 2>(4096);
+    bad += check_reg<32, 4>(4096);
+    bad += check_reg<64, 8>(4096);
+    bad += check_reg<128, 16>(4096);
+    bad += check_reg<256, 32>(4096);
+    bad += check_reg<512, 64>(512);
+    bad += check_reg<512, 32>(4096);
+    bad += check_reg<1024, 64>(4096);
+    bad += check_reg<2048, 128>(2048);
+    bad += check_reg<2048, 256>(4096);
+    bad += check_reg<4096, 256>(4096);
     printf("%s\n", bad ? "FAILED" : "ALL OK");
     return bad ? 1 : 0;
 }

@@ -148,11 +148,12 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// red: LDS scratch of at least (NT/64) * 6 doubles.
+// red: LDS scratch of at least (NTH/64) * 6 doubles; NTH = threads of the workgroup.
+template <int NTH>
 __device__ inline void epi_reduce(const FieldArgs& a, EpiAcc& acc, double* red, int blk) {
     const int flags = a.flags;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int NW = NT / 64;
+    constexpr int NW = NTH / 64 > 0 ? NTH / 64 : 1;
     if (flags & (EPI_ERR | EPI_MAXTQ)) {
         const float e = wave_max(acc.errmax), t = wave_max(acc.tqmax);
         if (lane == 0) {

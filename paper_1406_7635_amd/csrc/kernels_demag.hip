@@ -183,7 +183,7 @@ hipError_t demag_tensor_octant(int nx, int ny, int nz, double dx, double dy, dou
                        dy, dz, gl, gl + GL_TABLE, out);
     e = hipGetLastError();
     const hipError_t e2 = hipStreamSynchronize(s);
-    hipFree(gl);
+    (void)hipFree(gl);
     return e != hipSuccess ? e : e2;
 }
 
@@ -258,7 +258,8 @@ __global__ void __launch_bounds__(256) k_fft64_lines(double2* __restrict__ data,
 }
 
 // Keep Re of the spectrum's non-negative octant as FP32, in the layout the
-// convolution pass reads: [kx][ky_h][4] when nz == 1, else [ky_h][kx][kz_h][6].
+// convolution pass reads: [kx][ky_h][kz_h][ncomp] (ncomp = 4 when nz == 1:
+// xx, yy, zz, xy; else 6).
 __global__ void __launch_bounds__(256) k_extract(int px, int py, int pz, int comp, int ncomp, int kx,
                                                  const double2* __restrict__ work, float* __restrict__ khat) {
     const int kyh = py / 2 + 1, kzh = pz / 2 + 1;
@@ -269,11 +270,7 @@ __global__ void __launch_bounds__(256) k_extract(int px, int py, int pz, int com
     const long long rest = id / kx;
     const int iy = (int)(rest % kyh), iz = (int)(rest / kyh);
     const double v = work[((long long)iz * py + iy) * px + ix].x;
-    long long dst;
-    if (ncomp == 4)
-        dst = ((long long)ix * kyh + iy) * 4 + comp;
-    else
-        dst = (((long long)iy * kx + ix) * kzh + iz) * 6 + comp;
+    const long long dst = (((long long)ix * kyh + iy) * kzh + iz) * ncomp + comp;
     khat[dst] = (float)v;
 }
 
@@ -300,7 +297,7 @@ hipError_t demag_kernel_spectrum(int nx, int ny, int nz, int px, int py, int pz,
                 outer_stride = 0;
             }
             const size_t lds = 2 * (size_t)p * sizeof(double2);
-            hipFuncSetAttribute((const void*)k_fft64_lines, hipFuncAttributeMaxDynamicSharedMemorySize,
+            (void)hipFuncSetAttribute((const void*)k_fft64_lines, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
             hipLaunchKernelGGL(k_fft64_lines, dim3((unsigned)nlines), dim3(256), lds, s, work, p, 0, stride,
                                n_inner, inner_stride, outer_stride);

@@ -1,296 +1,426 @@
 // kernels_fft.hip -- the FP32 magnetostatic convolution passes.
 //
 // Section "Magnetostatic field": B_demag = K * M evaluated with the
-// convolution theorem on a grid zero-padded to px x py x pz.  The passes:
-//   x-forward  : per pair of x-rows, stage combine m_s = m0 + dt sum a k,
-//                M = Msat[region] m_s, zero padding in LDS, real-to-complex
-//                FFT along x (two real rows packed per complex transform),
-//                written as 3 interleaved complex components per (row, kx);
-//   column     : FFT along y (and z) of T adjacent kx columns; in the last
-//                axis the pointwise B^ = K^ M^ (K^ real symmetric, stored as
-//                one octant with mirror signs) and the inverse transform;
-//   x-inverse  : complex-to-real along x (two real rows per transform), crop
-//                to the physical cells, then the per-cell epilogue (exchange,
-//                anisotropy, Zeeman, torque, error norm, energies).
+// convolution theorem on a grid zero-padded to px x py x pz.
+//
+// Spectrum layout (complex64): element (z, kx, y, c) at
+//   z * zstride + kx * colstride + y * 3 + c,  colstride = 3 * ycount,
+// ycount = py in 3D (the y transforms run in place), ny in 2D.  Every column
+// along y is contiguous, so the column passes read and write whole columns.
+//
+// The three real components of two x-rows a, b travel as three complex
+// "slots": slot 0 = Mx_a + i My_a, slot 1 = Mx_b + i My_b, slot 2 = Mz_a + i Mz_b.
+// Each thread owns one slot (or one component in the column passes), so a
+// row pair or a column is spread over three thread groups.
+//
+// Passes:
+//   x-forward : one slot of one row pair per thread group: stage combine
+//               m_s = m0 + dt sum a k, M = Msat[region] m_s, FFT along x of
+//               the zero-padded rows, separation of the two real transforms
+//               X = (Z[k] + conj Z[P-k])/2, Y = (Z[k] - conj Z[P-k])/(2i);
+//   column    : per column, one thread group per component: FFT along y (3D:
+//               forward and inverse around the z pass), or forward FFT,
+//               B^_i = sum_j K^_ij M^_j through LDS (K^ real symmetric, one
+//               octant stored, mirror signs applied), inverse FFT.  In 2D the
+//               DC and Nyquist columns (both real along y) share one complex
+//               column;
+//   x-inverse : the three slots of a row pair: Hermitian extension, inverse
+//               FFT, crop, then the per-cell epilogue (exchange, anisotropy,
+//               Zeeman, torque, error norm, energies).
 // The 1/(px py pz) normalisation and -mu0 are folded into K^.
-#include <algorithm>
-
 #include "field_epilogue.h"
 
 namespace mm {
 
-// rows of the x passes per workgroup: H rows = 3H/2 complex transforms
-constexpr int rows_per_wg(int P) { return P >= 2048 ? 2 : (P >= 256 ? 4096 / P : 16); }
-// adjacent kx columns per workgroup in the column passes
-constexpr int cols_per_wg(int P) { return P >= 2048 ? 1 : (P >= 128 ? 2048 / P : 16); }
+template <int P>
+struct Cfg {
+    static constexpr int PPT = P < 8 ? P : (P >= 4096 ? 16 : 8);  // points per thread
+    static constexpr int TPF = P / PPT;                           // threads per sequence
+    static constexpr int G = TPF >= 256 ? 1 : 256 / TPF;          // sequences per 256 threads
+};
 
-__device__ inline long long row_offset(const FieldArgs& a, int row) {
+// x-forward: G row pairs of one slot per workgroup
+template <int P>
+struct XfCfg {
+    static constexpr int G = Cfg<P>::G;
+    static constexpr int NTH = G * Cfg<P>::TPF;
+};
+
+// x-inverse: the 3 slots of GI row pairs per workgroup
+template <int P>
+struct XiCfg {
+    static constexpr int GI = Cfg<P>::TPF >= 256 ? 1 : (Cfg<P>::TPF >= 128 ? 2 : 256 / Cfg<P>::TPF);
+    static constexpr int NTH = 3 * GI * Cfg<P>::TPF;
+};
+
+// columns: the 3 components of T columns per workgroup
+template <int P>
+struct ColCfg {
+    static constexpr int T = Cfg<P>::TPF >= 256 ? 1 : (Cfg<P>::TPF >= 128 ? 2 : 256 / Cfg<P>::TPF);
+    static constexpr int NTH = 3 * T * Cfg<P>::TPF;
+};
+
+__device__ inline long long row_base(const FieldArgs& a, int row) {
     const int z = row / a.ny, y = row - z * a.ny;
-    return (long long)z * a.zstride + (long long)y * a.rowstride;
+    return (long long)z * a.zstride + 3LL * y;
 }
 
 // ---------------------------------------------------------------------------
-template <int P, int H>
-__global__ void __launch_bounds__(NT) k_xfwd(const FieldArgs a) {
-    constexpr int F = 3 * H / 2;
+template <int P>
+__global__ void __launch_bounds__(XfCfg<P>::NTH) k_xfwd(const FieldArgs a) {
+    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, G = XfCfg<P>::G;
     constexpr int SEQ = seq_len(P);
-    constexpr int KX = P / 2 + 1;
+    constexpr int MH = PPT / 2 + 1;
     extern __shared__ cf lds[];
     if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
     const int tid = threadIdx.x;
-    const int row0 = xcd_remap(blockIdx.x, gridDim.x) * H;
+    const int g = tid / TPF, t = tid - g * TPF;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int slot = blk % 3;
+    const int pair = (blk / 3) * G + g;
+    const int ra = 2 * pair, rb = ra + 1;
+    const bool va = ra < a.nrows, vb = rb < a.nrows;
     const float dt = (float)a.st->dt;
-    const bool write_ms = a.sd.nk > 0;
+    cf* buf = lds + g * SEQ;
+    const long long n = a.ncell;
 
-    // load, combine, scale by Msat; pack rows (a, b) as Mx_a + i My_a,
-    // Mx_b + i My_b and Mz_a + i Mz_b
-    for (int idx = tid; idx < H * P; idx += NT) {
-        const int rr = idx / P, x = idx - rr * P;
-        const int row = row0 + rr;
-        float3 M = make_float3(0.f, 0.f, 0.f);
-        if (x < a.nx && row < a.nrows) {
-            const long long cell = (long long)row * a.nx + x;
-            const float3 m = stage_state(a, cell, dt);
-            if (write_ms) st3(a.ms, a.ncell, cell, m);
-            M = f3scale(a.lut[a.region[cell]].a.x, m);
-        }
-        const int p = rr >> 1;
-        cf* s01 = lds + (3 * p + (rr & 1)) * SEQ;
-        cf* s2 = lds + (3 * p + 2) * SEQ;
-        const int px = lds_pad(x);
-        s01[px] = mkc(M.x, M.y);
-        if (rr & 1)
-            s2[px].y = M.z;
-        else
-            s2[px].x = M.z;
-    }
-    __syncthreads();
-    Fft<P, 1, F, NT, false>::run(lds, a.tw, a.twshift, tid);
+    // slot 0: (x, y) of row a, slot 1: (x, y) of row b, slot 2: z of rows a and b
+    const int r0 = slot == 1 ? rb : ra;
+    const bool v0 = slot == 1 ? vb : va;
+    const int c0 = slot == 2 ? 2 : 0;
+    const int r1 = slot == 0 ? ra : rb;
+    const bool v1 = slot == 0 ? va : vb;
+    const int c1 = slot == 2 ? 2 : 1;
 
-    // unpack the half spectra: X = (Z[k] + conj Z[P-k])/2, Y = (Z[k] - conj Z[P-k])/(2i)
-    for (int idx = tid; idx < (H / 2) * KX; idx += NT) {
-        const int p = idx / KX, k = idx - p * KX;
-        const int kn = (P - k) & (P - 1);
-        const int ra = row0 + 2 * p, rb = ra + 1;
-        const cf* s0 = lds + (3 * p) * SEQ;
-        cf X[3], Y[3];
+    cf v[1][PPT];
 #pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            const cf z = s0[s * SEQ + lds_pad(k)];
-            const cf w = cconj(s0[s * SEQ + lds_pad(kn)]);
-            const cf d = z - w;
-            X[s] = 0.5f * (z + w);
-            Y[s] = mkc(0.5f * d.y, -0.5f * d.x);
+    for (int m = 0; m < PPT; ++m) {
+        const int x = t + TPF * m;
+        float re = 0.f, im = 0.f;
+        if (x < a.nx) {
+            if (v0) {
+                const long long cell = (long long)r0 * a.nx + x;
+                float s = a.m0[c0 * n + cell];
+                if (a.sd.nk > 0) {
+                    float acc = 0.f;
+                    for (int j = 0; j < a.sd.nk; ++j) acc += a.sd.a[j] * kslot(a, a.sd.kidx[j])[c0 * n + cell];
+                    s += dt * acc;
+                    a.ms[c0 * n + cell] = s;
+                }
+                re = a.lut[a.region[cell]].a.x * s;
+            }
+            if (v1) {
+                const long long cell = (long long)r1 * a.nx + x;
+                float s = a.m0[c1 * n + cell];
+                if (a.sd.nk > 0) {
+                    float acc = 0.f;
+                    for (int j = 0; j < a.sd.nk; ++j) acc += a.sd.a[j] * kslot(a, a.sd.kidx[j])[c1 * n + cell];
+                    s += dt * acc;
+                    a.ms[c1 * n + cell] = s;
+                }
+                im = a.lut[a.region[cell]].a.x * s;
+            }
         }
-        // slot 0 -> row a (x, y), slot 1 -> row b (x, y), slot 2 -> (z of a, z of b)
-        if (ra < a.nrows) {
-            cf* d = a.spec + row_offset(a, ra) + 3LL * k;
-            d[0] = X[0];
-            d[1] = Y[0];
-            d[2] = X[2];
-        }
-        if (rb < a.nrows) {
-            cf* d = a.spec + row_offset(a, rb) + 3LL * k;
-            d[0] = X[1];
-            d[1] = Y[1];
-            d[2] = Y[2];
+        v[0][m] = mkc(re, im);
+    }
+    RegFft<P, TPF, 1, false>::run(v, buf, a.tw, a.twshift, t);
+
+    // separate the two real transforms of this slot
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
+    __syncthreads();
+    const long long b0 = v0 ? row_base(a, r0) : 0, b1 = v1 ? row_base(a, r1) : 0;
+#pragma unroll
+    for (int m = 0; m < MH; ++m) {
+        const int k = t + TPF * m;
+        if (2 * k > P) continue;
+        const cf z = v[0][m < PPT ? m : 0];
+        const cf w = cconj(buf[lds_pad((P - k) & (P - 1))]);
+        const cf d = z - w;
+        const cf X = 0.5f * (z + w);
+        const cf Y = mkc(0.5f * d.y, -0.5f * d.x);
+        const long long off = (long long)k * a.colstride;
+        if (slot == 2) {
+            if (v0) a.spec[b0 + off + 2] = X;
+            if (v1) a.spec[b1 + off + 2] = Y;
+        } else if (v0) {
+            cf* dst = a.spec + b0 + off;
+            dst[0] = X;
+            dst[1] = Y;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-template <int P, int T, int MODE, int NC>
-__global__ void __launch_bounds__(NT) k_col(const ColArgs a) {
-    constexpr int F = 3 * T;
+// Column pass.  Threads: (column ci < T, component s < 3, t < TPF); with
+// CFAST the column index varies fastest over the lanes (strided columns, so
+// neighbouring lanes read neighbouring columns), else t does (contiguous
+// columns).
+template <int P, int MODE, int NC, bool CFAST>
+__global__ void __launch_bounds__(ColCfg<P>::NTH) k_col(const ColArgs a) {
+    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, T = ColCfg<P>::T;
     constexpr int SEQ = seq_len(P);
-    constexpr int W = 3 * T;
     extern __shared__ cf lds[];
     if (a.check_done && a.st->done) return;
     const int tid = threadIdx.x;
-    const int ntile = (a.ncolx + T - 1) / T;
+    int ci, s, t;
+    if (CFAST) {
+        s = tid % 3;
+        ci = (tid / 3) % T;
+        t = tid / (3 * T);
+    } else {
+        t = tid % TPF;
+        s = (tid / TPF) % 3;
+        ci = tid / (3 * TPF);
+    }
+    const int ntile = (a.ncol + T - 1) / T;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int o = blk / ntile, tile = blk - o * ntile;
-    const int kx0 = tile * T;
-    const int wv = 3 * min(T, a.ncolx - kx0);
-    cf* base = a.spec + (long long)o * a.outer_stride + 3LL * kx0;
+    const int c = tile * T + ci;
+    const bool valid = c < a.ncol;
+    // 2D convolution: column 0 carries kx = 0 (real part) and kx = px/2 (imaginary part)
+    const bool packed = MODE == COL_CONV && NC == 4 && a.pack_col > 0 && c == 0;
+    cf* base = a.spec + (long long)o * a.outer_stride + (long long)(valid ? c : 0) * a.col_stride;
+    cf* baseN = a.spec + (long long)a.pack_col * a.col_stride;
+    cf* bufs = lds + ci * 3 * SEQ;
+    cf* buf = bufs + s * SEQ;
 
-    for (int idx = tid; idx < P * W; idx += NT) {
-        const int q = idx / W, tc = idx - q * W;
-        cf v = mkc(0.f, 0.f);
-        if (q < a.n_in && tc < wv) v = base[(long long)q * a.stride + tc];
-        lds[tc * SEQ + lds_pad(q)] = v;
+    cf v[1][PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int q = t + TPF * m;
+        const bool ld = valid && q < a.n_in;
+        const long long off = (long long)q * a.pos_stride + s;
+        cf x = ld ? base[off] : mkc(0.f, 0.f);
+        if (packed) x = mkc(x.x, ld ? baseN[off].x : 0.f);
+        v[0][m] = x;
     }
-    __syncthreads();
-    if (MODE == COL_INV)
-        Fft<P, 1, F, NT, true>::run(lds, a.tw, a.twshift, tid);
-    else
-        Fft<P, 1, F, NT, false>::run(lds, a.tw, a.twshift, tid);
+    RegFft<P, TPF, 1, MODE == COL_INV>::run(v, buf, a.tw, a.twshift, t);
 
     if (MODE == COL_CONV) {
-        // outer index o is ky in 3D (parity of xy, yz in y), 0 in 2D
-        int ah = o;
+        // all three components of this column through LDS
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
+        __syncthreads();
+        // 2D: column c is kx and the transform runs along y.
+        // 3D: outer o is kx, column c is ky, the transform runs along z.
+        int kx = NC == 6 ? o : c;
+        asm volatile("" : "+v"(kx));  // load K^ here, not before the forward transform
+        int kyh = 0;
         bool fa = false;
-        if (a.pa > 1 && 2 * o > a.pa) {
-            ah = a.pa - o;
-            fa = true;
+        if (NC == 6) {
+            kyh = c;
+            if (2 * c > a.pa) {
+                kyh = a.pa - c;
+                fa = true;
+            }
         }
-        for (int idx = tid; idx < P * T; idx += NT) {
-            const int t = idx / P, q = idx - t * P;
-            if (3 * t >= wv) continue;
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
+            const int q = t + TPF * m;
             int qh = q;
             bool fq = false;
             if (2 * q > P) {
                 qh = P - q;
                 fq = true;
             }
-            const float* K = a.khat + (((long long)ah * a.ncolx + kx0 + t) * a.khq + qh) * NC;
-            const float kxx = K[0], kyy = K[1], kzz = K[2];
-            float kxy = K[3], kxz = 0.f, kyz = 0.f;
-            if (NC == 6) {
-                kxz = K[4];
-                kyz = K[5];
-                if (fq) {  // conv axis z: xz and yz are odd in z
-                    kxz = -kxz;
-                    kyz = -kyz;
-                }
-                if (fa) {  // outer axis y: xy and yz are odd in y
+            // row s of the symmetric K^ at (kxx, ky, q), with the mirror signs
+            auto krow = [&](int kxx) {
+                float3 r = make_float3(0.f, 0.f, 0.f);
+                if (!valid) return r;
+                const float* K = a.khat + (((long long)kxx * a.kyh + kyh) * a.kzh + qh) * NC;
+                float kxy = K[3], kxz = 0.f, kyz = 0.f;
+                if (NC == 6) {
+                    kxz = K[4];
+                    kyz = K[5];
+                    if (fq) {  // z: xz and yz are odd in z
+                        kxz = -kxz;
+                        kyz = -kyz;
+                    }
+                    if (fa) {  // y: xy and yz are odd in y
+                        kxy = -kxy;
+                        kyz = -kyz;
+                    }
+                } else if (fq) {  // y: xy is odd in y
                     kxy = -kxy;
-                    kyz = -kyz;
                 }
-            } else if (fq) {  // conv axis y: xy is odd in y
-                kxy = -kxy;
+                if (s == 0)
+                    r = make_float3(K[0], kxy, kxz);
+                else if (s == 1)
+                    r = make_float3(kxy, K[1], kyz);
+                else
+                    r = make_float3(kxz, kyz, K[2]);
+                return r;
+            };
+            const cf m0 = bufs[lds_pad(q)], m1 = bufs[SEQ + lds_pad(q)], m2 = bufs[2 * SEQ + lds_pad(q)];
+            if (!packed) {
+                const float3 K = krow(kx);
+                v[0][m] = K.x * m0 + K.y * m1 + K.z * m2;
+            } else {
+                // Z = A0 + i AN with A0, AN real along y: A0^(k) = (Z(k) + conj Z(-k))/2,
+                // AN^(k) = (Z(k) - conj Z(-k))/(2i); both field columns stay real, so
+                // B0^ + i BN^ recombines them.
+                const int qn = (P - q) & (P - 1);
+                const cf n0 = cconj(bufs[lds_pad(qn)]), n1 = cconj(bufs[SEQ + lds_pad(qn)]),
+                         n2 = cconj(bufs[2 * SEQ + lds_pad(qn)]);
+                const cf a00 = 0.5f * (m0 + n0), a01 = 0.5f * (m1 + n1), a02 = 0.5f * (m2 + n2);
+                const cf d0 = m0 - n0, d1 = m1 - n1, d2 = m2 - n2;
+                const cf an0 = mkc(0.5f * d0.y, -0.5f * d0.x), an1 = mkc(0.5f * d1.y, -0.5f * d1.x),
+                         an2 = mkc(0.5f * d2.y, -0.5f * d2.x);
+                const float3 K0 = krow(0), KN = krow(a.pack_col);
+                const cf b0 = K0.x * a00 + K0.y * a01 + K0.z * a02;
+                const cf bn = KN.x * an0 + KN.y * an1 + KN.z * an2;
+                v[0][m] = mkc(b0.x - bn.y, b0.y + bn.x);
             }
-            cf* sx = lds + (3 * t) * SEQ + lds_pad(q);
-            cf* sy = sx + SEQ;
-            cf* sz = sy + SEQ;
-            const cf mx = *sx, my = *sy, mz = *sz;
-            *sx = kxx * mx + kxy * my + kxz * mz;
-            *sy = kxy * mx + kyy * my + kyz * mz;
-            *sz = kxz * mx + kyz * my + kzz * mz;
         }
-        __syncthreads();
-        Fft<P, 1, F, NT, true>::run(lds, a.tw, a.twshift, tid);
+        RegFft<P, TPF, 1, true>::run(v, buf, a.tw, a.twshift, t);
     }
 
-    for (int idx = tid; idx < a.n_out * W; idx += NT) {
-        const int q = idx / W, tc = idx - q * W;
-        if (tc < wv) base[(long long)q * a.stride + tc] = lds[tc * SEQ + lds_pad(q)];
+    int t2 = t;
+    asm volatile("" : "+v"(t2));  // form the store addresses here, not at load time
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int q = t2 + TPF * m;
+        if (valid && q < a.n_out) {
+            const long long off = (long long)q * a.pos_stride + s;
+            if (!packed) {
+                base[off] = v[0][m];
+            } else {
+                base[off] = mkc(v[0][m].x, 0.f);
+                baseN[off] = mkc(v[0][m].y, 0.f);
+            }
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-template <int P, int H>
-__global__ void __launch_bounds__(NT) k_xinv(const FieldArgs a) {
-    constexpr int F = 3 * H / 2;
+template <int P>
+__global__ void __launch_bounds__(XiCfg<P>::NTH) k_xinv(const FieldArgs a) {
+    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XiCfg<P>::GI, NTH = XiCfg<P>::NTH;
     constexpr int SEQ = seq_len(P);
-    constexpr int KX = P / 2 + 1;
+    constexpr int MH = PPT / 2 + 1;
     extern __shared__ cf lds[];
-    __shared__ double red[(NT / 64) * 6];
+    __shared__ double red[(NTH / 64 > 0 ? NTH / 64 : 1) * 6];
     if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
     const int tid = threadIdx.x;
+    const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int row0 = blk * H;
+    const int pair0 = blk * GI;
+    const int pair = pair0 + g;
+    const int ra = 2 * pair, rb = ra + 1;
+    const bool va = ra < a.nrows, vb = rb < a.nrows;
+    cf* bufs = lds + g * 3 * SEQ;
+    cf* buf = bufs + slot * SEQ;
 
-    // Hermitian extension: slot[k] = X[k] + i Y[k], slot[P-k] = conj X[k] + i conj Y[k]
-    for (int idx = tid; idx < (H / 2) * KX; idx += NT) {
-        const int p = idx / KX, k = idx - p * KX;
-        const int ra = row0 + 2 * p, rb = ra + 1;
-        cf A[3] = {mkc(0.f, 0.f), mkc(0.f, 0.f), mkc(0.f, 0.f)};
-        cf B[3] = {mkc(0.f, 0.f), mkc(0.f, 0.f), mkc(0.f, 0.f)};
-        if (ra < a.nrows) {
-            const cf* s = a.spec + row_offset(a, ra) + 3LL * k;
-            A[0] = s[0];
-            A[1] = s[1];
-            A[2] = s[2];
-        }
-        if (rb < a.nrows) {
-            const cf* s = a.spec + row_offset(a, rb) + 3LL * k;
-            B[0] = s[0];
-            B[1] = s[1];
-            B[2] = s[2];
-        }
-        const bool edge = (k == 0) || (2 * k == P);
-        if (edge) {  // DC and Nyquist bins of a real signal are real
+    // Hermitian extension of this slot u + i w (slot 0: x, y of row a;
+    // slot 1: x, y of row b; slot 2: z of rows a and b) from the half spectra:
+    // Z[k] = u + i w, Z[P-k] = conj u + i conj w for k <= P/2; the DC and
+    // Nyquist bins of a real signal are real.
+    {
+        const int ru = slot == 1 ? rb : ra, rw = slot == 0 ? ra : rb;
+        const bool vu = slot == 1 ? vb : va, vw = slot == 0 ? va : vb;
+        const int cu = slot == 2 ? 2 : 0, cw = slot == 2 ? 2 : 1;
+        const long long bu = vu ? row_base(a, ru) : 0, bw = vw ? row_base(a, rw) : 0;
 #pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                A[s].y = 0.f;
-                B[s].y = 0.f;
+        for (int m = 0; m < MH; ++m) {
+            const int k = t + TPF * m;
+            if (2 * k > P) continue;
+            cf u = vu ? a.spec[bu + (long long)k * a.colstride + cu] : mkc(0.f, 0.f);
+            cf w = vw ? a.spec[bw + (long long)k * a.colstride + cw] : mkc(0.f, 0.f);
+            if (k == 0 || 2 * k == P) {
+                u.y = 0.f;
+                w.y = 0.f;
             }
-        }
-        cf* s0 = lds + (3 * p) * SEQ;
-        const cf u[3] = {A[0], B[0], A[2]};
-        const cf v[3] = {A[1], B[1], B[2]};
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            s0[s * SEQ + lds_pad(k)] = mkc(u[s].x - v[s].y, u[s].y + v[s].x);
-            if (!edge) s0[s * SEQ + lds_pad(P - k)] = mkc(u[s].x + v[s].y, v[s].x - u[s].y);
+            buf[lds_pad(k)] = mkc(u.x - w.y, u.y + w.x);
+            if (k != 0 && 2 * k != P) buf[lds_pad(P - k)] = mkc(u.x + w.y, w.x - u.y);
         }
     }
     __syncthreads();
-    Fft<P, 1, F, NT, true>::run(lds, a.tw, a.twshift, tid);
+    cf v[1][PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) v[0][m] = buf[lds_pad(t + TPF * m)];
+    RegFft<P, TPF, 1, true>::run(v, buf, a.tw, a.twshift, t);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
+    __syncthreads();
 
+    // per-cell epilogue over the 2 GI rows of this workgroup
     EpiAcc acc;
     epi_init(acc);
     const float* mp = a.sd.nk > 0 ? a.ms : a.m0;
-    for (int idx = tid; idx < H * a.nx; idx += NT) {
+    for (int idx = tid; idx < 2 * GI * a.nx; idx += NTH) {
         const int rr = idx / a.nx, x = idx - rr * a.nx;
-        const int row = row0 + rr;
+        const int row = 2 * pair0 + rr;
         if (row >= a.nrows) continue;
-        const cf* s0 = lds + (3 * (rr >> 1)) * SEQ;
-        const cf v = s0[(rr & 1) * SEQ + lds_pad(x)];
-        const cf w = s0[2 * SEQ + lds_pad(x)];
-        const float3 bd = make_float3(v.x, v.y, (rr & 1) ? w.y : w.x);
+        const cf* b3 = lds + (rr >> 1) * 3 * SEQ;
+        const cf v01 = b3[(rr & 1) * SEQ + lds_pad(x)];
+        const cf v2 = b3[2 * SEQ + lds_pad(x)];
         const int z = row / a.ny, y = row - z * a.ny;
-        epilogue(a, mp, (long long)row * a.nx + x, x, y, z, bd, acc);
+        epilogue(a, mp, (long long)row * a.nx + x, x, y, z, make_float3(v01.x, v01.y, (rr & 1) ? v2.y : v2.x),
+                 acc);
     }
-    if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce(a, acc, red, blk);
+    if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NTH>(a, acc, red, blk);
 }
 
 // ---------------------------------------------------------------------------
 // Launch helpers: dispatch the run-time padded length to a template instance.
 
 template <int P>
+static int xf_blocks(int nrows) {
+    const int npairs = (nrows + 1) / 2;
+    return 3 * ((npairs + XfCfg<P>::G - 1) / XfCfg<P>::G);
+}
+
+template <int P>
+static int xi_blocks(int nrows) {
+    const int npairs = (nrows + 1) / 2;
+    return (npairs + XiCfg<P>::GI - 1) / XiCfg<P>::GI;
+}
+
+template <int P>
 static hipError_t xfwd_p(const FieldArgs& a, hipStream_t s) {
-    constexpr int H = rows_per_wg(P);
-    const size_t lds = (size_t)(3 * H / 2) * seq_len(P) * sizeof(cf);
-    const int nb = (a.nrows + H - 1) / H;
-    hipFuncSetAttribute((const void*)k_xfwd<P, H>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_xfwd<P, H>), dim3(nb), dim3(NT), lds, s, a);
+    const size_t lds = (size_t)XfCfg<P>::G * seq_len(P) * sizeof(cf);
+    (void)hipFuncSetAttribute((const void*)k_xfwd<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_xfwd<P>), dim3(xf_blocks<P>(a.nrows)), dim3(XfCfg<P>::NTH), lds, s, a);
     return hipGetLastError();
 }
 
 template <int P>
 static hipError_t xinv_p(const FieldArgs& a, hipStream_t s, int* nb_out) {
-    constexpr int H = rows_per_wg(P);
-    const size_t lds = (size_t)(3 * H / 2) * seq_len(P) * sizeof(cf);
-    const int nb = (a.nrows + H - 1) / H;
+    const size_t lds = (size_t)XiCfg<P>::GI * 3 * seq_len(P) * sizeof(cf);
+    const int nb = xi_blocks<P>(a.nrows);
     if (nb_out) *nb_out = nb;
-    hipFuncSetAttribute((const void*)k_xinv<P, H>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_xinv<P, H>), dim3(nb), dim3(NT), lds, s, a);
+    (void)hipFuncSetAttribute((const void*)k_xinv<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_xinv<P>), dim3(nb), dim3(XiCfg<P>::NTH), lds, s, a);
     return hipGetLastError();
 }
 
-template <int P, int MODE, int NC>
+template <int P, int MODE, int NC, bool CFAST>
 static hipError_t col_p(const ColArgs& a, hipStream_t s) {
-    constexpr int T = cols_per_wg(P);
-    const size_t lds = (size_t)(3 * T) * seq_len(P) * sizeof(cf);
-    const int ntile = (a.ncolx + T - 1) / T;
-    const long long nb = (long long)ntile * a.nouter;
-    hipFuncSetAttribute((const void*)k_col<P, T, MODE, NC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    const size_t lds = (size_t)ColCfg<P>::T * 3 * seq_len(P) * sizeof(cf);
+    const long long nb = (long long)((a.ncol + ColCfg<P>::T - 1) / ColCfg<P>::T) * a.nouter;
+    (void)hipFuncSetAttribute((const void*)k_col<P, MODE, NC, CFAST>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
-    hipLaunchKernelGGL((k_col<P, T, MODE, NC>), dim3((unsigned)nb), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((k_col<P, MODE, NC, CFAST>), dim3((unsigned)nb), dim3(ColCfg<P>::NTH), lds, s, a);
     return hipGetLastError();
 }
+
+#define MM_CASES(M) M(1) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048) M(4096)
 
 int xinv_blocks(int px, int nrows) {
-    int H = 16;
-    if (px >= 2048) H = 2;
-    else if (px >= 256) H = 4096 / px;
-    return (nrows + H - 1) / H;
+    switch (px) {
+#define M(p) \
+    case p:  \
+        return xi_blocks<p>(nrows);
+        MM_CASES(M)
+#undef M
+        default:
+            return 0;
+    }
 }
-
-#define MM_CASES(M)                                                                        \
-    M(1) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048) M(4096)
 
 hipError_t launch_xfwd(int px, const FieldArgs& a, hipStream_t s) {
     switch (px) {
@@ -321,7 +451,7 @@ hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t 
         switch (p) {
 #define M(q) \
     case q:  \
-        return col_p<q, COL_FWD, 4>(a, s);
+        return col_p<q, COL_FWD, 4, false>(a, s);
             MM_CASES(M)
 #undef M
             default:
@@ -332,7 +462,7 @@ hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t 
         switch (p) {
 #define M(q) \
     case q:  \
-        return col_p<q, COL_INV, 4>(a, s);
+        return col_p<q, COL_INV, 4, false>(a, s);
             MM_CASES(M)
 #undef M
             default:
@@ -343,7 +473,7 @@ hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t 
         switch (p) {
 #define M(q) \
     case q:  \
-        return col_p<q, COL_CONV, 4>(a, s);
+        return col_p<q, COL_CONV, 4, false>(a, s);
             MM_CASES(M)
 #undef M
             default:
@@ -353,7 +483,7 @@ hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t 
     switch (p) {
 #define M(q) \
     case q:  \
-        return col_p<q, COL_CONV, 6>(a, s);
+        return col_p<q, COL_CONV, 6, true>(a, s);
         MM_CASES(M)
 #undef M
         default:

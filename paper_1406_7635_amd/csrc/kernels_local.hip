@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(NT) k_local(const FieldArgs a) {
         const float* mp = a.sd.nk > 0 ? a.ms : a.m0;
         epilogue(a, mp, i, x, y, z, make_float3(0.f, 0.f, 0.f), acc);
     }
-    if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce(a, acc, red, blockIdx.x);
+    if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NT>(a, acc, red, blockIdx.x);
 }
 
 hipError_t launch_local(const FieldArgs& a, hipStream_t s, int* nblocks_out) {

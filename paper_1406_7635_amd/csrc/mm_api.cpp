@@ -101,7 +101,7 @@ struct mm_ctx {
     int nx = 0, ny = 0, nz = 0, nrows = 0;
     double dx = 0, dy = 0, dz = 0;
     int px = 1, py = 1, pz = 1, kx = 1, ncomp = 4;
-    long long ncell = 0, rowstride = 0, zstride = 0, spec_elems = 0, khat_elems = 0;
+    long long ncell = 0, colstride = 0, zstride = 0, spec_elems = 0, khat_elems = 0;
     int pt = 1, twshift = 0;
     bool demag_on = true, khat_ready = false;
     uint8_t* region = nullptr;
@@ -136,12 +136,12 @@ void free_all(mm_ctx* c) {
     void* ptrs[] = {c->region, c->params64, c->lut, c->ptab, c->tw, c->spec,
                     c->khat,   c->kbuf,     c->ms,  c->st,   c->partials};
     for (void* p : ptrs)
-        if (p) hipFree(p);
-    if (c->hst) hipHostFree(c->hst);
+        if (p) (void)hipFree(p);
+    if (c->hst) (void)hipHostFree(c->hst);
     for (auto& t : c->timing)
         for (auto& pr : t.ev) {
-            hipEventDestroy(pr.first);
-            hipEventDestroy(pr.second);
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
         }
 }
 
@@ -165,7 +165,7 @@ FieldArgs base_args(mm_ctx* c, const float* m0) {
     a.st = c->st;
     a.sd.out_k = -1;
     a.spec = c->spec;
-    a.rowstride = c->rowstride;
+    a.colstride = c->colstride;
     a.zstride = c->zstride;
     a.tw = c->tw;
     a.twshift = c->twshift;
@@ -180,14 +180,14 @@ struct Timed {
     hipEvent_t e1 = nullptr, e2 = nullptr;
     Timed(mm_ctx* c_, int w) : c(c_), which(w) {
         if (c->timing[which].enabled) {
-            hipEventCreate(&e1);
-            hipEventCreate(&e2);
-            hipEventRecord(e1, c->stream);
+            (void)hipEventCreate(&e1);
+            (void)hipEventCreate(&e2);
+            (void)hipEventRecord(e1, c->stream);
         }
     }
     ~Timed() {
         if (e1) {
-            hipEventRecord(e2, c->stream);
+            (void)hipEventRecord(e2, c->stream);
             c->timing[which].ev.emplace_back(e1, e2);
         }
     }
@@ -206,49 +206,58 @@ int run_field(mm_ctx* c, FieldArgs& a, int* nblocks_out) {
         ColArgs ca;
         memset(&ca, 0, sizeof(ca));
         ca.spec = c->spec;
-        ca.ncolx = c->kx;
         ca.tw = c->tw;
         ca.twshift = c->twshift;
         ca.st = c->st;
         ca.check_done = (a.flags & EPI_CHECK_DONE) ? 1 : 0;
         ca.khat = c->khat;
+        ca.kyh = c->py / 2 + 1;
+        ca.kzh = c->pz / 2 + 1;
+        ca.pa = c->py;
         {
             Timed t(c, 1);
             if (c->pz > 1) {
+                // y transforms of every (z, kx) column, in place (ny rows -> py rows)
+                ca.pos_stride = 3;
+                ca.col_stride = c->colstride;
+                ca.ncol = c->kx;
+                ca.outer_stride = c->zstride;
+                ca.nouter = c->nz;
                 if (c->py > 1) {
                     ca.n_in = c->ny;
                     ca.n_out = c->py;
-                    ca.stride = c->rowstride;
-                    ca.nouter = c->nz;
-                    ca.outer_stride = c->zstride;
-                    ca.pa = 1;
                     MM_TRY(launch_col(c->py, COL_FWD, ca, 6, s));
                 }
+                // z convolution of every (kx, ky) column; tiles of adjacent ky
+                ca.pos_stride = c->zstride;
+                ca.col_stride = 3;
+                ca.ncol = c->py;
+                ca.outer_stride = c->colstride;
+                ca.nouter = c->kx;
                 ca.n_in = c->nz;
                 ca.n_out = c->nz;
-                ca.stride = c->zstride;
-                ca.nouter = c->py;
-                ca.outer_stride = c->rowstride;
-                ca.pa = c->py;
-                ca.khq = c->pz / 2 + 1;
                 MM_TRY(launch_col(c->pz, COL_CONV, ca, 6, s));
                 if (c->py > 1) {
+                    ca.pos_stride = 3;
+                    ca.col_stride = c->colstride;
+                    ca.ncol = c->kx;
+                    ca.outer_stride = c->zstride;
+                    ca.nouter = c->nz;
                     ca.n_in = c->py;
                     ca.n_out = c->ny;
-                    ca.stride = c->rowstride;
-                    ca.nouter = c->nz;
-                    ca.outer_stride = c->zstride;
-                    ca.pa = 1;
                     MM_TRY(launch_col(c->py, COL_INV, ca, 6, s));
                 }
             } else {
+                // 2D: y convolution of every kx column; the DC and Nyquist columns
+                // (both real along y) share the first workgroup
+                ca.pos_stride = 3;
+                ca.col_stride = c->colstride;
+                ca.ncol = c->px >= 2 ? c->px / 2 : 1;
+                ca.pack_col = c->px >= 2 ? c->px / 2 : 0;
+                ca.outer_stride = 0;
+                ca.nouter = 1;
                 ca.n_in = c->ny;
                 ca.n_out = c->ny;
-                ca.stride = c->rowstride;
-                ca.nouter = 1;
-                ca.outer_stride = 0;
-                ca.pa = 1;
-                ca.khq = c->py / 2 + 1;
                 MM_TRY(launch_col(c->py, COL_CONV, ca, 4, s));
             }
         }
@@ -413,7 +422,7 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
     mm_ctx* c = new (std::nothrow) mm_ctx();
     if (!c) return MM_ENOMEM;
     c->stream = (hipStream_t)hip_stream;
-    hipGetDevice(&c->device);
+    (void)hipGetDevice(&c->device);
     c->nx = g->nx;
     c->ny = g->ny;
     c->nz = g->nz;
@@ -431,9 +440,9 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
     }
     c->kx = c->px / 2 + 1;
     c->ncomp = (c->pz > 1) ? 6 : 4;
-    c->rowstride = 3LL * c->kx;
-    const long long zrows = (c->pz > 1) ? c->py : c->ny;
-    c->zstride = zrows * c->rowstride;
+    const long long ycount = (c->pz > 1) ? c->py : c->ny;
+    c->colstride = 3LL * ycount;
+    c->zstride = (long long)c->kx * c->colstride;
     c->spec_elems = c->zstride * c->nz;
     c->khat_elems = (long long)c->kx * (c->py / 2 + 1) * (c->pz / 2 + 1) * c->ncomp;
     c->pt = c->px;
@@ -494,8 +503,8 @@ int mm_demag_kernel_init(mm_ctx* c) {
         e = demag_kernel_spectrum(c->nx, c->ny, c->nz, c->px, c->py, c->pz, oct, work, c->khat, c->ncomp,
                                   c->kx, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (oct) hipFree(oct);
-    if (work) hipFree(work);
+    if (oct) (void)hipFree(oct);
+    if (work) (void)hipFree(work);
     if (e != hipSuccess) return map_err(e);
     c->khat_ready = true;
     c->fsal_valid = false;
@@ -755,8 +764,8 @@ int mm_timing_enable(mm_ctx* c, int32_t which, int32_t enable) {
     TimingClass& t = c->timing[which];
     MM_TRY(hipStreamSynchronize(c->stream));
     for (auto& pr : t.ev) {
-        hipEventDestroy(pr.first);
-        hipEventDestroy(pr.second);
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
     }
     t.ev.clear();
     t.enabled = enable != 0;
@@ -779,7 +788,7 @@ int mm_timing_read(mm_ctx* c, int32_t which, int64_t* launches, double* total_ms
 
 void mm_destroy(mm_ctx* c) {
     if (!c) return;
-    hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     free_all(c);
     delete c;
 }

@@ -71,8 +71,8 @@ struct FieldArgs {
     float* kbuf;                  // [MAXK][3][ncell]
     DevState* st;
     StageDesc sd;
-    cf* spec;                     // interleaved spectrum, 3 complex per (row, kx)
-    long long rowstride, zstride; // in complex elements
+    cf* spec;                     // spectrum, element (z, kx, y, c) at z*zstride + kx*colstride + 3y + c
+    long long colstride, zstride; // in complex elements
     const cf* tw;                 // exp(-2 pi i m / PT)
     int twshift;                  // log2 PT
     float* beff;
@@ -85,14 +85,16 @@ struct FieldArgs {
 
 struct ColArgs {
     cf* spec;
-    int n_in, n_out;              // non-zero input length, kept output length
-    long long stride;             // complex elements between consecutive positions
-    int ncolx;                    // spectral columns kx
-    long long outer_stride;       // between outer columns (z slab or ky row)
+    int n_in, n_out;              // non-zero input length, kept output length along the transform
+    long long pos_stride;         // complex elements between consecutive transform positions
+    long long col_stride;         // between adjacent columns of a workgroup tile
+    int ncol;                     // columns along the tile direction
+    long long outer_stride;       // between outer indices
     int nouter;
-    int pa;                       // padded length of the outer axis (1 in 2D)
-    const float* khat;            // conv only
-    int khq;                      // folded conv-axis length p/2 + 1
+    int pa;                       // 3D convolution: padded y length (ky folding)
+    const float* khat;            // convolution only: [kx][ky_h][kz_h][ncomp]
+    int kyh, kzh;                 // folded lengths py/2+1, pz/2+1
+    int pack_col;                 // 2D convolution: > 0 when column 0 also carries kx = pack_col (Nyquist)
     const cf* tw;
     int twshift;
     const DevState* st;

@@ -11,7 +11,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmm.so")
+LIB_PATH = os.environ.get("MM_LIBRARY") or os.path.join(_HERE, "libmm.so")
 NREG = 256
 NPAIR = NREG * (NREG + 1) // 2
 

@@ -88,12 +88,9 @@ def test_kernel_spectrum_matches_padded_dft(gpu):
         assert np.max(np.abs(Kh.imag)) < 1e-9 * np.max(np.abs(Kh.real))
         got = to_np(ctx.kernel_dump())
         kyh, kzh, kx = py // 2 + 1, pz // 2 + 1, px // 2 + 1
-        if info["ncomp"] == 4:
-            g = got.reshape(kx, kyh, 4)
-            ref = np.stack([Kh[c, 0, :kyh, :kx].real.T for c in (0, 1, 2, 3)], axis=-1)
-        else:
-            g = got.reshape(kyh, kx, kzh, 6)
-            ref = np.stack([np.transpose(Kh[c, :kzh, :kyh, :kx].real, (1, 2, 0)) for c in range(6)], axis=-1)
+        nc = info["ncomp"]
+        g = got.reshape(kx, kyh, kzh, nc)
+        ref = np.stack([np.transpose(Kh[c, :kzh, :kyh, :kx].real, (2, 1, 0)) for c in range(nc)], axis=-1)
         assert np.max(np.abs(g - ref)) < 2e-7 * np.max(np.abs(ref))
 
 
