@@ -12,7 +12,7 @@
 
 namespace mm {
 
-struct cf {
+struct alignas(8) cf {
     float x, y;
 };
 

@@ -34,43 +34,89 @@ __device__ inline int pair_index(int a, int b) {
     return hi * (hi + 1) / 2 + lo;
 }
 
-__device__ inline float* kslot(const FieldArgs& a, int logical) {
-    return a.kbuf + (long long)a.st->perm[logical] * 3 * a.ncell;
+// Stage-derivative pointers and dt, read once per kernel from the device-side
+// solver state (the logical-to-physical buffer map changes on the device when
+// a step is accepted).  Reading them up front keeps the per-cell loops free of
+// dependent state loads.
+struct Resolved {
+    const float* kin[6];  // stage-combine inputs, kin[j] for j < sd.nk
+    float* kout;          // where the torque goes (a k buffer or the caller's tau)
+    const float* ke[7];   // error-norm inputs (null: the torque just computed)
+    float dt;
+};
+
+__device__ inline Resolved resolve(const FieldArgs& a) {
+    Resolved r;
+    const long long n3 = 3 * a.ncell;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+        r.kin[j] = j < a.sd.nk ? a.kbuf + (long long)a.st->perm[a.sd.kidx[j]] * n3 : nullptr;
+    r.kout = a.sd.out_k >= 0 ? a.kbuf + (long long)a.st->perm[a.sd.out_k] * n3 : a.tau;
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+        r.ke[j] = (j < a.sd.nerr && a.sd.eidx[j] != a.sd.out_k)
+                      ? a.kbuf + (long long)a.st->perm[a.sd.eidx[j]] * n3
+                      : nullptr;
+    r.dt = (float)a.st->dt;
+    return r;
 }
 
-// Stage state m_s = m0 + dt sum_j a_j k_j of one cell (FP32).
-__device__ inline float3 stage_state(const FieldArgs& a, long long cell, float dt) {
-    float3 m = ld3(a.m0, a.ncell, cell);
-    if (a.sd.nk > 0) {
-        float3 acc = make_float3(0.f, 0.f, 0.f);
-        for (int j = 0; j < a.sd.nk; ++j) {
-            float3 k = ld3(kslot(a, a.sd.kidx[j]), a.ncell, cell);
-            acc = f3add(acc, f3scale(a.sd.a[j], k));
-        }
-        m = f3add(m, f3scale(dt, acc));
-    }
-    return m;
+// Component c of the stage state m_s = m0 + dt sum_j a_j k_j of one cell (FP32).
+// All terms are loaded before any is used so their latencies overlap.
+__device__ inline float stage_comp(const FieldArgs& a, const Resolved& r, long long idx) {
+    const float m0 = a.m0[idx];
+    if (a.sd.nk == 0) return m0;
+    float kv[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) kv[j] = j < a.sd.nk ? r.kin[j][idx] : 0.f;
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc += a.sd.a[j] * kv[j];
+    return m0 + r.dt * acc;
 }
 
-// Exchange field at (x, y, z) from the state array mp.
+__device__ inline float3 stage_state(const FieldArgs& a, const Resolved& r, long long cell) {
+    const long long n = a.ncell;
+    return make_float3(stage_comp(a, r, cell), stage_comp(a, r, n + cell), stage_comp(a, r, 2 * n + cell));
+}
+
+// Exchange field at (x, y, z) from the state array mp.  A neighbour outside
+// the grid is replaced by the cell itself (the Neumann rule), which adds
+// c (m - m) = 0; so every neighbour is loaded without a branch.
 __device__ inline float3 exchange_at(const FieldArgs& a, const float* __restrict__ mp, long long cell,
                                      int x, int y, int z, int r, float3 mc) {
-    float3 b = make_float3(0.f, 0.f, 0.f);
     const long long n = a.ncell;
     const long long sxy = (long long)a.nx * a.ny;
-#define MM_NB(cond, off, id2)                                               \
-    if (cond) {                                                            \
-        const long long nc = cell + (off);                                 \
-        const float c = a.ptab[pair_index(r, a.region[nc])] * (id2);       \
-        b = f3add(b, f3scale(c, f3sub(ld3(mp, n, nc), mc)));               \
+    long long nb[6];
+    float id2[6];
+    int cnt = 2;
+    nb[0] = x > 0 ? cell - 1 : cell;
+    nb[1] = x < a.nx - 1 ? cell + 1 : cell;
+    id2[0] = id2[1] = a.idx2;
+    if (a.ny > 1) {
+        nb[cnt] = y > 0 ? cell - a.nx : cell;
+        nb[cnt + 1] = y < a.ny - 1 ? cell + a.nx : cell;
+        id2[cnt] = id2[cnt + 1] = a.idy2;
+        cnt += 2;
     }
-    MM_NB(x > 0, -1, a.idx2)
-    MM_NB(x < a.nx - 1, 1, a.idx2)
-    MM_NB(y > 0, -(long long)a.nx, a.idy2)
-    MM_NB(y < a.ny - 1, (long long)a.nx, a.idy2)
-    MM_NB(z > 0, -sxy, a.idz2)
-    MM_NB(z < a.nz - 1, sxy, a.idz2)
-#undef MM_NB
+    if (a.nz > 1) {
+        nb[cnt] = z > 0 ? cell - sxy : cell;
+        nb[cnt + 1] = z < a.nz - 1 ? cell + sxy : cell;
+        id2[cnt] = id2[cnt + 1] = a.idz2;
+        cnt += 2;
+    }
+    int rn[6];
+    float3 mn[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        if (i < cnt) {
+            rn[i] = a.region[nb[i]];
+            mn[i] = ld3(mp, n, nb[i]);
+        }
+    float3 b = make_float3(0.f, 0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        if (i < cnt) b = f3add(b, f3scale(a.ptab[pair_index(r, rn[i])] * id2[i], f3sub(mn[i], mc)));
     return b;
 }
 
@@ -88,8 +134,8 @@ __device__ inline void epi_init(EpiAcc& acc) {
 }
 
 // Everything after the magnetostatic field for one cell.
-__device__ inline void epilogue(const FieldArgs& a, const float* __restrict__ mp, long long cell,
-                                int x, int y, int z, float3 bd, EpiAcc& acc) {
+__device__ inline void epilogue(const FieldArgs& a, const Resolved& rs, const float* __restrict__ mp,
+                                long long cell, int x, int y, int z, float3 bd, EpiAcc& acc) {
     const int flags = a.flags;
     const int r = a.region[cell];
     const RegionLut L = a.lut[r];
@@ -98,7 +144,7 @@ __device__ inline void epilogue(const FieldArgs& a, const float* __restrict__ mp
     float3 tq = make_float3(0.f, 0.f, 0.f);
     if (L.a.x == 0.f) {  // non-magnetic cell: no field, no torque
         if (flags & EPI_BEFF) st3(a.beff, n, cell, tq);
-        if (flags & EPI_TORQUE) st3(a.sd.out_k >= 0 ? kslot(a, a.sd.out_k) : a.tau, n, cell, tq);
+        if (flags & EPI_TORQUE) st3(rs.kout, n, cell, tq);
         return;
     }
     const float3 m = ld3(mp, n, cell);
@@ -116,14 +162,17 @@ __device__ inline void epilogue(const FieldArgs& a, const float* __restrict__ mp
         const float alpha = L.a.w;
         tq = (flags & EPI_PRECESS) ? f3scale(L.b.w, f3add(mxb, f3scale(alpha, mxmxb)))
                                    : f3scale(L.b.w * alpha, mxmxb);
-        if (flags & EPI_TORQUE) st3(a.sd.out_k >= 0 ? kslot(a, a.sd.out_k) : a.tau, n, cell, tq);
+        if (flags & EPI_TORQUE) st3(rs.kout, n, cell, tq);
         if (flags & EPI_MAXTQ) acc.tqmax = fmaxf(acc.tqmax, sqrtf(f3dot(tq, tq)));
         if (flags & EPI_ERR) {
+            float3 kv[7];
+#pragma unroll
+            for (int j = 0; j < 7; ++j)
+                if (j < a.sd.nerr) kv[j] = rs.ke[j] ? ld3(rs.ke[j], n, cell) : tq;
             float3 d = make_float3(0.f, 0.f, 0.f);
-            for (int j = 0; j < a.sd.nerr; ++j) {
-                const float3 k = (a.sd.eidx[j] == a.sd.out_k) ? tq : ld3(kslot(a, a.sd.eidx[j]), n, cell);
-                d = f3add(d, f3scale(a.sd.e[j], k));
-            }
+#pragma unroll
+            for (int j = 0; j < 7; ++j)
+                if (j < a.sd.nerr) d = f3add(d, f3scale(a.sd.e[j], kv[j]));
             acc.errmax = fmaxf(acc.errmax, sqrtf(f3dot(d, d)));
         }
     }

@@ -39,18 +39,16 @@ struct Cfg {
     static constexpr int G = TPF >= 256 ? 1 : 256 / TPF;          // sequences per 256 threads
 };
 
-// x-forward: G row pairs of one slot per workgroup
+// x passes: the 3 slots of GI row pairs per workgroup.  GL = LDS elements per
+// row pair: the three exchange sequences, reused afterwards as the staging
+// area [kx][row][component] through which the spectrum is written / read in
+// contiguous runs (rows a, b are adjacent in the spectrum when a is even).
 template <int P>
-struct XfCfg {
-    static constexpr int G = Cfg<P>::G;
-    static constexpr int NTH = G * Cfg<P>::TPF;
-};
-
-// x-inverse: the 3 slots of GI row pairs per workgroup
-template <int P>
-struct XiCfg {
+struct XCfg {
     static constexpr int GI = Cfg<P>::TPF >= 256 ? 1 : (Cfg<P>::TPF >= 128 ? 2 : 256 / Cfg<P>::TPF);
     static constexpr int NTH = 3 * GI * Cfg<P>::TPF;
+    static constexpr int KH = P / 2 + 1;
+    static constexpr int GL = 3 * seq_len(P) > 6 * KH ? 3 * seq_len(P) : 6 * KH;
 };
 
 // columns: the 3 components of T columns per workgroup
@@ -67,21 +65,22 @@ __device__ inline long long row_base(const FieldArgs& a, int row) {
 
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ void __launch_bounds__(XfCfg<P>::NTH) k_xfwd(const FieldArgs a) {
-    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, G = XfCfg<P>::G;
-    constexpr int SEQ = seq_len(P);
+__global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
+    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI, NTH = XCfg<P>::NTH;
+    constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL, KH = XCfg<P>::KH;
     constexpr int MH = PPT / 2 + 1;
     extern __shared__ cf lds[];
     if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
     const int tid = threadIdx.x;
-    const int g = tid / TPF, t = tid - g * TPF;
+    const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int slot = blk % 3;
-    const int pair = (blk / 3) * G + g;
+    const int pair0 = blk * GI;
+    const int pair = pair0 + g;
     const int ra = 2 * pair, rb = ra + 1;
     const bool va = ra < a.nrows, vb = rb < a.nrows;
-    const float dt = (float)a.st->dt;
-    cf* buf = lds + g * SEQ;
+    const Resolved rs = resolve(a);
+    cf* gbuf = lds + g * GL;
+    cf* buf = gbuf + slot * SEQ;
     const long long n = a.ncell;
 
     // slot 0: (x, y) of row a, slot 1: (x, y) of row b, slot 2: z of rows a and b
@@ -92,35 +91,37 @@ __global__ void __launch_bounds__(XfCfg<P>::NTH) k_xfwd(const FieldArgs a) {
     const bool v1 = slot == 0 ? va : vb;
     const int c1 = slot == 2 ? 2 : 1;
 
+    // Only x < P/2 can hold cells (P >= 2 nx - 1); rows and columns past the
+    // grid are clamped for the loads and masked afterwards, so every load of
+    // the thread is issued before the first one is used.
+    constexpr int MV = PPT > 1 ? PPT / 2 : 1;
+    const int r0c = v0 ? r0 : 0, r1c = v1 ? r1 : 0;
     cf v[1][PPT];
 #pragma unroll
-    for (int m = 0; m < PPT; ++m) {
+    for (int m = MV; m < PPT; ++m) v[0][m] = mkc(0.f, 0.f);
+    float s0[MV], s1[MV];
+    int g0[MV], g1[MV];
+#pragma unroll
+    for (int m = 0; m < MV; ++m) {
         const int x = t + TPF * m;
-        float re = 0.f, im = 0.f;
-        if (x < a.nx) {
-            if (v0) {
-                const long long cell = (long long)r0 * a.nx + x;
-                float s = a.m0[c0 * n + cell];
-                if (a.sd.nk > 0) {
-                    float acc = 0.f;
-                    for (int j = 0; j < a.sd.nk; ++j) acc += a.sd.a[j] * kslot(a, a.sd.kidx[j])[c0 * n + cell];
-                    s += dt * acc;
-                    a.ms[c0 * n + cell] = s;
-                }
-                re = a.lut[a.region[cell]].a.x * s;
-            }
-            if (v1) {
-                const long long cell = (long long)r1 * a.nx + x;
-                float s = a.m0[c1 * n + cell];
-                if (a.sd.nk > 0) {
-                    float acc = 0.f;
-                    for (int j = 0; j < a.sd.nk; ++j) acc += a.sd.a[j] * kslot(a, a.sd.kidx[j])[c1 * n + cell];
-                    s += dt * acc;
-                    a.ms[c1 * n + cell] = s;
-                }
-                im = a.lut[a.region[cell]].a.x * s;
-            }
+        const int xc = x < a.nx ? x : a.nx - 1;
+        const long long cell0 = (long long)r0c * a.nx + xc, cell1 = (long long)r1c * a.nx + xc;
+        s0[m] = stage_comp(a, rs, c0 * n + cell0);
+        s1[m] = stage_comp(a, rs, c1 * n + cell1);
+        g0[m] = a.region[cell0];
+        g1[m] = a.region[cell1];
+    }
+#pragma unroll
+    for (int m = 0; m < MV; ++m) {
+        const int x = t + TPF * m;
+        const bool in = x < a.nx;
+        const long long cell0 = (long long)r0c * a.nx + x, cell1 = (long long)r1c * a.nx + x;
+        if (a.sd.nk > 0) {
+            if (in && v0) a.ms[c0 * n + cell0] = s0[m];
+            if (in && v1) a.ms[c1 * n + cell1] = s1[m];
         }
+        const float re = (in && v0) ? a.lut[g0[m]].a.x * s0[m] : 0.f;
+        const float im = (in && v1) ? a.lut[g1[m]].a.x * s1[m] : 0.f;
         v[0][m] = mkc(re, im);
     }
     RegFft<P, TPF, 1, false>::run(v, buf, a.tw, a.twshift, t);
@@ -130,25 +131,37 @@ __global__ void __launch_bounds__(XfCfg<P>::NTH) k_xfwd(const FieldArgs a) {
 #pragma unroll
     for (int m = 0; m < PPT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
     __syncthreads();
-    const long long b0 = v0 ? row_base(a, r0) : 0, b1 = v1 ? row_base(a, r1) : 0;
+    cf X[MH], Y[MH];
+#pragma unroll
+    for (int m = 0; m < MH; ++m) {
+        const int k = t + TPF * m;
+        const cf z = v[0][m < PPT ? m : 0];
+        const cf w = cconj(buf[lds_pad((P - k) & (P - 1))]);
+        const cf d = z - w;
+        X[m] = 0.5f * (z + w);
+        Y[m] = mkc(0.5f * d.y, -0.5f * d.x);
+    }
+    __syncthreads();
+    // stage [kx][row][component] and write the runs of 6 complex per kx
 #pragma unroll
     for (int m = 0; m < MH; ++m) {
         const int k = t + TPF * m;
         if (2 * k > P) continue;
-        const cf z = v[0][m < PPT ? m : 0];
-        const cf w = cconj(buf[lds_pad((P - k) & (P - 1))]);
-        const cf d = z - w;
-        const cf X = 0.5f * (z + w);
-        const cf Y = mkc(0.5f * d.y, -0.5f * d.x);
-        const long long off = (long long)k * a.colstride;
         if (slot == 2) {
-            if (v0) a.spec[b0 + off + 2] = X;
-            if (v1) a.spec[b1 + off + 2] = Y;
-        } else if (v0) {
-            cf* dst = a.spec + b0 + off;
-            dst[0] = X;
-            dst[1] = Y;
+            gbuf[k * 6 + 2] = X[m];
+            gbuf[k * 6 + 5] = Y[m];
+        } else {
+            gbuf[k * 6 + slot * 3] = X[m];
+            gbuf[k * 6 + slot * 3 + 1] = Y[m];
         }
+    }
+    __syncthreads();
+    for (int u = tid; u < GI * KH * 6; u += NTH) {
+        const int gg = u / (KH * 6), rem = u - gg * (KH * 6);
+        const int k = rem / 6, rc = rem - 6 * k;
+        const int row = 2 * (pair0 + gg) + (rc >= 3 ? 1 : 0);
+        if (row < a.nrows)
+            a.spec[row_base(a, row) + (long long)k * a.colstride + (rc >= 3 ? rc - 3 : rc)] = lds[gg * GL + rem];
     }
 }
 
@@ -297,9 +310,9 @@ __global__ void __launch_bounds__(ColCfg<P>::NTH) k_col(const ColArgs a) {
 
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ void __launch_bounds__(XiCfg<P>::NTH) k_xinv(const FieldArgs a) {
-    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XiCfg<P>::GI, NTH = XiCfg<P>::NTH;
-    constexpr int SEQ = seq_len(P);
+__global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
+    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI, NTH = XCfg<P>::NTH;
+    constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL, KH = XCfg<P>::KH;
     constexpr int MH = PPT / 2 + 1;
     extern __shared__ cf lds[];
     __shared__ double red[(NTH / 64 > 0 ? NTH / 64 : 1) * 6];
@@ -308,34 +321,43 @@ __global__ void __launch_bounds__(XiCfg<P>::NTH) k_xinv(const FieldArgs a) {
     const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int pair0 = blk * GI;
-    const int pair = pair0 + g;
-    const int ra = 2 * pair, rb = ra + 1;
-    const bool va = ra < a.nrows, vb = rb < a.nrows;
-    cf* bufs = lds + g * 3 * SEQ;
-    cf* buf = bufs + slot * SEQ;
+    cf* gbuf = lds + g * GL;
+    cf* buf = gbuf + slot * SEQ;
 
-    // Hermitian extension of this slot u + i w (slot 0: x, y of row a;
-    // slot 1: x, y of row b; slot 2: z of rows a and b) from the half spectra:
-    // Z[k] = u + i w, Z[P-k] = conj u + i conj w for k <= P/2; the DC and
-    // Nyquist bins of a real signal are real.
-    {
-        const int ru = slot == 1 ? rb : ra, rw = slot == 0 ? ra : rb;
-        const bool vu = slot == 1 ? vb : va, vw = slot == 0 ? va : vb;
-        const int cu = slot == 2 ? 2 : 0, cw = slot == 2 ? 2 : 1;
-        const long long bu = vu ? row_base(a, ru) : 0, bw = vw ? row_base(a, rw) : 0;
+    // read the half spectra of the row pairs in contiguous runs into [kx][row][component]
+    for (int u = tid; u < GI * KH * 6; u += NTH) {
+        const int gg = u / (KH * 6), rem = u - gg * (KH * 6);
+        const int k = rem / 6, rc = rem - 6 * k;
+        const int row = 2 * (pair0 + gg) + (rc >= 3 ? 1 : 0);
+        lds[gg * GL + rem] = row < a.nrows
+                                 ? a.spec[row_base(a, row) + (long long)k * a.colstride + (rc >= 3 ? rc - 3 : rc)]
+                                 : mkc(0.f, 0.f);
+    }
+    __syncthreads();
+    // slot s = u + i w (slot 0: x, y of row a; slot 1: x, y of row b; slot 2: z of
+    // rows a and b); the DC and Nyquist bins of a real signal are real
+    const int iu = slot == 2 ? 2 : slot * 3, iw = slot == 2 ? 5 : slot * 3 + 1;
+    cf U[MH], W[MH];
 #pragma unroll
-        for (int m = 0; m < MH; ++m) {
-            const int k = t + TPF * m;
-            if (2 * k > P) continue;
-            cf u = vu ? a.spec[bu + (long long)k * a.colstride + cu] : mkc(0.f, 0.f);
-            cf w = vw ? a.spec[bw + (long long)k * a.colstride + cw] : mkc(0.f, 0.f);
-            if (k == 0 || 2 * k == P) {
-                u.y = 0.f;
-                w.y = 0.f;
-            }
-            buf[lds_pad(k)] = mkc(u.x - w.y, u.y + w.x);
-            if (k != 0 && 2 * k != P) buf[lds_pad(P - k)] = mkc(u.x + w.y, w.x - u.y);
+    for (int m = 0; m < MH; ++m) {
+        const int k = t + TPF * m;
+        const int kc = 2 * k <= P ? k : 0;
+        U[m] = gbuf[kc * 6 + iu];
+        W[m] = gbuf[kc * 6 + iw];
+        if (k == 0 || 2 * k == P) {
+            U[m].y = 0.f;
+            W[m].y = 0.f;
         }
+    }
+    __syncthreads();
+    // Hermitian extension: Z[k] = u + i w, Z[P-k] = conj u + i conj w for k <= P/2
+#pragma unroll
+    for (int m = 0; m < MH; ++m) {
+        const int k = t + TPF * m;
+        if (2 * k > P) continue;
+        const cf u = U[m], w = W[m];
+        buf[lds_pad(k)] = mkc(u.x - w.y, u.y + w.x);
+        if (k != 0 && 2 * k != P) buf[lds_pad(P - k)] = mkc(u.x + w.y, w.x - u.y);
     }
     __syncthreads();
     cf v[1][PPT];
@@ -348,6 +370,7 @@ __global__ void __launch_bounds__(XiCfg<P>::NTH) k_xinv(const FieldArgs a) {
     __syncthreads();
 
     // per-cell epilogue over the 2 GI rows of this workgroup
+    const Resolved rs = resolve(a);
     EpiAcc acc;
     epi_init(acc);
     const float* mp = a.sd.nk > 0 ? a.ms : a.m0;
@@ -355,12 +378,12 @@ __global__ void __launch_bounds__(XiCfg<P>::NTH) k_xinv(const FieldArgs a) {
         const int rr = idx / a.nx, x = idx - rr * a.nx;
         const int row = 2 * pair0 + rr;
         if (row >= a.nrows) continue;
-        const cf* b3 = lds + (rr >> 1) * 3 * SEQ;
+        const cf* b3 = lds + (rr >> 1) * GL;
         const cf v01 = b3[(rr & 1) * SEQ + lds_pad(x)];
         const cf v2 = b3[2 * SEQ + lds_pad(x)];
         const int z = row / a.ny, y = row - z * a.ny;
-        epilogue(a, mp, (long long)row * a.nx + x, x, y, z, make_float3(v01.x, v01.y, (rr & 1) ? v2.y : v2.x),
-                 acc);
+        epilogue(a, rs, mp, (long long)row * a.nx + x, x, y, z,
+                 make_float3(v01.x, v01.y, (rr & 1) ? v2.y : v2.x), acc);
     }
     if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NTH>(a, acc, red, blk);
 }
@@ -369,32 +392,26 @@ __global__ void __launch_bounds__(XiCfg<P>::NTH) k_xinv(const FieldArgs a) {
 // Launch helpers: dispatch the run-time padded length to a template instance.
 
 template <int P>
-static int xf_blocks(int nrows) {
+static int x_blocks(int nrows) {
     const int npairs = (nrows + 1) / 2;
-    return 3 * ((npairs + XfCfg<P>::G - 1) / XfCfg<P>::G);
-}
-
-template <int P>
-static int xi_blocks(int nrows) {
-    const int npairs = (nrows + 1) / 2;
-    return (npairs + XiCfg<P>::GI - 1) / XiCfg<P>::GI;
+    return (npairs + XCfg<P>::GI - 1) / XCfg<P>::GI;
 }
 
 template <int P>
 static hipError_t xfwd_p(const FieldArgs& a, hipStream_t s) {
-    const size_t lds = (size_t)XfCfg<P>::G * seq_len(P) * sizeof(cf);
+    const size_t lds = (size_t)XCfg<P>::GI * XCfg<P>::GL * sizeof(cf);
     (void)hipFuncSetAttribute((const void*)k_xfwd<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_xfwd<P>), dim3(xf_blocks<P>(a.nrows)), dim3(XfCfg<P>::NTH), lds, s, a);
+    hipLaunchKernelGGL((k_xfwd<P>), dim3(x_blocks<P>(a.nrows)), dim3(XCfg<P>::NTH), lds, s, a);
     return hipGetLastError();
 }
 
 template <int P>
 static hipError_t xinv_p(const FieldArgs& a, hipStream_t s, int* nb_out) {
-    const size_t lds = (size_t)XiCfg<P>::GI * 3 * seq_len(P) * sizeof(cf);
-    const int nb = xi_blocks<P>(a.nrows);
+    const size_t lds = (size_t)XCfg<P>::GI * XCfg<P>::GL * sizeof(cf);
+    const int nb = x_blocks<P>(a.nrows);
     if (nb_out) *nb_out = nb;
     (void)hipFuncSetAttribute((const void*)k_xinv<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_xinv<P>), dim3(nb), dim3(XiCfg<P>::NTH), lds, s, a);
+    hipLaunchKernelGGL((k_xinv<P>), dim3(nb), dim3(XCfg<P>::NTH), lds, s, a);
     return hipGetLastError();
 }
 
@@ -414,7 +431,7 @@ int xinv_blocks(int px, int nrows) {
     switch (px) {
 #define M(p) \
     case p:  \
-        return xi_blocks<p>(nrows);
+        return x_blocks<p>(nrows);
         MM_CASES(M)
 #undef M
         default:

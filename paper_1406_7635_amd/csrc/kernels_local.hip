@@ -74,7 +74,8 @@ __global__ void __launch_bounds__(NT) k_combine(const FieldArgs a) {
     if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
     const long long i = (long long)blockIdx.x * NT + threadIdx.x;
     if (i >= a.ncell) return;
-    st3(a.ms, a.ncell, i, stage_state(a, i, (float)a.st->dt));
+    const Resolved rs = resolve(a);
+    st3(a.ms, a.ncell, i, stage_state(a, rs, i));
 }
 
 hipError_t launch_combine(const FieldArgs& a, hipStream_t s) {
@@ -87,6 +88,7 @@ __global__ void __launch_bounds__(NT) k_local(const FieldArgs a) {
     __shared__ double red[(NT / 64) * 6];
     if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
     const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    const Resolved rs = resolve(a);
     EpiAcc acc;
     epi_init(acc);
     if (i < a.ncell) {
@@ -94,7 +96,7 @@ __global__ void __launch_bounds__(NT) k_local(const FieldArgs a) {
         const long long r = i / a.nx;
         const int y = (int)(r % a.ny), z = (int)(r / a.ny);
         const float* mp = a.sd.nk > 0 ? a.ms : a.m0;
-        epilogue(a, mp, i, x, y, z, make_float3(0.f, 0.f, 0.f), acc);
+        epilogue(a, rs, mp, i, x, y, z, make_float3(0.f, 0.f, 0.f), acc);
     }
     if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NT>(a, acc, red, blockIdx.x);
 }
@@ -252,7 +254,8 @@ hipError_t launch_finalize(const FieldArgs& a, hipStream_t s) {
 __global__ void __launch_bounds__(NT) k_final_combine(const FieldArgs a) {
     const long long i = (long long)blockIdx.x * NT + threadIdx.x;
     if (i >= a.ncell) return;
-    const float3 m = stage_state(a, i, (float)a.st->dt);
+    const Resolved rs = resolve(a);
+    const float3 m = stage_state(a, rs, i);
     const float n2 = f3dot(m, m);
     const float inv = n2 > 0.f ? rsqrtf(n2) : 0.f;
     st3(const_cast<float*>(a.m0), a.ncell, i, f3scale(inv, m));
