@@ -6,11 +6,17 @@ advanced by Dormand-Prince RK45 steps with MaxErr 1e-5 under device-side step
 control.  One benchmark step = one RK45 attempt = 6 fused B_eff + torque
 evaluations (demag FFT convolution, exchange, anisotropy, Zeeman, torque,
 stage combine, error norm).  Following the paper's protocol (appendix
-"Benchmark: throughput"), throughput = cells x evaluations / wall time.
+"Benchmark: throughput"), throughput = cells x evaluations / wall time of the
+timed attempts, which run without instrumentation.  A second pass of the same
+number of attempts has every field-pass launch record HIP events at its own
+start and end; those durations give the per-kernel figures and the roofline
+fraction of the dominant kernel.
 
 Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +29,41 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Beff evals·cells/s: plain FP32 vs MFMA/surrogate at ≤1e-4 rel demag error"
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_1406_7635_amd", "csrc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "film1024_rk45_hbm_traffic.txt")
+
+
+def kernel_source_digest():
+    """SHA-256 over every HIP/C++ source and header of the library: measured
+    traffic is only reported while the kernels are the ones it was taken on."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(path, n):
+    """HBM bytes per launch from a rocprofv3 FETCH_SIZE / WRITE_SIZE summary
+    (lines 'source_sha256 <hex>', 'grid <n>' and 'traffic_bytes <pass> <bytes>');
+    {} when absent, taken on another film size or on other kernel sources."""
+    if not path or not os.path.exists(path):
+        return {}
+    digest, grid, out = None, None, {}
+    with open(path) as fh:
+        for line in fh:
+            w = line.split()
+            if len(w) == 2 and w[0] == "source_sha256":
+                digest = w[1]
+            elif len(w) == 2 and w[0] == "grid":
+                grid = int(w[1])
+            elif len(w) == 3 and w[0] == "traffic_bytes":
+                out[w[1]] = float(w[2])
+    if digest != kernel_source_digest() or grid != n:
+        return {}
+    return out
 
 
 def column_pass_bytes(ctx):
@@ -78,7 +119,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=1024, help="film edge in cells")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch")
+    ap.add_argument("--traffic", default=TRAFFIC_FILE,
+                    help="rocprofv3 traffic summary with measured HBM bytes per launch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy 10 times (counter calibration)")
     args = ap.parse_args()
@@ -107,9 +149,7 @@ def main():
     m = torch.from_numpy(case["m0"]).to("cuda:0")
     opts = mm.solver_opts(max_err=1e-5)
     t, dt, _ = ctx.run(m, float("inf"), dt=1e-14, max_attempts=max(1, args.warmup), opts=opts)
-    ctx.timing_enable(0)
-    ctx.timing_enable(1)
-    ctx.timing_enable(2)
+    # timed region: exactly `steps` RK45 attempts, no instrumentation
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -121,10 +161,18 @@ def main():
     gpu_ms = e0.elapsed_time(e1)
     evals = st["evals"]
     value = ncell * evals / wall
+    # the same number of attempts again with every field-pass launch recording a
+    # HIP event pair at its own start and end (on the context stream): the
+    # per-kernel durations behind the roofline figures
+    for k in range(3):
+        ctx.timing_enable(k)
+    t, dt, st2 = ctx.run(m, float("inf"), t=t, dt=dt, max_attempts=args.steps, opts=opts)
+    torch.cuda.synchronize()
     per = {}
     for k, name in enumerate(("x_forward", "column_conv", "x_inverse")):
         n, ms = ctx.timing_read(k)
         per[name] = {"launches": n, "avg_us": 1e3 * ms / max(n, 1), "total_ms": ms}
+        ctx.timing_enable(k, False)
     dominant = max(per, key=lambda k: per[k]["total_ms"])
     avg_k = 20.0 / 6.0  # stage-derivative reads per evaluation in RK45 (20 over 6 stages)
     bytes_per_launch = {"x_forward": xfwd_pass_bytes(ctx, avg_k), "column_conv": column_pass_bytes(ctx),
@@ -133,10 +181,7 @@ def main():
         per[k]["alg_bytes"] = bytes_per_launch[k]
         per[k]["gbs"] = bytes_per_launch[k] / (per[k]["avg_us"] * 1e-6) / 1e9
     ach = per[dominant]["gbs"]
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as fh:
-            traffic = json.load(fh).get(dominant)
+    traffic = measured_traffic(args.traffic, args.n).get(dominant)
     out = {
         "metric": METRIC, "value": value, "unit": "Beff evals*cells/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
@@ -145,7 +190,8 @@ def main():
         "config": {"workload": "vortex film %dx%dx1, 2 nm cells, Msat 8e5, Aex 1.3e-11, alpha 0.01, "
                                "B_ext 10 mT x; RK45 MaxErr 1e-5; plain FP32 FFT demag" % (args.n, args.n),
                    "cells": ncell, "evals": evals, "accepted": st["steps"], "rejected": st["rejects"],
-                   "evals_per_step": 6, "gpu_event_ms": gpu_ms},
+                   "evals_per_step": 6, "gpu_event_ms": gpu_ms,
+                   "kernel_timing": "second pass of %d attempts, dispatch-recorded HIP events" % args.steps},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant},
         "kernels": per,

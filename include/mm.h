@@ -235,10 +235,13 @@ int mm_demag_kernel_dump(mm_ctx *c, float *out_dev);
 int mm_exchange_dump(mm_ctx *c, float *out_dev);
 
 /* Kernel timing with HIP events on the context stream.  mm_timing_enable(c,
- * which, 1) records an event pair around every later launch of kernel class
- * `which` (0 = x-forward FFT pass, 1 = column (y/z) convolution pass,
- * 2 = x-inverse FFT + field/torque pass); mm_timing_read returns the number of
- * launches and the summed milliseconds since enabling (synchronises). */
+ * which, 1) has every later launch of kernel class `which` (0 = x-forward FFT
+ * pass, 1 = column (y/z) convolution pass, 2 = x-inverse FFT + field/torque
+ * pass) record an event pair at the start and end of the kernel itself (3D:
+ * from the start of the y-forward to the end of the y-inverse launch); the
+ * event pairs are created by this call.  mm_timing_read returns the number of
+ * launches and the summed milliseconds since enabling (synchronises).
+ * Enabling again restarts the count; enable = 0 frees the events. */
 int mm_timing_enable(mm_ctx *c, int32_t which, int32_t enable);
 int mm_timing_read(mm_ctx *c, int32_t which, int64_t *launches, double *total_ms);
 

@@ -122,6 +122,50 @@ struct Dft<16, INV> {
     }
 };
 
+// exp(-+2 pi i m / 16) x for a compile-time m (after unrolling): the
+// multiplications by 0 and +-1 are spelled out, since the compiler may not
+// drop them itself (signed zeros)
+template <bool INV>
+__host__ __device__ inline cf twist16(cf x, int m) {
+    const float c1 = 0.92387953251128676f, s1 = 0.38268343236508977f, h = 0.70710678118654752f;
+    m &= 15;
+    if (m == 0) return x;
+    if (m == 4) return rot90<INV>(x);
+    if (m == 8) return mkc(-x.x, -x.y);
+    if (m == 12) return rot90<!INV>(x);
+    const float cs[16][2] = {{1.f, 0.f}, {c1, s1}, {h, h}, {s1, c1}, {0.f, 1.f}, {-s1, c1}, {-h, h}, {-c1, s1},
+                             {-1.f, 0.f}, {-c1, -s1}, {-h, -h}, {-s1, -c1}, {0.f, -1.f}, {s1, -c1}, {h, -h}, {c1, -s1}};
+    const float wr = cs[m][0], wi = INV ? cs[m][1] : -cs[m][1];
+    if ((m & 3) == 2) {  // +-h (1 +- i): two products instead of four
+        const float hr = wr, hi = wi;  // |hr| = |hi| = h
+        return (hr == hi) ? mkc(hr * (x.x - x.y), hr * (x.x + x.y)) : mkc(hr * (x.x + x.y), hr * (x.y - x.x));
+    }
+    return cmul(x, mkc(wr, wi));
+}
+
+// R-point DFT of a sequence whose upper R/2 inputs are zero (zero padding):
+// the even outputs are the R/2-point DFT of the inputs, the odd outputs that
+// of the inputs twisted by w_R^n.  Inputs in v[0..R/2), outputs in v[0..R).
+template <int R, bool INV>
+struct DftHalf {
+    __host__ __device__ static void run(cf* v) {
+        constexpr int H = R / 2;
+        cf y[H], z[H];
+#pragma unroll
+        for (int n = 0; n < H; ++n) {
+            y[n] = v[n];
+            z[n] = twist16<INV>(v[n], n * (16 / R));
+        }
+        Dft<H, INV>::run(y);
+        Dft<H, INV>::run(z);
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            v[2 * j] = y[j];
+            v[2 * j + 1] = z[j];
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Register-resident transform.  A group of TPF threads owns NF sequences of
 // length P; thread t keeps PPT = P/TPF points of each in registers, in
@@ -133,7 +177,9 @@ struct Dft<16, INV> {
 // single LDS sequence one after the other, so a group needs seq_len(P)
 // elements of LDS.  The exchange halves are separate __host__ __device__
 // functions so a host program can emulate a group without a GPU.
-template <int P, int TPF, int NF, bool INV>
+// HIN: the inputs x[n], n >= P/2, are zero (zero padding) and the registers
+// holding them are ignored; stage 0 then runs the half-input butterflies.
+template <int P, int TPF, int NF, bool INV, bool HIN = false>
 struct RegFft {
     static constexpr int PPT = P / TPF;
     static constexpr int LP = ilog2(P);
@@ -146,8 +192,10 @@ struct RegFft {
     // span of stage s (product of the radices before it)
     __host__ __device__ static int span(int s) { return s == 0 ? 1 : R0 << (LA * (s - 1)); }
 
-    // natural order -> stage-0 order, then the stage-0 butterflies (no twiddles)
+    // natural order -> stage-0 order, then the stage-0 butterflies (no twiddles).
+    // Input r of butterfly u is x[t + TPF u + r P/R0], zero for r >= R0/2 under HIN.
     __host__ __device__ static void stage0(cf (&v)[NF][PPT]) {
+        constexpr bool HALF = HIN && R0 >= 2;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             cf w[PPT];
@@ -156,7 +204,12 @@ struct RegFft {
 #pragma unroll
                 for (int r = 0; r < R0; ++r) w[u * R0 + r] = v[f][u + r * (PPT / R0)];
 #pragma unroll
-            for (int u = 0; u < PPT / R0; ++u) Dft<R0, INV>::run(w + u * R0);
+            for (int u = 0; u < PPT / R0; ++u) {
+                if constexpr (HALF)
+                    DftHalf<R0, INV>::run(w + u * R0);
+                else
+                    Dft<R0, INV>::run(w + u * R0);
+            }
 #pragma unroll
             for (int i = 0; i < PPT; ++i) v[f][i] = w[i];
         }

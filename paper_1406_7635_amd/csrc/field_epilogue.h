@@ -82,41 +82,39 @@ __device__ inline float3 stage_state(const FieldArgs& a, const Resolved& r, long
 
 // Exchange field at (x, y, z) from the state array mp.  A neighbour outside
 // the grid is replaced by the cell itself (the Neumann rule), which adds
-// c (m - m) = 0; so every neighbour is loaded without a branch.
+// c (m - m) = 0; so every neighbour is loaded without a branch.  The six
+// neighbour slots have fixed positions (x-, x+, y-, y+, z-, z+) so the arrays
+// stay in registers; the y and z pairs are skipped (uniformly) for a single
+// layer along that axis.
 __device__ inline float3 exchange_at(const FieldArgs& a, const float* __restrict__ mp, long long cell,
                                      int x, int y, int z, int r, float3 mc) {
     const long long n = a.ncell;
     const long long sxy = (long long)a.nx * a.ny;
+    const bool use_y = a.ny > 1, use_z = a.nz > 1;
     long long nb[6];
-    float id2[6];
-    int cnt = 2;
     nb[0] = x > 0 ? cell - 1 : cell;
     nb[1] = x < a.nx - 1 ? cell + 1 : cell;
-    id2[0] = id2[1] = a.idx2;
-    if (a.ny > 1) {
-        nb[cnt] = y > 0 ? cell - a.nx : cell;
-        nb[cnt + 1] = y < a.ny - 1 ? cell + a.nx : cell;
-        id2[cnt] = id2[cnt + 1] = a.idy2;
-        cnt += 2;
-    }
-    if (a.nz > 1) {
-        nb[cnt] = z > 0 ? cell - sxy : cell;
-        nb[cnt + 1] = z < a.nz - 1 ? cell + sxy : cell;
-        id2[cnt] = id2[cnt + 1] = a.idz2;
-        cnt += 2;
-    }
+    nb[2] = y > 0 ? cell - a.nx : cell;
+    nb[3] = y < a.ny - 1 ? cell + a.nx : cell;
+    nb[4] = z > 0 ? cell - sxy : cell;
+    nb[5] = z < a.nz - 1 ? cell + sxy : cell;
+    const float id2[3] = {a.idx2, a.idy2, a.idz2};
     int rn[6];
     float3 mn[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
-        if (i < cnt) {
+    for (int i = 0; i < 6; ++i) {
+        const bool use = i < 2 || (i < 4 ? use_y : use_z);
+        if (use) {
             rn[i] = a.region[nb[i]];
             mn[i] = ld3(mp, n, nb[i]);
         }
+    }
     float3 b = make_float3(0.f, 0.f, 0.f);
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
-        if (i < cnt) b = f3add(b, f3scale(a.ptab[pair_index(r, rn[i])] * id2[i], f3sub(mn[i], mc)));
+    for (int i = 0; i < 6; ++i) {
+        const bool use = i < 2 || (i < 4 ? use_y : use_z);
+        if (use) b = f3add(b, f3scale(a.ptab[pair_index(r, rn[i])] * id2[i / 2], f3sub(mn[i], mc)));
+    }
     return b;
 }
 

@@ -28,6 +28,8 @@
 //               FFT, crop, then the per-cell epilogue (exchange, anisotropy,
 //               Zeeman, torque, error norm, energies).
 // The 1/(px py pz) normalisation and -mu0 are folded into K^.
+#include <hip/hip_ext.h>
+
 #include "field_epilogue.h"
 
 namespace mm {
@@ -58,9 +60,38 @@ struct ColCfg {
     static constexpr int NTH = 3 * T * Cfg<P>::TPF;
 };
 
+// 2D convolution: the K^ octant rows (xx, yy, zz, xy) of the workgroup's T
+// columns, staged in LDS after the exchange buffers (bytes)
+template <int P>
+constexpr size_t khat_lds() {
+    return (size_t)ColCfg<P>::T * (P / 2 + 1) * sizeof(float4);
+}
+
 __device__ inline long long row_base(const FieldArgs& a, int row) {
     const int z = row / a.ny, y = row - z * a.ny;
     return (long long)z * a.zstride + 3LL * y;
+}
+
+// Spectrum offsets of the 2 GI rows of a workgroup (-1 past the grid), into
+// LDS by the first threads; the cooperative copies read them after a barrier.
+template <int GI>
+__device__ inline void row_bases(const FieldArgs& a, int pair0, long long* rbs) {
+    if (threadIdx.x < 2 * GI) {
+        const int row = 2 * pair0 + (int)threadIdx.x;
+        rbs[threadIdx.x] = row < a.nrows ? row_base(a, row) : -1;
+    }
+}
+
+// Element u of a workgroup's staged half spectra [pair][kx][row][component]
+// (6 complex per kx) and its offset in the spectrum (-1: row past the grid).
+template <int KH>
+__device__ inline long long staged_offset(const FieldArgs& a, const long long* rbs, int u, int* lofs) {
+    const int gg = u / (KH * 6), rem = u - gg * (KH * 6);
+    const int k = rem / 6, rc = rem - 6 * k;
+    const int h = rc >= 3 ? 1 : 0;
+    *lofs = rem;
+    const long long rb = rbs[2 * gg + h];
+    return rb < 0 ? -1 : rb + (long long)k * a.colstride + (rc - 3 * h);
 }
 
 // ---------------------------------------------------------------------------
@@ -70,12 +101,14 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
     constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL, KH = XCfg<P>::KH;
     constexpr int MH = PPT / 2 + 1;
     extern __shared__ cf lds[];
+    __shared__ long long rbs[2 * GI];
     if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
     const int tid = threadIdx.x;
     const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int pair0 = blk * GI;
     const int pair = pair0 + g;
+    row_bases<GI>(a, pair0, rbs);
     const int ra = 2 * pair, rb = ra + 1;
     const bool va = ra < a.nrows, vb = rb < a.nrows;
     const Resolved rs = resolve(a);
@@ -124,7 +157,8 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
         const float im = (in && v1) ? a.lut[g1[m]].a.x * s1[m] : 0.f;
         v[0][m] = mkc(re, im);
     }
-    RegFft<P, TPF, 1, false>::run(v, buf, a.tw, a.twshift, t);
+    // x >= nx is zero padding (nx <= P/2)
+    RegFft<P, TPF, 1, false, (P >= 2)>::run(v, buf, a.tw, a.twshift, t);
 
     // separate the two real transforms of this slot
     __syncthreads();
@@ -156,12 +190,14 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
         }
     }
     __syncthreads();
-    for (int u = tid; u < GI * KH * 6; u += NTH) {
-        const int gg = u / (KH * 6), rem = u - gg * (KH * 6);
-        const int k = rem / 6, rc = rem - 6 * k;
-        const int row = 2 * (pair0 + gg) + (rc >= 3 ? 1 : 0);
-        if (row < a.nrows)
-            a.spec[row_base(a, row) + (long long)k * a.colstride + (rc >= 3 ? rc - 3 : rc)] = lds[gg * GL + rem];
+    constexpr int TOT = GI * KH * 6, NIT = (TOT + NTH - 1) / NTH;
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int u = tid + NTH * i;
+        if (i == NIT - 1 && u >= TOT) break;  // only the last round is partial
+        int lofs;
+        const long long off = staged_offset<KH>(a, rbs, u, &lofs);
+        if (off >= 0) a.spec[off] = lds[(u / (KH * 6)) * GL + lofs];
     }
 }
 
@@ -199,17 +235,45 @@ __global__ void __launch_bounds__(ColCfg<P>::NTH) k_col(const ColArgs a) {
     cf* bufs = lds + ci * 3 * SEQ;
     cf* buf = bufs + s * SEQ;
 
+    // A padded axis has P >= 2 n: the forward transforms read only q < P/2
+    // (the rest is zero padding) and the cropped outputs are q < P/2.
+    constexpr bool HIN = MODE != COL_INV && P >= 2;
+    constexpr int MIN = HIN ? PPT / 2 : PPT;
+    constexpr int MOUT = (MODE != COL_FWD && P >= 2) ? PPT / 2 : PPT;
     cf v[1][PPT];
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         const int q = t + TPF * m;
-        const bool ld = valid && q < a.n_in;
+        const bool ld = m < MIN && valid && q < a.n_in;
         const long long off = (long long)q * a.pos_stride + s;
         cf x = ld ? base[off] : mkc(0.f, 0.f);
         if (packed) x = mkc(x.x, ld ? baseN[off].x : 0.f);
         v[0][m] = x;
     }
-    RegFft<P, TPF, 1, MODE == COL_INV>::run(v, buf, a.tw, a.twshift, t);
+    // 2D convolution: the K^ rows of the workgroup's columns go to LDS now, so
+    // their latency overlaps that of the column loads (K^ column kx is
+    // contiguous: (P/2 + 1) rows of 4 floats)
+    constexpr int KHP = P / 2 + 1;
+    float4* lk = reinterpret_cast<float4*>(lds + T * 3 * SEQ);
+    if constexpr (MODE == COL_CONV && NC == 4) {
+        constexpr int TOT = T * KHP, NTH = ColCfg<P>::NTH, NIT = (TOT + NTH - 1) / NTH;
+        const float4* kh = reinterpret_cast<const float4*>(a.khat);
+        const int c0 = (blk - o * ntile) * T;
+        float4 kt[NIT];
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int e = tid + NTH * i;
+            const int ce = e / KHP, r = e - ce * KHP;
+            const bool in = (i < NIT - 1 || e < TOT) && c0 + ce < a.ncol;
+            kt[i] = in ? kh[(long long)(c0 + ce) * KHP + r] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int e = tid + NTH * i;
+            if (i < NIT - 1 || e < TOT) lk[e] = kt[i];
+        }
+    }
+    RegFft<P, TPF, 1, MODE == COL_INV, HIN>::run(v, buf, a.tw, a.twshift, t);
 
     if (MODE == COL_CONV) {
         // all three components of this column through LDS
@@ -240,14 +304,29 @@ __global__ void __launch_bounds__(ColCfg<P>::NTH) k_col(const ColArgs a) {
                 fq = true;
             }
             // row s of the symmetric K^ at (kxx, ky, q), with the mirror signs
+            // (2D: column kxx == c of this thread is staged in LDS)
             auto krow = [&](int kxx) {
                 float3 r = make_float3(0.f, 0.f, 0.f);
                 if (!valid) return r;
-                const float* K = a.khat + (((long long)kxx * a.kyh + kyh) * a.kzh + qh) * NC;
-                float kxy = K[3], kxz = 0.f, kyz = 0.f;
+                float k0, k1, k2, kxy, kxz = 0.f, kyz = 0.f;
+                if (NC == 4 && kxx == c) {
+                    const float4 k4 = lk[ci * KHP + qh];
+                    k0 = k4.x;
+                    k1 = k4.y;
+                    k2 = k4.z;
+                    kxy = k4.w;
+                } else {
+                    const float* K = a.khat + (((long long)kxx * a.kyh + kyh) * a.kzh + qh) * NC;
+                    k0 = K[0];
+                    k1 = K[1];
+                    k2 = K[2];
+                    kxy = K[3];
+                    if (NC == 6) {
+                        kxz = K[4];
+                        kyz = K[5];
+                    }
+                }
                 if (NC == 6) {
-                    kxz = K[4];
-                    kyz = K[5];
                     if (fq) {  // z: xz and yz are odd in z
                         kxz = -kxz;
                         kyz = -kyz;
@@ -260,11 +339,11 @@ __global__ void __launch_bounds__(ColCfg<P>::NTH) k_col(const ColArgs a) {
                     kxy = -kxy;
                 }
                 if (s == 0)
-                    r = make_float3(K[0], kxy, kxz);
+                    r = make_float3(k0, kxy, kxz);
                 else if (s == 1)
-                    r = make_float3(kxy, K[1], kyz);
+                    r = make_float3(kxy, k1, kyz);
                 else
-                    r = make_float3(kxz, kyz, K[2]);
+                    r = make_float3(kxz, kyz, k2);
                 return r;
             };
             const cf m0 = bufs[lds_pad(q)], m1 = bufs[SEQ + lds_pad(q)], m2 = bufs[2 * SEQ + lds_pad(q)];
@@ -294,7 +373,7 @@ __global__ void __launch_bounds__(ColCfg<P>::NTH) k_col(const ColArgs a) {
     int t2 = t;
     asm volatile("" : "+v"(t2));  // form the store addresses here, not at load time
 #pragma unroll
-    for (int m = 0; m < PPT; ++m) {
+    for (int m = 0; m < MOUT; ++m) {
         const int q = t2 + TPF * m;
         if (valid && q < a.n_out) {
             const long long off = (long long)q * a.pos_stride + s;
@@ -316,6 +395,7 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
     constexpr int MH = PPT / 2 + 1;
     extern __shared__ cf lds[];
     __shared__ double red[(NTH / 64 > 0 ? NTH / 64 : 1) * 6];
+    __shared__ long long rbs[2 * GI];
     if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
     const int tid = threadIdx.x;
     const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
@@ -323,15 +403,26 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
     const int pair0 = blk * GI;
     cf* gbuf = lds + g * GL;
     cf* buf = gbuf + slot * SEQ;
+    row_bases<GI>(a, pair0, rbs);
+    __syncthreads();
 
-    // read the half spectra of the row pairs in contiguous runs into [kx][row][component]
-    for (int u = tid; u < GI * KH * 6; u += NTH) {
-        const int gg = u / (KH * 6), rem = u - gg * (KH * 6);
-        const int k = rem / 6, rc = rem - 6 * k;
-        const int row = 2 * (pair0 + gg) + (rc >= 3 ? 1 : 0);
-        lds[gg * GL + rem] = row < a.nrows
-                                 ? a.spec[row_base(a, row) + (long long)k * a.colstride + (rc >= 3 ? rc - 3 : rc)]
-                                 : mkc(0.f, 0.f);
+    // read the half spectra of the row pairs in contiguous runs into
+    // [kx][row][component]: every load of the thread first, then the LDS writes
+    constexpr int TOT = GI * KH * 6, NIT = (TOT + NTH - 1) / NTH;
+    cf tmp[NIT];
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int u = tid + NTH * i;
+        const bool in = i < NIT - 1 || u < TOT;  // only the last round is partial
+        int lofs;
+        const long long off = staged_offset<KH>(a, rbs, in ? u : 0, &lofs);
+        tmp[i] = (in && off >= 0) ? a.spec[off] : mkc(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int u = tid + NTH * i;
+        if (i == NIT - 1 && u >= TOT) break;
+        lds[(u / (KH * 6)) * GL + (u % (KH * 6))] = tmp[i];
     }
     __syncthreads();
     // slot s = u + i w (slot 0: x, y of row a; slot 1: x, y of row b; slot 2: z of
@@ -364,9 +455,11 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
 #pragma unroll
     for (int m = 0; m < PPT; ++m) v[0][m] = buf[lds_pad(t + TPF * m)];
     RegFft<P, TPF, 1, true>::run(v, buf, a.tw, a.twshift, t);
+    // only x < nx <= P/2 is kept
+    constexpr int MOUT = P >= 2 ? PPT / 2 : PPT;
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < PPT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
+    for (int m = 0; m < MOUT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
     __syncthreads();
 
     // per-cell epilogue over the 2 GI rows of this workgroup
@@ -391,6 +484,16 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
 // ---------------------------------------------------------------------------
 // Launch helpers: dispatch the run-time padded length to a template instance.
 
+// Dynamic LDS of each pass (bytes per workgroup).
+template <int P>
+constexpr size_t x_lds() {
+    return (size_t)XCfg<P>::GI * XCfg<P>::GL * sizeof(cf);
+}
+template <int P, int MODE, int NC>
+constexpr size_t col_lds() {
+    return (size_t)ColCfg<P>::T * 3 * seq_len(P) * sizeof(cf) + (MODE == COL_CONV && NC == 4 ? khat_lds<P>() : 0);
+}
+
 template <int P>
 static int x_blocks(int nrows) {
     const int npairs = (nrows + 1) / 2;
@@ -398,34 +501,94 @@ static int x_blocks(int nrows) {
 }
 
 template <int P>
-static hipError_t xfwd_p(const FieldArgs& a, hipStream_t s) {
-    const size_t lds = (size_t)XCfg<P>::GI * XCfg<P>::GL * sizeof(cf);
-    (void)hipFuncSetAttribute((const void*)k_xfwd<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_xfwd<P>), dim3(x_blocks<P>(a.nrows)), dim3(XCfg<P>::NTH), lds, s, a);
+static hipError_t xfwd_p(const FieldArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const size_t lds = x_lds<P>();
+    hipExtLaunchKernelGGL((k_xfwd<P>), dim3(x_blocks<P>(a.nrows)), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0,
+                          a);
     return hipGetLastError();
 }
 
 template <int P>
-static hipError_t xinv_p(const FieldArgs& a, hipStream_t s, int* nb_out) {
-    const size_t lds = (size_t)XCfg<P>::GI * XCfg<P>::GL * sizeof(cf);
+static hipError_t xinv_p(const FieldArgs& a, hipStream_t s, int* nb_out, hipEvent_t e0, hipEvent_t e1) {
+    const size_t lds = x_lds<P>();
     const int nb = x_blocks<P>(a.nrows);
     if (nb_out) *nb_out = nb;
-    (void)hipFuncSetAttribute((const void*)k_xinv<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_xinv<P>), dim3(nb), dim3(XCfg<P>::NTH), lds, s, a);
+    hipExtLaunchKernelGGL((k_xinv<P>), dim3(nb), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0, a);
     return hipGetLastError();
 }
 
 template <int P, int MODE, int NC, bool CFAST>
-static hipError_t col_p(const ColArgs& a, hipStream_t s) {
-    const size_t lds = (size_t)ColCfg<P>::T * 3 * seq_len(P) * sizeof(cf);
+static hipError_t col_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const size_t lds = col_lds<P, MODE, NC>();
     const long long nb = (long long)((a.ncol + ColCfg<P>::T - 1) / ColCfg<P>::T) * a.nouter;
-    (void)hipFuncSetAttribute((const void*)k_col<P, MODE, NC, CFAST>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-    hipLaunchKernelGGL((k_col<P, MODE, NC, CFAST>), dim3((unsigned)nb), dim3(ColCfg<P>::NTH), lds, s, a);
+    hipExtLaunchKernelGGL((k_col<P, MODE, NC, CFAST>), dim3((unsigned)nb), dim3(ColCfg<P>::NTH), (uint32_t)lds, s,
+                          e0, e1, 0, a);
     return hipGetLastError();
 }
 
 #define MM_CASES(M) M(1) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048) M(4096)
+
+template <int P>
+static hipError_t allow_lds(const void* f, size_t bytes) {
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int P>
+static hipError_t configure_x(void) {
+    hipError_t e = allow_lds<P>((const void*)k_xfwd<P>, x_lds<P>());
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P>, x_lds<P>());
+    return e;
+}
+
+template <int P>
+static hipError_t configure_col(bool three_d) {
+    if (!three_d) return allow_lds<P>((const void*)k_col<P, COL_CONV, 4, false>, col_lds<P, COL_CONV, 4>());
+    hipError_t e = allow_lds<P>((const void*)k_col<P, COL_FWD, 4, false>, col_lds<P, COL_FWD, 4>());
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_col<P, COL_INV, 4, false>, col_lds<P, COL_INV, 4>());
+    return e;
+}
+
+template <int P>
+static hipError_t configure_zconv(void) {
+    return allow_lds<P>((const void*)k_col<P, COL_CONV, 6, true>, col_lds<P, COL_CONV, 6>());
+}
+
+hipError_t configure_field_kernels(int px, int py, int pz) {
+    hipError_t e = hipErrorInvalidValue;
+    switch (px) {
+#define M(p)                 \
+    case p:                  \
+        e = configure_x<p>(); \
+        break;
+        MM_CASES(M)
+#undef M
+        default:
+            return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    switch (py) {
+#define M(p)                         \
+    case p:                          \
+        e = configure_col<p>(pz > 1); \
+        break;
+        MM_CASES(M)
+#undef M
+        default:
+            return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess || pz == 1) return e;
+    switch (pz) {
+#define M(p)                    \
+    case p:                     \
+        e = configure_zconv<p>(); \
+        break;
+        MM_CASES(M)
+#undef M
+        default:
+            return hipErrorInvalidValue;
+    }
+    return e;
+}
 
 int xinv_blocks(int px, int nrows) {
     switch (px) {
@@ -439,11 +602,11 @@ int xinv_blocks(int px, int nrows) {
     }
 }
 
-hipError_t launch_xfwd(int px, const FieldArgs& a, hipStream_t s) {
+hipError_t launch_xfwd(int px, const FieldArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (px) {
 #define M(p) \
     case p:  \
-        return xfwd_p<p>(a, s);
+        return xfwd_p<p>(a, s, e0, e1);
         MM_CASES(M)
 #undef M
         default:
@@ -451,11 +614,11 @@ hipError_t launch_xfwd(int px, const FieldArgs& a, hipStream_t s) {
     }
 }
 
-hipError_t launch_xinv(int px, const FieldArgs& a, hipStream_t s, int* nb_out) {
+hipError_t launch_xinv(int px, const FieldArgs& a, hipStream_t s, int* nb_out, hipEvent_t e0, hipEvent_t e1) {
     switch (px) {
 #define M(p) \
     case p:  \
-        return xinv_p<p>(a, s, nb_out);
+        return xinv_p<p>(a, s, nb_out, e0, e1);
         MM_CASES(M)
 #undef M
         default:
@@ -463,12 +626,12 @@ hipError_t launch_xinv(int px, const FieldArgs& a, hipStream_t s, int* nb_out) {
     }
 }
 
-hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t s) {
+hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (mode == COL_FWD) {
         switch (p) {
 #define M(q) \
     case q:  \
-        return col_p<q, COL_FWD, 4, false>(a, s);
+        return col_p<q, COL_FWD, 4, false>(a, s, e0, e1);
             MM_CASES(M)
 #undef M
             default:
@@ -479,7 +642,7 @@ hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t 
         switch (p) {
 #define M(q) \
     case q:  \
-        return col_p<q, COL_INV, 4, false>(a, s);
+        return col_p<q, COL_INV, 4, false>(a, s, e0, e1);
             MM_CASES(M)
 #undef M
             default:
@@ -490,7 +653,7 @@ hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t 
         switch (p) {
 #define M(q) \
     case q:  \
-        return col_p<q, COL_CONV, 4, false>(a, s);
+        return col_p<q, COL_CONV, 4, false>(a, s, e0, e1);
             MM_CASES(M)
 #undef M
             default:
@@ -500,7 +663,7 @@ hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t 
     switch (p) {
 #define M(q) \
     case q:  \
-        return col_p<q, COL_CONV, 6, true>(a, s);
+        return col_p<q, COL_CONV, 6, true>(a, s, e0, e1);
         MM_CASES(M)
 #undef M
         default:

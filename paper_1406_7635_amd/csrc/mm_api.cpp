@@ -14,10 +14,14 @@ using namespace mm;
 
 namespace {
 
+// Event pairs are created when timing is enabled (not in the launch path) and
+// handed out in order; `used` of them hold launches.
 struct TimingClass {
     bool enabled = false;
+    size_t used = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
 };
+constexpr size_t TIMING_POOL = 4096;
 
 // Butcher tableaux (section "Dynamics"): row s holds a_{s+1, j}, j <= s.
 struct Tableau {
@@ -174,22 +178,28 @@ FieldArgs base_args(mm_ctx* c, const float* m0) {
     return a;
 }
 
+// Per-launch timing of one launch class: the events are handed to the
+// launches (start on the first kernel of the class, stop on the last), which
+// record them at the kernels' own start and end.
 struct Timed {
     mm_ctx* c;
     int which;
     hipEvent_t e1 = nullptr, e2 = nullptr;
     Timed(mm_ctx* c_, int w) : c(c_), which(w) {
-        if (c->timing[which].enabled) {
-            (void)hipEventCreate(&e1);
-            (void)hipEventCreate(&e2);
-            (void)hipEventRecord(e1, c->stream);
+        TimingClass& t = c->timing[which];
+        if (!t.enabled) return;
+        if (t.used == t.ev.size()) {
+            hipEvent_t a = nullptr, b = nullptr;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return;
+            }
+            t.ev.emplace_back(a, b);
         }
-    }
-    ~Timed() {
-        if (e1) {
-            (void)hipEventRecord(e2, c->stream);
-            c->timing[which].ev.emplace_back(e1, e2);
-        }
+        e1 = t.ev[t.used].first;
+        e2 = t.ev[t.used].second;
+        ++t.used;
     }
 };
 
@@ -201,7 +211,7 @@ int run_field(mm_ctx* c, FieldArgs& a, int* nblocks_out) {
         a.flags |= EPI_HAS_DEMAG;
         {
             Timed t(c, 0);
-            MM_TRY(launch_xfwd(c->px, a, s));
+            MM_TRY(launch_xfwd(c->px, a, s, t.e1, t.e2));
         }
         ColArgs ca;
         memset(&ca, 0, sizeof(ca));
@@ -223,10 +233,11 @@ int run_field(mm_ctx* c, FieldArgs& a, int* nblocks_out) {
                 ca.ncol = c->kx;
                 ca.outer_stride = c->zstride;
                 ca.nouter = c->nz;
-                if (c->py > 1) {
+                const bool ypass = c->py > 1;
+                if (ypass) {
                     ca.n_in = c->ny;
                     ca.n_out = c->py;
-                    MM_TRY(launch_col(c->py, COL_FWD, ca, 6, s));
+                    MM_TRY(launch_col(c->py, COL_FWD, ca, 6, s, t.e1, nullptr));
                 }
                 // z convolution of every (kx, ky) column; tiles of adjacent ky
                 ca.pos_stride = c->zstride;
@@ -236,8 +247,8 @@ int run_field(mm_ctx* c, FieldArgs& a, int* nblocks_out) {
                 ca.nouter = c->kx;
                 ca.n_in = c->nz;
                 ca.n_out = c->nz;
-                MM_TRY(launch_col(c->pz, COL_CONV, ca, 6, s));
-                if (c->py > 1) {
+                MM_TRY(launch_col(c->pz, COL_CONV, ca, 6, s, ypass ? nullptr : t.e1, ypass ? nullptr : t.e2));
+                if (ypass) {
                     ca.pos_stride = 3;
                     ca.col_stride = c->colstride;
                     ca.ncol = c->kx;
@@ -245,7 +256,7 @@ int run_field(mm_ctx* c, FieldArgs& a, int* nblocks_out) {
                     ca.nouter = c->nz;
                     ca.n_in = c->py;
                     ca.n_out = c->ny;
-                    MM_TRY(launch_col(c->py, COL_INV, ca, 6, s));
+                    MM_TRY(launch_col(c->py, COL_INV, ca, 6, s, nullptr, t.e2));
                 }
             } else {
                 // 2D: y convolution of every kx column; the DC and Nyquist columns
@@ -258,12 +269,12 @@ int run_field(mm_ctx* c, FieldArgs& a, int* nblocks_out) {
                 ca.nouter = 1;
                 ca.n_in = c->ny;
                 ca.n_out = c->ny;
-                MM_TRY(launch_col(c->py, COL_CONV, ca, 4, s));
+                MM_TRY(launch_col(c->py, COL_CONV, ca, 4, s, t.e1, t.e2));
             }
         }
         {
             Timed t(c, 2);
-            MM_TRY(launch_xinv(c->px, a, s, nblocks_out));
+            MM_TRY(launch_xinv(c->px, a, s, nblocks_out, t.e1, t.e2));
         }
     } else {
         if (a.sd.nk > 0) MM_TRY(launch_combine(a, s));
@@ -477,6 +488,7 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
         if (e == hipSuccess) e = hipMemcpyAsync(c->params64, p, sizeof(mm_params), hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = launch_prepare_tables(c->params64, c->lut, c->ptab, c->stream);
         if (e == hipSuccess) e = launch_twiddles(c->tw, c->pt, c->stream);
+        if (e == hipSuccess) e = configure_field_kernels(c->px, c->py, c->pz);
         if (e == hipSuccess)
             e = launch_set_state(c->st, 0.0, 1e-14, INFINITY, 1e-5, 0.8, 0.0, 0.0, 4, 1, 1, 0, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -763,12 +775,25 @@ int mm_timing_enable(mm_ctx* c, int32_t which, int32_t enable) {
     if (!c || which < 0 || which > 2) return MM_EINVAL;
     TimingClass& t = c->timing[which];
     MM_TRY(hipStreamSynchronize(c->stream));
-    for (auto& pr : t.ev) {
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
-    }
-    t.ev.clear();
+    t.used = 0;
     t.enabled = enable != 0;
+    if (!t.enabled) {
+        for (auto& pr : t.ev) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        t.ev.clear();
+        return MM_OK;
+    }
+    while (t.ev.size() < TIMING_POOL) {
+        hipEvent_t a = nullptr, b = nullptr;
+        MM_TRY(hipEventCreate(&a));
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return MM_EDEVICE;
+        }
+        t.ev.emplace_back(a, b);
+    }
     return MM_OK;
 }
 
@@ -776,12 +801,13 @@ int mm_timing_read(mm_ctx* c, int32_t which, int64_t* launches, double* total_ms
     if (!c || which < 0 || which > 2 || !launches || !total_ms) return MM_EINVAL;
     MM_TRY(hipStreamSynchronize(c->stream));
     double tot = 0.0;
-    for (auto& pr : c->timing[which].ev) {
+    const TimingClass& t = c->timing[which];
+    for (size_t i = 0; i < t.used; ++i) {
         float ms = 0.f;
-        MM_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+        MM_TRY(hipEventElapsedTime(&ms, t.ev[i].first, t.ev[i].second));
         tot += ms;
     }
-    *launches = (int64_t)c->timing[which].ev.size();
+    *launches = (int64_t)t.used;
     *total_ms = tot;
     return MM_OK;
 }

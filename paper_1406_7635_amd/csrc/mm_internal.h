@@ -102,10 +102,18 @@ struct ColArgs {
 };
 
 // ---- launchers (kernels_fft.hip) -------------------------------------------
-hipError_t launch_xfwd(int px, const FieldArgs& a, hipStream_t s);
-hipError_t launch_xinv(int px, const FieldArgs& a, hipStream_t s, int* nblocks_out);
-hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t s);
+// e0 / e1 (optional) are recorded by the dispatch itself at the start / end of
+// the kernel, so their elapsed time is the kernel's own duration.
+hipError_t launch_xfwd(int px, const FieldArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
+hipError_t launch_xinv(int px, const FieldArgs& a, hipStream_t s, int* nblocks_out, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
+hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t s, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr);
 int xinv_blocks(int px, int nrows);
+// Raise the dynamic-LDS limit of every pass a grid of padded size px x py x pz
+// launches (once per context, on the current device).
+hipError_t configure_field_kernels(int px, int py, int pz);
 enum ColMode { COL_FWD = 0, COL_INV = 1, COL_CONV = 2 };
 
 // ---- launchers (kernels_local.hip) -----------------------------------------

@@ -24,6 +24,17 @@ def make_pair(case, demag=True):
     return ctx, prob, m
 
 
+def make_ctx(case, demag=True):
+    """(GPU context, m0 tensor on cuda:0) without the oracle problem (whose
+    demagnetising tensor would be built for nothing)."""
+    import torch
+
+    from paper_1406_7635_amd import mm
+
+    ctx = mm.Context(case["grid"], case["cell"], case["region"], case["params"], demag=demag)
+    return ctx, torch.from_numpy(np.ascontiguousarray(case["m0"])).to("cuda:0")
+
+
 def rel_inf(got, ref):
     """max |got - ref| / max |ref| over all cells and components."""
     got = np.asarray(got, dtype=np.float64)
