@@ -34,30 +34,39 @@ __device__ inline int pair_index(int a, int b) {
     return hi * (hi + 1) / 2 + lo;
 }
 
-// Stage-derivative pointers and dt, read once per kernel from the device-side
-// solver state (the logical-to-physical buffer map changes on the device when
-// a step is accepted).  Reading them up front keeps the per-cell loops free of
-// dependent state loads.
+// Stage-derivative pointers, dt and the done flag, read once per kernel from
+// the device-side solver state (the logical-to-physical buffer map changes on
+// the device when a step is accepted).  All state words are loaded
+// unconditionally first, so they arrive in one round trip, and the pointers
+// are then picked with selects; the per-cell loops see no state loads.
 struct Resolved {
     const float* kin[6];  // stage-combine inputs, kin[j] for j < sd.nk
     float* kout;          // where the torque goes (a k buffer or the caller's tau)
     const float* ke[7];   // error-norm inputs (null: the torque just computed)
     float dt;
+    int done;             // the run already reached its end
 };
 
 __device__ inline Resolved resolve(const FieldArgs& a) {
+    // the map (entries < 8) is packed 3 bits per entry into one word, so a
+    // lookup is a shift rather than an indexed array
+    unsigned int pk = 0;
+#pragma unroll
+    for (int j = 0; j < MAXK; ++j) pk |= ((unsigned int)a.st->perm[j] & 7u) << (3 * j);
+    const double dt = a.st->dt;
+    const int done = a.st->done;
+    auto phys = [&](int logical) { return (int)((pk >> (3 * logical)) & 7u); };
     Resolved r;
     const long long n3 = 3 * a.ncell;
 #pragma unroll
-    for (int j = 0; j < 6; ++j)
-        r.kin[j] = j < a.sd.nk ? a.kbuf + (long long)a.st->perm[a.sd.kidx[j]] * n3 : nullptr;
-    r.kout = a.sd.out_k >= 0 ? a.kbuf + (long long)a.st->perm[a.sd.out_k] * n3 : a.tau;
+    for (int j = 0; j < 6; ++j) r.kin[j] = j < a.sd.nk ? a.kbuf + (long long)phys(a.sd.kidx[j]) * n3 : nullptr;
+    r.kout = a.sd.out_k >= 0 ? a.kbuf + (long long)phys(a.sd.out_k) * n3 : a.tau;
 #pragma unroll
     for (int j = 0; j < 7; ++j)
-        r.ke[j] = (j < a.sd.nerr && a.sd.eidx[j] != a.sd.out_k)
-                      ? a.kbuf + (long long)a.st->perm[a.sd.eidx[j]] * n3
-                      : nullptr;
-    r.dt = (float)a.st->dt;
+        r.ke[j] = (j < a.sd.nerr && a.sd.eidx[j] != a.sd.out_k) ? a.kbuf + (long long)phys(a.sd.eidx[j]) * n3
+                                                                 : nullptr;
+    r.dt = (float)dt;
+    r.done = done;
     return r;
 }
 
@@ -73,6 +82,43 @@ __device__ inline float stage_comp(const FieldArgs& a, const Resolved& r, long l
 #pragma unroll
     for (int j = 0; j < 6; ++j) acc += a.sd.a[j] * kv[j];
     return m0 + r.dt * acc;
+}
+
+// Stage-state components at N positions, out[i] = m0[idx[i]] + dt sum_{j<NK}
+// a_j k_j[idx[i]], with NK a compile-time count so that every load of the
+// batch is issued before the first is used (no data-dependent branches).
+template <int NK, int N>
+__device__ inline void stage_batch_nk(const FieldArgs& a, const Resolved& r, const long long (&idx)[N],
+                                      float (&out)[N]) {
+    float m0v[N];
+    float kv[N][NK > 0 ? NK : 1];
+#pragma unroll
+    for (int i = 0; i < N; ++i) m0v[i] = a.m0[idx[i]];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < NK; ++j) kv[i][j] = r.kin[j][idx[i]];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < NK; ++j) acc += a.sd.a[j] * kv[i][j];
+        out[i] = NK > 0 ? m0v[i] + r.dt * acc : m0v[i];
+    }
+}
+
+template <int N>
+__device__ inline void stage_batch(const FieldArgs& a, const Resolved& r, const long long (&idx)[N],
+                                   float (&out)[N]) {
+    switch (a.sd.nk) {
+        case 0: stage_batch_nk<0>(a, r, idx, out); break;
+        case 1: stage_batch_nk<1>(a, r, idx, out); break;
+        case 2: stage_batch_nk<2>(a, r, idx, out); break;
+        case 3: stage_batch_nk<3>(a, r, idx, out); break;
+        case 4: stage_batch_nk<4>(a, r, idx, out); break;
+        case 5: stage_batch_nk<5>(a, r, idx, out); break;
+        default: stage_batch_nk<6>(a, r, idx, out); break;
+    }
 }
 
 __device__ inline float3 stage_state(const FieldArgs& a, const Resolved& r, long long cell) {
@@ -132,11 +178,13 @@ __device__ inline void epi_init(EpiAcc& acc) {
 }
 
 // Everything after the magnetostatic field for one cell.
-__device__ inline void epilogue(const FieldArgs& a, const Resolved& rs, const float* __restrict__ mp,
-                                long long cell, int x, int y, int z, float3 bd, EpiAcc& acc) {
+// lut: the region table (global memory, or a copy in LDS).
+__device__ inline void epilogue(const FieldArgs& a, const Resolved& rs, const RegionLut* lut,
+                                const float* __restrict__ mp, long long cell, int x, int y, int z, float3 bd,
+                                EpiAcc& acc) {
     const int flags = a.flags;
     const int r = a.region[cell];
-    const RegionLut L = a.lut[r];
+    const RegionLut L = lut[r];
     const long long n = a.ncell;
     if (flags & EPI_BDEMAG) st3(a.bdemag, n, cell, bd);
     float3 tq = make_float3(0.f, 0.f, 0.f);

@@ -96,13 +96,15 @@ __device__ inline long long staged_offset(const FieldArgs& a, const long long* r
 
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
+__global__ void __launch_bounds__(XCfg<P>::NTH)
+k_xfwd(const FieldArgs a) {
     constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI, NTH = XCfg<P>::NTH;
     constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL, KH = XCfg<P>::KH;
     constexpr int MH = PPT / 2 + 1;
     extern __shared__ cf lds[];
     __shared__ long long rbs[2 * GI];
-    if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
+    const Resolved rs = resolve(a);
+    if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
     const int tid = threadIdx.x;
     const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -111,7 +113,6 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
     row_bases<GI>(a, pair0, rbs);
     const int ra = 2 * pair, rb = ra + 1;
     const bool va = ra < a.nrows, vb = rb < a.nrows;
-    const Resolved rs = resolve(a);
     cf* gbuf = lds + g * GL;
     cf* buf = gbuf + slot * SEQ;
     const long long n = a.ncell;
@@ -126,35 +127,57 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
 
     // Only x < P/2 can hold cells (P >= 2 nx - 1); rows and columns past the
     // grid are clamped for the loads and masked afterwards, so every load of
-    // the thread is issued before the first one is used.
+    // the thread is issued before the first one is used.  Msat of the 256
+    // regions is staged in LDS meanwhile (no dependent region -> table load).
     constexpr int MV = PPT > 1 ? PPT / 2 : 1;
+    float* msat_l = reinterpret_cast<float*>(lds + GI * GL);
+    constexpr int NMS = (NREG + NTH - 1) / NTH;
+    float msv[NMS];
+#pragma unroll
+    for (int i = 0; i < NMS; ++i) msv[i] = tid + NTH * i < NREG ? a.lut[tid + NTH * i].a.x : 0.f;
     const int r0c = v0 ? r0 : 0, r1c = v1 ? r1 : 0;
     cf v[1][PPT];
 #pragma unroll
     for (int m = MV; m < PPT; ++m) v[0][m] = mkc(0.f, 0.f);
-    float s0[MV], s1[MV];
+    long long idx0[MV], idx1[MV];
     int g0[MV], g1[MV];
 #pragma unroll
     for (int m = 0; m < MV; ++m) {
         const int x = t + TPF * m;
         const int xc = x < a.nx ? x : a.nx - 1;
         const long long cell0 = (long long)r0c * a.nx + xc, cell1 = (long long)r1c * a.nx + xc;
-        s0[m] = stage_comp(a, rs, c0 * n + cell0);
-        s1[m] = stage_comp(a, rs, c1 * n + cell1);
+        idx0[m] = c0 * n + cell0;
+        idx1[m] = c1 * n + cell1;
         g0[m] = a.region[cell0];
         g1[m] = a.region[cell1];
     }
+    // two batches (one per component) bound the loads in flight per thread
+    float sv[2 * MV];
+    {
+        float s0[MV], s1[MV];
+        stage_batch(a, rs, idx0, s0);
+        stage_batch(a, rs, idx1, s1);
+#pragma unroll
+        for (int m = 0; m < MV; ++m) {
+            sv[m] = s0[m];
+            sv[MV + m] = s1[m];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NMS; ++i)
+        if (tid + NTH * i < NREG) msat_l[tid + NTH * i] = msv[i];
+    __syncthreads();
 #pragma unroll
     for (int m = 0; m < MV; ++m) {
         const int x = t + TPF * m;
         const bool in = x < a.nx;
         const long long cell0 = (long long)r0c * a.nx + x, cell1 = (long long)r1c * a.nx + x;
         if (a.sd.nk > 0) {
-            if (in && v0) a.ms[c0 * n + cell0] = s0[m];
-            if (in && v1) a.ms[c1 * n + cell1] = s1[m];
+            if (in && v0) a.ms[c0 * n + cell0] = sv[m];
+            if (in && v1) a.ms[c1 * n + cell1] = sv[MV + m];
         }
-        const float re = (in && v0) ? a.lut[g0[m]].a.x * s0[m] : 0.f;
-        const float im = (in && v1) ? a.lut[g1[m]].a.x * s1[m] : 0.f;
+        const float re = (in && v0) ? msat_l[g0[m]] * sv[m] : 0.f;
+        const float im = (in && v1) ? msat_l[g1[m]] * sv[MV + m] : 0.f;
         v[0][m] = mkc(re, im);
     }
     // x >= nx is zero padding (nx <= P/2)
@@ -388,6 +411,189 @@ __global__ void __launch_bounds__(ColCfg<P>::NTH) k_col(const ColArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// 2D convolution, one thread group per column carrying all three components
+// (three sequences through one LDS exchange buffer).  The K^ product is then
+// local to the thread, and the twiddles and exchange addresses of a stage
+// serve all three components.  Workgroup: T columns of TPF threads; LDS per
+// column: the exchange buffer, then a region that holds the column's K^ rows
+// (or, in the workgroup of the packed DC/Nyquist column, a second buffer).
+template <int P>
+struct Col3Cfg {
+    static constexpr int TPF = Cfg<P>::TPF;
+    static constexpr int T = TPF >= 256 ? 1 : 256 / TPF;
+    static constexpr int NTH = T * TPF;
+    static constexpr int SEQ = seq_len(P);
+    static constexpr int KHP = P / 2 + 1;
+    // complex elements per column: buffer + max(K^ rows (2 cf each), buffer)
+    static constexpr int CL = SEQ + (2 * KHP > SEQ ? 2 * KHP : SEQ);
+};
+
+template <int P>
+constexpr size_t col3_lds() {
+    return (size_t)Col3Cfg<P>::T * Col3Cfg<P>::CL * sizeof(cf);
+}
+
+template <int P>
+__global__ void __launch_bounds__(Col3Cfg<P>::NTH, 4) k_col3(const ColArgs a) {
+    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, T = Col3Cfg<P>::T, NTH = Col3Cfg<P>::NTH;
+    constexpr int SEQ = Col3Cfg<P>::SEQ, KHP = Col3Cfg<P>::KHP, CL = Col3Cfg<P>::CL, MH = PPT / 2;
+    extern __shared__ cf lds[];
+    if (a.check_done && a.st->done) return;
+    const int tid = threadIdx.x;
+    const int t = tid % TPF, ci = tid / TPF;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int c0 = blk * T, c = c0 + ci;
+    const bool valid = c < a.ncol;
+    const bool wg_packed = a.pack_col > 0 && blk == 0;  // uniform over the workgroup
+    const bool packed = wg_packed && ci == 0;
+    cf* buf = lds + ci * CL;
+    cf* reg2 = buf + SEQ;
+    const cf* base = a.spec + (long long)(valid ? c : 0) * a.col_stride;
+    const cf* baseN = a.spec + (long long)a.pack_col * a.col_stride;
+
+    // rows y < ny <= P/2 hold data; the rest is zero padding
+    cf v[3][PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int q = t + TPF * m;
+        const bool ld = m < MH && valid && q < a.n_in;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            cf x = ld ? base[3LL * q + k] : mkc(0.f, 0.f);
+            if (packed) x = mkc(x.x, ld ? baseN[3LL * q + k].x : 0.f);
+            v[k][m] = x;
+        }
+    }
+    // the K^ rows of every column of the workgroup into LDS (their latency
+    // overlaps that of the column loads); column kx is contiguous
+    {
+        constexpr int TOT = T * KHP, NIT = (TOT + NTH - 1) / NTH;
+        const float4* kh = reinterpret_cast<const float4*>(a.khat);
+        float4 kt[NIT];
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int e = tid + NTH * i;
+            const int ce = e / KHP, r = e - ce * KHP;
+            const bool in = (i < NIT - 1 || e < TOT) && c0 + ce < a.ncol;
+            kt[i] = in ? kh[(long long)(c0 + ce) * KHP + r] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int e = tid + NTH * i;
+            const int ce = e / KHP, r = e - ce * KHP;
+            if (i < NIT - 1 || e < TOT) reinterpret_cast<float4*>(lds + ce * CL + SEQ)[r] = kt[i];
+        }
+    }
+    RegFft<P, TPF, 3, false, true>::run(v, buf, a.tw, a.twshift, t);
+
+    // B^ = K^ M^ (2D: K^ = [[xx, xy, 0], [xy, yy, 0], [0, 0, zz]], xy odd in y)
+    if (!wg_packed) {
+        const float4* lk = reinterpret_cast<const float4*>(reg2);
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
+            const int q = t + TPF * m;
+            const bool fq = 2 * q > P;
+            const float4 k4 = lk[fq ? P - q : q];
+            const float kxy = fq ? -k4.w : k4.w;
+            const cf mx = v[0][m], my = v[1][m];
+            v[0][m] = k4.x * mx + kxy * my;
+            v[1][m] = kxy * mx + k4.y * my;
+            v[2][m] = k4.z * v[2][m];
+        }
+    } else {
+        // Packed column Z = A0 + i AN (A0: kx = 0, AN: kx = px/2, both real along
+        // y): B = K0 A0 + i KN AN = Kp Z(q) + Km conj Z(-q), Kp = (K0 + KN)/2,
+        // Km = (K0 - KN)/2.  Z(-q) comes through LDS: z first (one buffer), then
+        // x and y together (two buffers).
+        auto kpm = [&](int q, float4& kp, float4& km) {
+            const bool fq = 2 * q > P;
+            const int qh = fq ? P - q : q;
+            float4 k0 = reinterpret_cast<const float4*>(a.khat)[qh];
+            float4 kn = reinterpret_cast<const float4*>(a.khat)[(long long)a.pack_col * KHP + qh];
+            if (fq) {
+                k0.w = -k0.w;
+                kn.w = -kn.w;
+            }
+            kp = make_float4(0.5f * (k0.x + kn.x), 0.5f * (k0.y + kn.y), 0.5f * (k0.z + kn.z), 0.5f * (k0.w + kn.w));
+            km = make_float4(0.5f * (k0.x - kn.x), 0.5f * (k0.y - kn.y), 0.5f * (k0.z - kn.z), 0.5f * (k0.w - kn.w));
+        };
+        __syncthreads();
+        if (packed) {
+#pragma unroll
+            for (int m = 0; m < PPT; ++m) buf[lds_pad(t + TPF * m)] = v[2][m];
+        }
+        __syncthreads();
+        if (packed) {
+#pragma unroll
+            for (int m = 0; m < PPT; ++m) {
+                const int q = t + TPF * m;
+                float4 kp, km;
+                kpm(q, kp, km);
+                const cf zr = cconj(buf[lds_pad((P - q) & (P - 1))]);
+                v[2][m] = kp.z * v[2][m] + km.z * zr;
+            }
+        }
+        __syncthreads();
+        if (packed) {
+#pragma unroll
+            for (int m = 0; m < PPT; ++m) {
+                buf[lds_pad(t + TPF * m)] = v[0][m];
+                reg2[lds_pad(t + TPF * m)] = v[1][m];
+            }
+        }
+        __syncthreads();
+        if (packed) {
+#pragma unroll
+            for (int m = 0; m < PPT; ++m) {
+                const int q = t + TPF * m;
+                const int qn = (P - q) & (P - 1);
+                float4 kp, km;
+                kpm(q, kp, km);
+                const cf xr = cconj(buf[lds_pad(qn)]), yr = cconj(reg2[lds_pad(qn)]);
+                const cf zx = v[0][m], zy = v[1][m];
+                v[0][m] = kp.x * zx + kp.w * zy + km.x * xr + km.w * yr;
+                v[1][m] = kp.w * zx + kp.y * zy + km.w * xr + km.y * yr;
+            }
+        } else {
+            const float4* lk = reinterpret_cast<const float4*>(reg2);
+#pragma unroll
+            for (int m = 0; m < PPT; ++m) {
+                const int q = t + TPF * m;
+                const bool fq = 2 * q > P;
+                const float4 k4 = lk[fq ? P - q : q];
+                const float kxy = fq ? -k4.w : k4.w;
+                const cf mx = v[0][m], my = v[1][m];
+                v[0][m] = k4.x * mx + kxy * my;
+                v[1][m] = kxy * mx + k4.y * my;
+                v[2][m] = k4.z * v[2][m];
+            }
+        }
+    }
+    RegFft<P, TPF, 3, true>::run(v, buf, a.tw, a.twshift, t);
+
+    // rows y < ny <= P/2 are kept
+    cf* out = a.spec + (long long)(valid ? c : 0) * a.col_stride;
+    cf* outN = a.spec + (long long)a.pack_col * a.col_stride;
+    int t2 = t;
+    asm volatile("" : "+v"(t2));  // form the store addresses here, not at load time
+#pragma unroll
+    for (int m = 0; m < MH; ++m) {
+        const int q = t2 + TPF * m;
+        if (valid && q < a.n_out) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (!packed) {
+                    out[3LL * q + k] = v[k][m];
+                } else {
+                    out[3LL * q + k] = mkc(v[k][m].x, 0.f);
+                    outN[3LL * q + k] = mkc(v[k][m].y, 0.f);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 template <int P>
 __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
     constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI, NTH = XCfg<P>::NTH;
@@ -396,7 +602,8 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
     extern __shared__ cf lds[];
     __shared__ double red[(NTH / 64 > 0 ? NTH / 64 : 1) * 6];
     __shared__ long long rbs[2 * GI];
-    if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
+    const Resolved rs = resolve(a);
+    if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
     const int tid = threadIdx.x;
     const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -405,6 +612,15 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
     cf* buf = gbuf + slot * SEQ;
     row_bases<GI>(a, pair0, rbs);
     __syncthreads();
+
+    // the region table goes to LDS (after the row-pair area) for the epilogue
+    RegionLut* lut_l = reinterpret_cast<RegionLut*>(lds + GI * GL);
+    constexpr int NL4 = NREG * (int)(sizeof(RegionLut) / sizeof(float4)), NLI = (NL4 + NTH - 1) / NTH;
+    float4 lt[NLI];
+#pragma unroll
+    for (int i = 0; i < NLI; ++i)
+        lt[i] = tid + NTH * i < NL4 ? reinterpret_cast<const float4*>(a.lut)[tid + NTH * i]
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
 
     // read the half spectra of the row pairs in contiguous runs into
     // [kx][row][component]: every load of the thread first, then the LDS writes
@@ -424,6 +640,9 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
         if (i == NIT - 1 && u >= TOT) break;
         lds[(u / (KH * 6)) * GL + (u % (KH * 6))] = tmp[i];
     }
+#pragma unroll
+    for (int i = 0; i < NLI; ++i)
+        if (tid + NTH * i < NL4) reinterpret_cast<float4*>(lut_l)[tid + NTH * i] = lt[i];
     __syncthreads();
     // slot s = u + i w (slot 0: x, y of row a; slot 1: x, y of row b; slot 2: z of
     // rows a and b); the DC and Nyquist bins of a real signal are real
@@ -463,7 +682,6 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
     __syncthreads();
 
     // per-cell epilogue over the 2 GI rows of this workgroup
-    const Resolved rs = resolve(a);
     EpiAcc acc;
     epi_init(acc);
     const float* mp = a.sd.nk > 0 ? a.ms : a.m0;
@@ -475,7 +693,7 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
         const cf v01 = b3[(rr & 1) * SEQ + lds_pad(x)];
         const cf v2 = b3[2 * SEQ + lds_pad(x)];
         const int z = row / a.ny, y = row - z * a.ny;
-        epilogue(a, rs, mp, (long long)row * a.nx + x, x, y, z,
+        epilogue(a, rs, lut_l, mp, (long long)row * a.nx + x, x, y, z,
                  make_float3(v01.x, v01.y, (rr & 1) ? v2.y : v2.x), acc);
     }
     if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NTH>(a, acc, red, blk);
@@ -487,7 +705,7 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
 // Dynamic LDS of each pass (bytes per workgroup).
 template <int P>
 constexpr size_t x_lds() {
-    return (size_t)XCfg<P>::GI * XCfg<P>::GL * sizeof(cf);
+    return (size_t)XCfg<P>::GI * XCfg<P>::GL * sizeof(cf) + NREG * sizeof(RegionLut);
 }
 template <int P, int MODE, int NC>
 constexpr size_t col_lds() {
@@ -526,6 +744,20 @@ static hipError_t col_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent
     return hipGetLastError();
 }
 
+template <int P>
+static hipError_t col3_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const long long nb = (a.ncol + Col3Cfg<P>::T - 1) / Col3Cfg<P>::T;
+    hipExtLaunchKernelGGL((k_col3<P>), dim3((unsigned)nb), dim3(Col3Cfg<P>::NTH), (uint32_t)col3_lds<P>(), s, e0, e1,
+                          0, a);
+    return hipGetLastError();
+}
+
+// the three-components-per-thread 2D convolution serves 64 <= P <= 2048
+template <int P>
+constexpr bool use_col3() {
+    return P >= 64 && P <= 2048;
+}
+
 #define MM_CASES(M) M(1) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048) M(4096)
 
 template <int P>
@@ -542,7 +774,10 @@ static hipError_t configure_x(void) {
 
 template <int P>
 static hipError_t configure_col(bool three_d) {
-    if (!three_d) return allow_lds<P>((const void*)k_col<P, COL_CONV, 4, false>, col_lds<P, COL_CONV, 4>());
+    if (!three_d) {
+        if constexpr (use_col3<P>()) return allow_lds<P>((const void*)k_col3<P>, col3_lds<P>());
+        return allow_lds<P>((const void*)k_col<P, COL_CONV, 4, false>, col_lds<P, COL_CONV, 4>());
+    }
     hipError_t e = allow_lds<P>((const void*)k_col<P, COL_FWD, 4, false>, col_lds<P, COL_FWD, 4>());
     if (e == hipSuccess) e = allow_lds<P>((const void*)k_col<P, COL_INV, 4, false>, col_lds<P, COL_INV, 4>());
     return e;
@@ -651,8 +886,9 @@ hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t 
     }
     if (ncomp == 4) {
         switch (p) {
-#define M(q) \
-    case q:  \
+#define M(q)                                          \
+    case q:                                           \
+        if constexpr (use_col3<q>()) return col3_p<q>(a, s, e0, e1); \
         return col_p<q, COL_CONV, 4, false>(a, s, e0, e1);
             MM_CASES(M)
 #undef M

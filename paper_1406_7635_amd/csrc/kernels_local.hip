@@ -71,10 +71,10 @@ hipError_t launch_twiddles(cf* tw, int pt, hipStream_t s) {
 // Stage combine m_s = m0 + dt sum a_j k_j (used when demag is off; with demag
 // the first FFT pass does it on the fly).
 __global__ void __launch_bounds__(NT) k_combine(const FieldArgs a) {
-    if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
+    const Resolved rs = resolve(a);
+    if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
     const long long i = (long long)blockIdx.x * NT + threadIdx.x;
     if (i >= a.ncell) return;
-    const Resolved rs = resolve(a);
     st3(a.ms, a.ncell, i, stage_state(a, rs, i));
 }
 
@@ -86,9 +86,9 @@ hipError_t launch_combine(const FieldArgs& a, hipStream_t s) {
 // Field pass without the magnetostatic term: one thread per cell.
 __global__ void __launch_bounds__(NT) k_local(const FieldArgs a) {
     __shared__ double red[(NT / 64) * 6];
-    if ((a.flags & EPI_CHECK_DONE) && a.st->done) return;
-    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
     const Resolved rs = resolve(a);
+    if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
     EpiAcc acc;
     epi_init(acc);
     if (i < a.ncell) {
@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(NT) k_local(const FieldArgs a) {
         const long long r = i / a.nx;
         const int y = (int)(r % a.ny), z = (int)(r / a.ny);
         const float* mp = a.sd.nk > 0 ? a.ms : a.m0;
-        epilogue(a, rs, mp, i, x, y, z, make_float3(0.f, 0.f, 0.f), acc);
+        epilogue(a, rs, a.lut, mp, i, x, y, z, make_float3(0.f, 0.f, 0.f), acc);
     }
     if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NT>(a, acc, red, blockIdx.x);
 }
