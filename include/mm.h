@@ -133,7 +133,8 @@ typedef struct {
  * pair table on the device.  Demag is enabled but needs mm_demag_kernel_init
  * before the first field evaluation.  Returns MM_EINVAL for null pointers,
  * non-positive sizes or non-finite cell sizes, MM_EUNSUPPORTED for padded
- * lengths above 4096 or non-zero pbc, MM_ENOMEM if allocation fails. */
+ * lengths above 4096, more than 2^28 cells or non-zero pbc, MM_ENOMEM if
+ * allocation fails. */
 int mm_create(mm_ctx **out, const mm_grid *g, const mm_params *p, const uint8_t *region_dev,
               void *hip_stream);
 

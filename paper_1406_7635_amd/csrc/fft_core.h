@@ -258,15 +258,22 @@ struct RegFft {
             write_r<PPT>(span(s - 1), v, f, buf, t);
     }
 
-    // read the inputs of stage s (>= 1) for sequence f and run its butterfly
-    __host__ __device__ static void read_compute(int s, cf (&v)[NF][PPT], int f, const cf* buf, int t,
-                                                 const cf (&wt)[PPT]) {
-        (void)s;
+    // read the inputs of stage s (>= 1) for sequence f
+    __host__ __device__ static void read(cf (&v)[NF][PPT], int f, const cf* buf, int t) {
 #pragma unroll
         for (int r = 0; r < PPT; ++r) v[f][r] = buf[lds_pad(t + r * TPF)];
+    }
+    // twiddle and butterfly of stage s (>= 1) for sequence f
+    __host__ __device__ static void compute(cf (&v)[NF][PPT], int f, const cf (&wt)[PPT]) {
 #pragma unroll
         for (int r = 1; r < PPT; ++r) v[f][r] = cmul(v[f][r], wt[r]);
         Dft<PPT, INV>::run(v[f]);
+    }
+    __host__ __device__ static void read_compute(int s, cf (&v)[NF][PPT], int f, const cf* buf, int t,
+                                                 const cf (&wt)[PPT]) {
+        (void)s;
+        read(v, f, buf, t);
+        compute(v, f, wt);
     }
 
     // stage order of the last stage -> natural order
@@ -285,6 +292,9 @@ struct RegFft {
         }
     }
 
+    // With NF > 1 the butterfly of sequence f - 1 runs between the LDS writes
+    // of sequence f and the barrier that publishes them, so it covers their
+    // latency and the wait at the barrier.
     __device__ static void run(cf (&v)[NF][PPT], cf* buf, const cf* __restrict__ tw, int twshift, int t) {
         if (NS == 0) return;
         stage0(v);
@@ -299,9 +309,11 @@ struct RegFft {
                     write_r<R0>(1, v, f, buf, t);
                 else
                     write_r<PPT>(span(s - 1), v, f, buf, t);
+                if (f > 0) compute(v, f - 1, wt);
                 __syncthreads();
-                read_compute(s, v, f, buf, t, wt);
+                read(v, f, buf, t);
             }
+            compute(v, NF - 1, wt);
         }
         finish(v);
     }

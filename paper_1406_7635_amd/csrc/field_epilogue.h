@@ -21,6 +21,29 @@ __device__ inline void st3(float* __restrict__ p, long long n, long long i, floa
     p[n + i] = v.y;
     p[2 * n + i] = v.z;
 }
+// Loads and stores through a uniform base and a 32-bit byte offset: an array
+// of 3 ncell floats (ncell <= 2^28) stays below 2^32 bytes, so every offset
+// fits, and the access takes the scalar-base + vector-offset form with no
+// 64-bit address arithmetic per lane.
+__device__ inline float ldo(const float* base, unsigned int off) {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + off);
+}
+__device__ inline void sto(float* base, unsigned int off, float v) {
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + off) = v;
+}
+// components at byte offsets off, off + n4, off + 2 n4 from one base (n4 =
+// 4 ncell; 3 ncell < 2^30 floats): one scalar base per array
+__device__ inline float3 ld3o(const float* p, long long n, unsigned int off) {
+    const unsigned int n4 = (unsigned int)n << 2;
+    return make_float3(ldo(p, off), ldo(p, off + n4), ldo(p, off + 2u * n4));
+}
+__device__ inline void st3o(float* p, long long n, unsigned int off, float3 v) {
+    const unsigned int n4 = (unsigned int)n << 2;
+    sto(p, off, v.x);
+    sto(p, off + n4, v.y);
+    sto(p, off + 2u * n4, v.z);
+}
+
 __device__ inline float3 f3add(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
 __device__ inline float3 f3sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
 __device__ inline float3 f3scale(float s, float3 a) { return make_float3(s * a.x, s * a.y, s * a.z); }
@@ -29,10 +52,8 @@ __device__ inline float3 f3cross(float3 a, float3 b) {
     return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 
-__device__ inline int pair_index(int a, int b) {
-    const int hi = a > b ? a : b, lo = a > b ? b : a;
-    return hi * (hi + 1) / 2 + lo;
-}
+// index of the region pair (a, b) in the square exchange-coefficient table
+__device__ inline int pair_index(int a, int b) { return (a << 8) | b; }
 
 // Stage-derivative pointers, dt and the done flag, read once per kernel from
 // the device-side solver state (the logical-to-physical buffer map changes on
@@ -84,20 +105,21 @@ __device__ inline float stage_comp(const FieldArgs& a, const Resolved& r, long l
     return m0 + r.dt * acc;
 }
 
-// Stage-state components at N positions, out[i] = m0[idx[i]] + dt sum_{j<NK}
-// a_j k_j[idx[i]], with NK a compile-time count so that every load of the
-// batch is issued before the first is used (no data-dependent branches).
+// Stage-state components at N positions given as byte offsets off[i] into the
+// [3][ncell] arrays: out[i] = m0 + dt sum_{j<NK} a_j k_j at off[i], with NK a
+// compile-time count so that every load of the batch is issued before the
+// first is used (no data-dependent branches).
 template <int NK, int N>
-__device__ inline void stage_batch_nk(const FieldArgs& a, const Resolved& r, const long long (&idx)[N],
+__device__ inline void stage_batch_nk(const FieldArgs& a, const Resolved& r, const unsigned int (&off)[N],
                                       float (&out)[N]) {
     float m0v[N];
     float kv[N][NK > 0 ? NK : 1];
 #pragma unroll
-    for (int i = 0; i < N; ++i) m0v[i] = a.m0[idx[i]];
+    for (int i = 0; i < N; ++i) m0v[i] = ldo(a.m0, off[i]);
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
-        for (int j = 0; j < NK; ++j) kv[i][j] = r.kin[j][idx[i]];
+        for (int j = 0; j < NK; ++j) kv[i][j] = ldo(r.kin[j], off[i]);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         float acc = 0.f;
@@ -108,16 +130,16 @@ __device__ inline void stage_batch_nk(const FieldArgs& a, const Resolved& r, con
 }
 
 template <int N>
-__device__ inline void stage_batch(const FieldArgs& a, const Resolved& r, const long long (&idx)[N],
+__device__ inline void stage_batch(const FieldArgs& a, const Resolved& r, const unsigned int (&off)[N],
                                    float (&out)[N]) {
     switch (a.sd.nk) {
-        case 0: stage_batch_nk<0>(a, r, idx, out); break;
-        case 1: stage_batch_nk<1>(a, r, idx, out); break;
-        case 2: stage_batch_nk<2>(a, r, idx, out); break;
-        case 3: stage_batch_nk<3>(a, r, idx, out); break;
-        case 4: stage_batch_nk<4>(a, r, idx, out); break;
-        case 5: stage_batch_nk<5>(a, r, idx, out); break;
-        default: stage_batch_nk<6>(a, r, idx, out); break;
+        case 0: stage_batch_nk<0>(a, r, off, out); break;
+        case 1: stage_batch_nk<1>(a, r, off, out); break;
+        case 2: stage_batch_nk<2>(a, r, off, out); break;
+        case 3: stage_batch_nk<3>(a, r, off, out); break;
+        case 4: stage_batch_nk<4>(a, r, off, out); break;
+        case 5: stage_batch_nk<5>(a, r, off, out); break;
+        default: stage_batch_nk<6>(a, r, off, out); break;
     }
 }
 
@@ -135,24 +157,26 @@ __device__ inline float3 stage_state(const FieldArgs& a, const Resolved& r, long
 __device__ inline float3 exchange_at(const FieldArgs& a, const float* __restrict__ mp, long long cell,
                                      int x, int y, int z, int r, float3 mc) {
     const long long n = a.ncell;
-    const long long sxy = (long long)a.nx * a.ny;
+    const int sxy = a.nx * a.ny;
     const bool use_y = a.ny > 1, use_z = a.nz > 1;
-    long long nb[6];
-    nb[0] = x > 0 ? cell - 1 : cell;
-    nb[1] = x < a.nx - 1 ? cell + 1 : cell;
-    nb[2] = y > 0 ? cell - a.nx : cell;
-    nb[3] = y < a.ny - 1 ? cell + a.nx : cell;
-    nb[4] = z > 0 ? cell - sxy : cell;
-    nb[5] = z < a.nz - 1 ? cell + sxy : cell;
+    int d[6];  // neighbour - cell, in cells
+    d[0] = x > 0 ? -1 : 0;
+    d[1] = x < a.nx - 1 ? 1 : 0;
+    d[2] = y > 0 ? -a.nx : 0;
+    d[3] = y < a.ny - 1 ? a.nx : 0;
+    d[4] = z > 0 ? -sxy : 0;
+    d[5] = z < a.nz - 1 ? sxy : 0;
     const float id2[3] = {a.idx2, a.idy2, a.idz2};
+    const unsigned int c = (unsigned int)cell;
     int rn[6];
     float3 mn[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         const bool use = i < 2 || (i < 4 ? use_y : use_z);
         if (use) {
-            rn[i] = a.region[nb[i]];
-            mn[i] = ld3(mp, n, nb[i]);
+            const unsigned int q = c + (unsigned int)d[i];
+            rn[i] = a.region[q];
+            mn[i] = ld3o(mp, n, q << 2);
         }
     }
     float3 b = make_float3(0.f, 0.f, 0.f);
@@ -183,17 +207,18 @@ __device__ inline void epilogue(const FieldArgs& a, const Resolved& rs, const Re
                                 const float* __restrict__ mp, long long cell, int x, int y, int z, float3 bd,
                                 EpiAcc& acc) {
     const int flags = a.flags;
-    const int r = a.region[cell];
+    const unsigned int c4 = (unsigned int)cell << 2;
+    const int r = a.region[(unsigned int)cell];
     const RegionLut L = lut[r];
     const long long n = a.ncell;
-    if (flags & EPI_BDEMAG) st3(a.bdemag, n, cell, bd);
+    if (flags & EPI_BDEMAG) st3o(a.bdemag, n, c4, bd);
     float3 tq = make_float3(0.f, 0.f, 0.f);
     if (L.a.x == 0.f) {  // non-magnetic cell: no field, no torque
-        if (flags & EPI_BEFF) st3(a.beff, n, cell, tq);
-        if (flags & EPI_TORQUE) st3(rs.kout, n, cell, tq);
+        if (flags & EPI_BEFF) st3o(a.beff, n, c4, tq);
+        if (flags & EPI_TORQUE) st3o(rs.kout, n, c4, tq);
         return;
     }
-    const float3 m = ld3(mp, n, cell);
+    const float3 m = ld3o(mp, n, c4);
     const float3 bex = exchange_at(a, mp, cell, x, y, z, r, m);
     const float3 u = make_float3(L.b.x, L.b.y, L.b.z);
     const float um = f3dot(u, m);
@@ -201,20 +226,20 @@ __device__ inline void epilogue(const FieldArgs& a, const Resolved& rs, const Re
     const float3 ban2 = f3scale(L.a.z * um * um * um, u);
     const float3 bz = make_float3(L.c.x, L.c.y, L.c.z);
     const float3 B = f3add(f3add(bd, bex), f3add(f3add(ban1, ban2), bz));
-    if (flags & EPI_BEFF) st3(a.beff, n, cell, B);
+    if (flags & EPI_BEFF) st3o(a.beff, n, c4, B);
     if (flags & (EPI_TORQUE | EPI_MAXTQ | EPI_ERR)) {
         const float3 mxb = f3cross(m, B);
         const float3 mxmxb = f3cross(m, mxb);
         const float alpha = L.a.w;
         tq = (flags & EPI_PRECESS) ? f3scale(L.b.w, f3add(mxb, f3scale(alpha, mxmxb)))
                                    : f3scale(L.b.w * alpha, mxmxb);
-        if (flags & EPI_TORQUE) st3(rs.kout, n, cell, tq);
+        if (flags & EPI_TORQUE) st3o(rs.kout, n, c4, tq);
         if (flags & EPI_MAXTQ) acc.tqmax = fmaxf(acc.tqmax, sqrtf(f3dot(tq, tq)));
         if (flags & EPI_ERR) {
             float3 kv[7];
 #pragma unroll
             for (int j = 0; j < 7; ++j)
-                if (j < a.sd.nerr) kv[j] = rs.ke[j] ? ld3(rs.ke[j], n, cell) : tq;
+                if (j < a.sd.nerr) kv[j] = rs.ke[j] ? ld3o(rs.ke[j], n, c4) : tq;
             float3 d = make_float3(0.f, 0.f, 0.f);
 #pragma unroll
             for (int j = 0; j < 7; ++j)

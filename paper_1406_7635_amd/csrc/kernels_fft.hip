@@ -82,17 +82,35 @@ __device__ inline void row_bases(const FieldArgs& a, int pair0, long long* rbs) 
     }
 }
 
-// Element u of a workgroup's staged half spectra [pair][kx][row][component]
-// (6 complex per kx) and its offset in the spectrum (-1: row past the grid).
-template <int KH>
-__device__ inline long long staged_offset(const FieldArgs& a, const long long* rbs, int u, int* lofs) {
-    const int gg = u / (KH * 6), rem = u - gg * (KH * 6);
-    const int k = rem / 6, rc = rem - 6 * k;
-    const int h = rc >= 3 ? 1 : 0;
-    *lofs = rem;
-    const long long rb = rbs[2 * gg + h];
-    return rb < 0 ? -1 : rb + (long long)k * a.colstride + (rc - 3 * h);
-}
+// Cooperative copy between a workgroup's staged half spectra
+// [pair][kx][row][component] (6 complex per kx) in LDS and the spectrum:
+// thread tid handles the elements u = tid + NTH i.  NTH is a multiple of 6, so
+// the (row, component) of a thread's elements is fixed and kx advances by
+// NTH/6 per step; offsets need no division per element.
+template <int P>
+struct Staged {
+    static constexpr int GI = XCfg<P>::GI, NTH = XCfg<P>::NTH, KH = XCfg<P>::KH, GL = XCfg<P>::GL;
+    static constexpr int TOT = GI * KH * 6, NIT = (TOT + NTH - 1) / NTH, KS = NTH / 6;
+    static_assert(NTH % 6 == 0, "workgroup size must be a multiple of 6");
+    int comp, h, kq0;
+    __device__ explicit Staged(int tid) {
+        const int rc = tid % 6;
+        h = rc >= 3 ? 1 : 0;
+        comp = rc - 3 * h;
+        kq0 = tid / 6;
+    }
+    // element i of the thread: LDS index, and spectrum offset (-1: no element,
+    // or its row is past the grid)
+    __device__ void at(const FieldArgs& a, const long long* rbs, int i, int& lidx, long long& off) const {
+        const int kq = kq0 + KS * i;
+        const int gg = GI == 1 ? 0 : kq / KH;
+        const int k = kq - gg * KH;
+        lidx = gg * GL + 6 * k + 3 * h + comp;
+        const bool in = i < NIT - 1 || kq < GI * KH;
+        const long long rb = rbs[2 * gg + h];
+        off = (in && rb >= 0) ? rb + (long long)k * a.colstride + comp : -1;
+    }
+};
 
 // ---------------------------------------------------------------------------
 template <int P>
@@ -139,15 +157,15 @@ k_xfwd(const FieldArgs a) {
     cf v[1][PPT];
 #pragma unroll
     for (int m = MV; m < PPT; ++m) v[0][m] = mkc(0.f, 0.f);
-    long long idx0[MV], idx1[MV];
+    unsigned int idx0[MV], idx1[MV];  // byte offsets into the [3][ncell] arrays
     int g0[MV], g1[MV];
 #pragma unroll
     for (int m = 0; m < MV; ++m) {
         const int x = t + TPF * m;
         const int xc = x < a.nx ? x : a.nx - 1;
-        const long long cell0 = (long long)r0c * a.nx + xc, cell1 = (long long)r1c * a.nx + xc;
-        idx0[m] = c0 * n + cell0;
-        idx1[m] = c1 * n + cell1;
+        const unsigned int cell0 = (unsigned int)(r0c * a.nx + xc), cell1 = (unsigned int)(r1c * a.nx + xc);
+        idx0[m] = (c0 * (unsigned int)n + cell0) << 2;
+        idx1[m] = (c1 * (unsigned int)n + cell1) << 2;
         g0[m] = a.region[cell0];
         g1[m] = a.region[cell1];
     }
@@ -171,10 +189,9 @@ k_xfwd(const FieldArgs a) {
     for (int m = 0; m < MV; ++m) {
         const int x = t + TPF * m;
         const bool in = x < a.nx;
-        const long long cell0 = (long long)r0c * a.nx + x, cell1 = (long long)r1c * a.nx + x;
         if (a.sd.nk > 0) {
-            if (in && v0) a.ms[c0 * n + cell0] = sv[m];
-            if (in && v1) a.ms[c1 * n + cell1] = sv[MV + m];
+            if (in && v0) sto(a.ms, idx0[m], sv[m]);
+            if (in && v1) sto(a.ms, idx1[m], sv[MV + m]);
         }
         const float re = (in && v0) ? msat_l[g0[m]] * sv[m] : 0.f;
         const float im = (in && v1) ? msat_l[g1[m]] * sv[MV + m] : 0.f;
@@ -213,14 +230,13 @@ k_xfwd(const FieldArgs a) {
         }
     }
     __syncthreads();
-    constexpr int TOT = GI * KH * 6, NIT = (TOT + NTH - 1) / NTH;
+    const Staged<P> sc(tid);
 #pragma unroll
-    for (int i = 0; i < NIT; ++i) {
-        const int u = tid + NTH * i;
-        if (i == NIT - 1 && u >= TOT) break;  // only the last round is partial
-        int lofs;
-        const long long off = staged_offset<KH>(a, rbs, u, &lofs);
-        if (off >= 0) a.spec[off] = lds[(u / (KH * 6)) * GL + lofs];
+    for (int i = 0; i < Staged<P>::NIT; ++i) {
+        int li;
+        long long off;
+        sc.at(a, rbs, i, li, off);
+        if (off >= 0) a.spec[off] = lds[li];
     }
 }
 
@@ -624,22 +640,19 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
 
     // read the half spectra of the row pairs in contiguous runs into
     // [kx][row][component]: every load of the thread first, then the LDS writes
-    constexpr int TOT = GI * KH * 6, NIT = (TOT + NTH - 1) / NTH;
+    const Staged<P> sc(tid);
+    constexpr int NIT = Staged<P>::NIT;
     cf tmp[NIT];
+    int li[NIT];
 #pragma unroll
     for (int i = 0; i < NIT; ++i) {
-        const int u = tid + NTH * i;
-        const bool in = i < NIT - 1 || u < TOT;  // only the last round is partial
-        int lofs;
-        const long long off = staged_offset<KH>(a, rbs, in ? u : 0, &lofs);
-        tmp[i] = (in && off >= 0) ? a.spec[off] : mkc(0.f, 0.f);
+        long long off;
+        sc.at(a, rbs, i, li[i], off);
+        tmp[i] = off >= 0 ? a.spec[off] : mkc(0.f, 0.f);
     }
 #pragma unroll
-    for (int i = 0; i < NIT; ++i) {
-        const int u = tid + NTH * i;
-        if (i == NIT - 1 && u >= TOT) break;
-        lds[(u / (KH * 6)) * GL + (u % (KH * 6))] = tmp[i];
-    }
+    for (int i = 0; i < NIT; ++i)
+        if (i < NIT - 1 || sc.kq0 + Staged<P>::KS * i < Staged<P>::GI * KH) lds[li[i]] = tmp[i];
 #pragma unroll
     for (int i = 0; i < NLI; ++i)
         if (tid + NTH * i < NL4) reinterpret_cast<float4*>(lut_l)[tid + NTH * i] = lt[i];

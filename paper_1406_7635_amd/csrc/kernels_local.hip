@@ -11,9 +11,11 @@ namespace mm {
 // Region tables (section "Material Regions") from the FP64 parameters.
 // lut: anisotropy prefactors 2 Ku1/Msat and 4 Ku2/Msat (the paper prints
 // B_sat; Msat is the reading with units of tesla), torque prefactor
-// -gamma/(1+alpha^2).  ptab: per region pair (i >= j, packed i(i+1)/2 + j)
-// the exchange coefficient 2 S(i,j) 2 l_i l_j/(l_i + l_j), l = Aex/Msat, of
-// Eq. eqBexch; S(i,i) = 1; 0 when either region is non-magnetic.
+// -gamma/(1+alpha^2).  ptab: for every ordered region pair (i, j), at
+// i * NREG + j, the exchange coefficient 2 S(i,j) 2 l_i l_j/(l_i + l_j),
+// l = Aex/Msat, of Eq. eqBexch (S from the packed lower triangle
+// max(i,j)(max(i,j)+1)/2 + min(i,j); S(i,i) = 1); 0 when either region is
+// non-magnetic.  The square layout makes the lookup a shift and an or.
 __global__ void k_prepare_tables(const mm_params* __restrict__ p, RegionLut* __restrict__ lut,
                                  float* __restrict__ ptab) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -30,16 +32,14 @@ __global__ void k_prepare_tables(const mm_params* __restrict__ p, RegionLut* __r
         L.c = make_float4((float)p->bext[i][0], (float)p->bext[i][1], (float)p->bext[i][2], 0.f);
         lut[i] = L;
     }
-    if (i < NPAIR) {
-        int hi = (int)floor((sqrt(8.0 * i + 1.0) - 1.0) * 0.5);
-        while (hi * (hi + 1) / 2 > i) --hi;
-        while ((hi + 1) * (hi + 2) / 2 <= i) ++hi;
-        const int lo = i - hi * (hi + 1) / 2;
+    if (i < NREG * NREG) {
+        const int r1 = i / NREG, r2 = i % NREG;
+        const int hi = r1 > r2 ? r1 : r2, lo = r1 > r2 ? r2 : r1;
         const double m1 = p->msat[hi], m2 = p->msat[lo];
         double c = 0.0;
         if (m1 > 0.0 && m2 > 0.0) {
             const double l1 = p->aex[hi] / m1, l2 = p->aex[lo] / m2;
-            const double s = (hi == lo) ? 1.0 : p->exch_scale[i];
+            const double s = (hi == lo) ? 1.0 : p->exch_scale[hi * (hi + 1) / 2 + lo];
             if (l1 + l2 > 0.0) c = 2.0 * s * (2.0 * l1 * l2 / (l1 + l2));
         }
         ptab[i] = (float)c;
@@ -47,7 +47,7 @@ __global__ void k_prepare_tables(const mm_params* __restrict__ p, RegionLut* __r
 }
 
 hipError_t launch_prepare_tables(const double* params64, RegionLut* lut, float* ptab, hipStream_t s) {
-    hipLaunchKernelGGL(k_prepare_tables, dim3((NPAIR + 255) / 256), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_prepare_tables, dim3((NREG * NREG + 255) / 256), dim3(256), 0, s,
                        reinterpret_cast<const mm_params*>(params64), lut, ptab);
     return hipGetLastError();
 }

@@ -429,6 +429,8 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
     if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->dz)) return MM_EINVAL;
     if (g->pbc[0] || g->pbc[1] || g->pbc[2]) return MM_EUNSUPPORTED;
     if (g->nx > 2048 || g->ny > 2048 || g->nz > 2048) return MM_EUNSUPPORTED;
+    // one component array must stay below 2^30 bytes (32-bit offsets in the kernels)
+    if ((long long)g->nx * g->ny * g->nz > (1LL << 28)) return MM_EUNSUPPORTED;
     MM_CHECK(validate_params(p));
     mm_ctx* c = new (std::nothrow) mm_ctx();
     if (!c) return MM_ENOMEM;
@@ -473,7 +475,7 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
     A((void**)&c->region, (size_t)c->ncell);
     A((void**)&c->params64, sizeof(mm_params));
     A((void**)&c->lut, NREG * sizeof(RegionLut));
-    A((void**)&c->ptab, NPAIR * sizeof(float));
+    A((void**)&c->ptab, (size_t)NREG * NREG * sizeof(float));
     A((void**)&c->tw, (size_t)c->pt * sizeof(cf));
     A((void**)&c->spec, (size_t)c->spec_elems * sizeof(cf));
     A((void**)&c->khat, (size_t)c->khat_elems * sizeof(float));

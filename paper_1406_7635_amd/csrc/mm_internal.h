@@ -10,6 +10,7 @@ namespace mm {
 
 constexpr int NREG = 256;
 constexpr int NPAIR = NREG * (NREG + 1) / 2;
+static_assert(NREG == 256, "the square exchange table index packs a region in 8 bits");
 constexpr int NT = 256;            // threads per workgroup of every field kernel
 constexpr int MAXK = 7;            // stage-derivative buffers (Dormand-Prince needs 7)
 constexpr double MU0 = 4.0e-7 * 3.14159265358979323846;
