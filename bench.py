@@ -77,19 +77,41 @@ def column_pass_bytes(ctx):
     return 2 * spec + khat
 
 
-def xinv_pass_bytes(ctx):
-    """x-inverse + field/torque pass: read spectrum, m_s and region; write torque."""
+def spectrum_bytes(ctx):
+    """Half spectrum of the three components (complex64 per (kx, y, z))."""
     info = ctx.info()
     nx, ny, nz = ctx.grid
-    return 3 * 8 * info["kx"] * ny * nz + (12 + 1 + 12) * nx * ny * nz
+    return 3 * 8 * info["kx"] * ny * nz
 
 
-def xfwd_pass_bytes(ctx, avg_k_reads):
-    """x-forward pass: read m0, region and the stage derivatives, write m_s and spectrum."""
-    info = ctx.info()
-    nx, ny, nz = ctx.grid
-    n = nx * ny * nz
-    return (12 + 1 + 12 * avg_k_reads + 12) * n + 3 * 8 * info["kx"] * ny * nz
+def xinv_pass_bytes(ctx, k_reads):
+    """x-inverse + field/torque pass of the last stage: read the spectrum, m_s,
+    the region map and k_reads stage derivatives (error norm); write the torque."""
+    n = int(np.prod(ctx.grid))
+    return spectrum_bytes(ctx) + (12 + 1 + 12 * k_reads + 12) * n
+
+
+def xfwd_pass_bytes(ctx, k_reads):
+    """x-forward pass: read m0, the region map and k_reads stage derivatives,
+    write m_s and the spectrum."""
+    n = int(np.prod(ctx.grid))
+    return (12 + 1 + 12 * k_reads + 12) * n + spectrum_bytes(ctx)
+
+
+def xrow_pass_bytes(ctx, k_reads):
+    """Fused x-inverse of stage s + x-forward of stage s+1: read the spectrum,
+    m_s, the region map, m0 and k_reads derivatives (k_s itself stays on chip);
+    write k_s, m_{s+1} and the spectrum."""
+    n = int(np.prod(ctx.grid))
+    return 2 * spectrum_bytes(ctx) + (12 + 1 + 12 + 12 + 12 * k_reads + 12) * n
+
+
+# Dormand-Prince 5(4) per attempt: the first x-forward combines k0 only, the
+# five fused passes read 1, 2, 3, 4, 4 earlier derivatives from HBM (the last
+# term of each combine is the one just computed), and the error norm of the
+# last stage reads 5 derivatives (e_1 = 0; e_6 multiplies the torque just
+# computed).
+DP45_XROW_K = (1 + 2 + 3 + 4 + 4) / 5.0
 
 
 def cpu_baseline(case, budget_s=12.0):
@@ -164,19 +186,20 @@ def main():
     # the same number of attempts again with every field-pass launch recording a
     # HIP event pair at its own start and end (on the context stream): the
     # per-kernel durations behind the roofline figures
-    for k in range(3):
+    names = ("x_forward", "column_conv", "x_inverse", "x_row")
+    for k in range(len(names)):
         ctx.timing_enable(k)
     t, dt, st2 = ctx.run(m, float("inf"), t=t, dt=dt, max_attempts=args.steps, opts=opts)
     torch.cuda.synchronize()
     per = {}
-    for k, name in enumerate(("x_forward", "column_conv", "x_inverse")):
+    for k, name in enumerate(names):
         n, ms = ctx.timing_read(k)
-        per[name] = {"launches": n, "avg_us": 1e3 * ms / max(n, 1), "total_ms": ms}
         ctx.timing_enable(k, False)
+        if n:
+            per[name] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms": ms}
     dominant = max(per, key=lambda k: per[k]["total_ms"])
-    avg_k = 20.0 / 6.0  # stage-derivative reads per evaluation in RK45 (20 over 6 stages)
-    bytes_per_launch = {"x_forward": xfwd_pass_bytes(ctx, avg_k), "column_conv": column_pass_bytes(ctx),
-                        "x_inverse": xinv_pass_bytes(ctx)}
+    bytes_per_launch = {"x_forward": xfwd_pass_bytes(ctx, 1), "column_conv": column_pass_bytes(ctx),
+                        "x_inverse": xinv_pass_bytes(ctx, 5), "x_row": xrow_pass_bytes(ctx, DP45_XROW_K)}
     for k in per:
         per[k]["alg_bytes"] = bytes_per_launch[k]
         per[k]["gbs"] = bytes_per_launch[k] / (per[k]["avg_us"] * 1e-6) / 1e9

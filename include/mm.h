@@ -238,7 +238,8 @@ int mm_exchange_dump(mm_ctx *c, float *out_dev);
 /* Kernel timing with HIP events on the context stream.  mm_timing_enable(c,
  * which, 1) has every later launch of kernel class `which` (0 = x-forward FFT
  * pass, 1 = column (y/z) convolution pass, 2 = x-inverse FFT + field/torque
- * pass) record an event pair at the start and end of the kernel itself (3D:
+ * pass, 3 = fused x-inverse of one Runge-Kutta stage and x-forward of the
+ * next) record an event pair at the start and end of the kernel itself (3D:
  * from the start of the y-forward to the end of the y-inverse launch); the
  * event pairs are created by this call.  mm_timing_read returns the number of
  * launches and the summed milliseconds since enabling (synchronises).

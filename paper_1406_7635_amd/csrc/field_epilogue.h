@@ -202,8 +202,9 @@ __device__ inline void epi_init(EpiAcc& acc) {
 }
 
 // Everything after the magnetostatic field for one cell.
-// lut: the region table (global memory, or a copy in LDS).
-__device__ inline void epilogue(const FieldArgs& a, const Resolved& rs, const RegionLut* lut,
+// lut: the region table (global memory, or a copy in LDS).  Returns the
+// torque (zero in non-magnetic cells; only meaningful with EPI_TORQUE).
+__device__ inline float3 epilogue(const FieldArgs& a, const Resolved& rs, const RegionLut* lut,
                                 const float* __restrict__ mp, long long cell, int x, int y, int z, float3 bd,
                                 EpiAcc& acc) {
     const int flags = a.flags;
@@ -216,7 +217,7 @@ __device__ inline void epilogue(const FieldArgs& a, const Resolved& rs, const Re
     if (L.a.x == 0.f) {  // non-magnetic cell: no field, no torque
         if (flags & EPI_BEFF) st3o(a.beff, n, c4, tq);
         if (flags & EPI_TORQUE) st3o(rs.kout, n, c4, tq);
-        return;
+        return tq;
     }
     const float3 m = ld3o(mp, n, c4);
     const float3 bex = exchange_at(a, mp, cell, x, y, z, r, m);
@@ -256,6 +257,7 @@ __device__ inline void epilogue(const FieldArgs& a, const Resolved& rs, const Re
         acc.e[2] += -0.5 * dot(ban1) - 0.25 * dot(ban2);
         acc.e[3] += -dot(bz);
     }
+    return tq;
 }
 
 // Workgroup reductions ------------------------------------------------------
@@ -291,17 +293,20 @@ __device__ inline void epi_reduce(const FieldArgs& a, EpiAcc& acc, double* red, 
     if (threadIdx.x == 0) {
         if (flags & EPI_ERR) {
             float e = 0.f;
+#pragma unroll 1
             for (int w = 0; w < NW; ++w) e = fmaxf(e, (float)red[w * 6 + 4]);
             atomicMax(&a.st->err_bits, __float_as_uint(e));
         }
         if (flags & EPI_MAXTQ) {
             float t = 0.f;
+#pragma unroll 1
             for (int w = 0; w < NW; ++w) t = fmaxf(t, (float)red[w * 6 + 5]);
             atomicMax(&a.st->tq_bits, __float_as_uint(t));
         }
         if (flags & EPI_ENERGY) {
             for (int i = 0; i < 4; ++i) {
                 double s = 0.0;
+#pragma unroll 1
                 for (int w = 0; w < NW; ++w) s += red[w * 6 + i];
                 a.partials[(long long)blk * 4 + i] = s;
             }

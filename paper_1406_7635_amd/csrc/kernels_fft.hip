@@ -113,22 +113,53 @@ struct Staged {
 };
 
 // ---------------------------------------------------------------------------
+// x passes.  Both stage the region table in LDS after the row-pair area.
 template <int P>
-__global__ void __launch_bounds__(XCfg<P>::NTH)
-k_xfwd(const FieldArgs a) {
-    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI, NTH = XCfg<P>::NTH;
-    constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL, KH = XCfg<P>::KH;
+struct XLut {
+    static constexpr int NTH = XCfg<P>::NTH;
+    static constexpr int NL4 = NREG * (int)(sizeof(RegionLut) / sizeof(float4));
+    static constexpr int NLI = (NL4 + NTH - 1) / NTH;
+    float4 lt[NLI];
+    __device__ void load(const FieldArgs& a, int tid) {
+#pragma unroll
+        for (int i = 0; i < NLI; ++i)
+            lt[i] = tid + NTH * i < NL4 ? reinterpret_cast<const float4*>(a.lut)[tid + NTH * i]
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __device__ void store(RegionLut* lut_l, int tid) const {
+#pragma unroll
+        for (int i = 0; i < NLI; ++i)
+            if (tid + NTH * i < NL4) reinterpret_cast<float4*>(lut_l)[tid + NTH * i] = lt[i];
+    }
+};
+
+// In the fused pass the torque of the finished stage is handed to the next
+// stage's combine through LDS: component c of a row pair's two rows ([row][x],
+// floats) in the upper half of slot buffer c, which the x-inverse results
+// (x < nx <= P/2, the lower half) leave free.  Needs P >= 2.
+template <int P>
+__device__ inline float* ks_stage(cf* gbuf, int c) {
+    return reinterpret_cast<float*>(gbuf + c * seq_len(P) + seq_len(P) / 2);
+}
+
+// Forward x pass of one workgroup: stage combine m_s = m0 + dt sum a k (FUSED:
+// plus dt a_last k_last, k_last from LDS), M = Msat[region] m_s, FFT of the
+// zero-padded rows, separation of the two real transforms, staged coalesced
+// spectrum write.  The region table is in LDS at lut_l once the first barrier
+// has passed (the non-fused pass writes it from lut after issuing its loads).
+template <int P, bool FUSED>
+__device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
+                                 RegionLut* lut_l, const XLut<P>* lut, float a_last) {
+    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI;
+    constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL;
     constexpr int MH = PPT / 2 + 1;
-    extern __shared__ cf lds[];
-    __shared__ long long rbs[2 * GI];
-    const Resolved rs = resolve(a);
-    if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    // in the fused pass, derive every index afresh here (nothing of the first
+    // part stays live across the boundary)
+    if constexpr (FUSED) asm volatile("" : "+v"(tid)::"memory");
     const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int pair0 = blk * GI;
+    const int pair0 = xcd_remap(blockIdx.x, gridDim.x) * GI;
     const int pair = pair0 + g;
-    row_bases<GI>(a, pair0, rbs);
     const int ra = 2 * pair, rb = ra + 1;
     const bool va = ra < a.nrows, vb = rb < a.nrows;
     cf* gbuf = lds + g * GL;
@@ -142,17 +173,12 @@ k_xfwd(const FieldArgs a) {
     const int r1 = slot == 0 ? ra : rb;
     const bool v1 = slot == 0 ? va : vb;
     const int c1 = slot == 2 ? 2 : 1;
+    const int rr0 = slot == 1 ? 1 : 0, rr1 = slot == 0 ? 0 : 1;  // rows within the pair
 
     // Only x < P/2 can hold cells (P >= 2 nx - 1); rows and columns past the
     // grid are clamped for the loads and masked afterwards, so every load of
-    // the thread is issued before the first one is used.  Msat of the 256
-    // regions is staged in LDS meanwhile (no dependent region -> table load).
+    // the thread is issued before the first one is used.
     constexpr int MV = PPT > 1 ? PPT / 2 : 1;
-    float* msat_l = reinterpret_cast<float*>(lds + GI * GL);
-    constexpr int NMS = (NREG + NTH - 1) / NTH;
-    float msv[NMS];
-#pragma unroll
-    for (int i = 0; i < NMS; ++i) msv[i] = tid + NTH * i < NREG ? a.lut[tid + NTH * i].a.x : 0.f;
     const int r0c = v0 ? r0 : 0, r1c = v1 ? r1 : 0;
     cf v[1][PPT];
 #pragma unroll
@@ -181,20 +207,33 @@ k_xfwd(const FieldArgs a) {
             sv[MV + m] = s1[m];
         }
     }
+    if constexpr (FUSED) {
+        // the last term of the combine, k of the stage the x-inverse part of
+        // this workgroup just finished (after the barrier that published it)
+        const float* k0 = ks_stage<P>(gbuf, c0);
+        const float* k1 = ks_stage<P>(gbuf, c1);
+        const float w = rs.dt * a_last;
 #pragma unroll
-    for (int i = 0; i < NMS; ++i)
-        if (tid + NTH * i < NREG) msat_l[tid + NTH * i] = msv[i];
-    __syncthreads();
+        for (int m = 0; m < MV; ++m) {
+            const int x = t + TPF * m;
+            const int xc = x < a.nx ? x : a.nx - 1;
+            sv[m] += w * k0[rr0 * a.nx + xc];
+            sv[MV + m] += w * k1[rr1 * a.nx + xc];
+        }
+    } else {
+        lut->store(lut_l, tid);
+        __syncthreads();
+    }
 #pragma unroll
     for (int m = 0; m < MV; ++m) {
         const int x = t + TPF * m;
         const bool in = x < a.nx;
-        if (a.sd.nk > 0) {
+        if (a.sd.nk > 0 || FUSED) {
             if (in && v0) sto(a.ms, idx0[m], sv[m]);
             if (in && v1) sto(a.ms, idx1[m], sv[MV + m]);
         }
-        const float re = (in && v0) ? msat_l[g0[m]] * sv[m] : 0.f;
-        const float im = (in && v1) ? msat_l[g1[m]] * sv[MV + m] : 0.f;
+        const float re = (in && v0) ? lut_l[g0[m]].a.x * sv[m] : 0.f;
+        const float im = (in && v1) ? lut_l[g1[m]].a.x * sv[MV + m] : 0.f;
         v[0][m] = mkc(re, im);
     }
     // x >= nx is zero padding (nx <= P/2)
@@ -238,6 +277,154 @@ k_xfwd(const FieldArgs a) {
         sc.at(a, rbs, i, li, off);
         if (off >= 0) a.spec[off] = lds[li];
     }
+}
+
+// Inverse x pass of one workgroup: staged coalesced spectrum read, Hermitian
+// extension, inverse FFT, crop, per-cell epilogue (FUSED: the torque also to
+// LDS for the next stage's combine), reductions.  The region table goes to
+// LDS at lut_l.
+template <int P, bool FUSED>
+__device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
+                                 RegionLut* lut_l, double* red) {
+    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI, NTH = XCfg<P>::NTH;
+    constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL;
+    constexpr int MH = PPT / 2 + 1;
+    const int tid = threadIdx.x;
+    const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int pair0 = blk * GI;
+    cf* gbuf = lds + g * GL;
+    cf* buf = gbuf + slot * SEQ;
+
+    XLut<P> lut;
+    lut.load(a, tid);
+    // read the half spectra of the row pairs in contiguous runs into
+    // [kx][row][component]: every load of the thread first, then the LDS writes
+    const Staged<P> sc(tid);
+    constexpr int NIT = Staged<P>::NIT;
+    cf tmp[NIT];
+    int li[NIT];
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        long long off;
+        sc.at(a, rbs, i, li[i], off);
+        tmp[i] = off >= 0 ? a.spec[off] : mkc(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < NIT; ++i)
+        if (i < NIT - 1 || sc.kq0 + Staged<P>::KS * i < Staged<P>::GI * XCfg<P>::KH) lds[li[i]] = tmp[i];
+    lut.store(lut_l, tid);
+    __syncthreads();
+    // slot s = u + i w (slot 0: x, y of row a; slot 1: x, y of row b; slot 2: z of
+    // rows a and b); the DC and Nyquist bins of a real signal are real
+    const int iu = slot == 2 ? 2 : slot * 3, iw = slot == 2 ? 5 : slot * 3 + 1;
+    cf U[MH], W[MH];
+#pragma unroll
+    for (int m = 0; m < MH; ++m) {
+        const int k = t + TPF * m;
+        const int kc = 2 * k <= P ? k : 0;
+        U[m] = gbuf[kc * 6 + iu];
+        W[m] = gbuf[kc * 6 + iw];
+        if (k == 0 || 2 * k == P) {
+            U[m].y = 0.f;
+            W[m].y = 0.f;
+        }
+    }
+    __syncthreads();
+    // Hermitian extension: Z[k] = u + i w, Z[P-k] = conj u + i conj w for k <= P/2
+#pragma unroll
+    for (int m = 0; m < MH; ++m) {
+        const int k = t + TPF * m;
+        if (2 * k > P) continue;
+        const cf u = U[m], w = W[m];
+        buf[lds_pad(k)] = mkc(u.x - w.y, u.y + w.x);
+        if (k != 0 && 2 * k != P) buf[lds_pad(P - k)] = mkc(u.x + w.y, w.x - u.y);
+    }
+    __syncthreads();
+    cf v[1][PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) v[0][m] = buf[lds_pad(t + TPF * m)];
+    RegFft<P, TPF, 1, true>::run(v, buf, a.tw, a.twshift, t);
+    // only x < nx <= P/2 is kept
+    constexpr int MOUT = P >= 2 ? PPT / 2 : PPT;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MOUT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
+    __syncthreads();
+
+    // per-cell epilogue over the 2 GI rows of this workgroup
+    EpiAcc acc;
+    epi_init(acc);
+    const float* mp = a.sd.nk > 0 || FUSED ? a.ms : a.m0;
+    for (int idx = tid; idx < 2 * GI * a.nx; idx += NTH) {
+        const int rr = idx / a.nx, x = idx - rr * a.nx;
+        const int row = 2 * pair0 + rr;
+        if (row >= a.nrows) continue;
+        cf* b3 = lds + (rr >> 1) * GL;
+        const cf v01 = b3[(rr & 1) * SEQ + lds_pad(x)];
+        const cf v2 = b3[2 * SEQ + lds_pad(x)];
+        const int z = row / a.ny, y = row - z * a.ny;
+        const float3 tq = epilogue(a, rs, lut_l, mp, (long long)row * a.nx + x, x, y, z,
+                                   make_float3(v01.x, v01.y, (rr & 1) ? v2.y : v2.x), acc);
+        if constexpr (FUSED) {
+            const int o = (rr & 1) * a.nx + x;
+            ks_stage<P>(b3, 0)[o] = tq.x;
+            ks_stage<P>(b3, 1)[o] = tq.y;
+            ks_stage<P>(b3, 2)[o] = tq.z;
+        }
+    }
+    // the fused pass serves inner stages only (no error norm, no reductions)
+    if constexpr (!FUSED)
+        if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NTH>(a, acc, red, blk);
+}
+
+template <int P>
+__global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
+    constexpr int GI = XCfg<P>::GI, GL = XCfg<P>::GL;
+    extern __shared__ cf lds[];
+    __shared__ long long rbs[2 * GI];
+    const Resolved rs = resolve(a);
+    if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
+    row_bases<GI>(a, xcd_remap(blockIdx.x, gridDim.x) * GI, rbs);
+    XLut<P> lut;
+    lut.load(a, threadIdx.x);
+    xfwd_part<P, false>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), &lut, 0.f);
+}
+
+template <int P>
+__global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
+    constexpr int GI = XCfg<P>::GI, GL = XCfg<P>::GL, NTH = XCfg<P>::NTH;
+    extern __shared__ cf lds[];
+    __shared__ double red[(NTH / 64 > 0 ? NTH / 64 : 1) * 6];
+    __shared__ long long rbs[2 * GI];
+    const Resolved rs = resolve(a);
+    if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
+    row_bases<GI>(a, xcd_remap(blockIdx.x, gridDim.x) * GI, rbs);
+    __syncthreads();
+    xinv_part<P, false>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), red);
+}
+
+// Fused pass: the x-inverse of stage s (torque k_s, read m_s from ai.ms)
+// followed, row pair by row pair, by the x-forward of stage s + 1 (combine
+// with k_s from LDS as the last term, m_{s+1} to af.ms, a second buffer since
+// other workgroups still read m_s for the exchange field).
+template <int P>
+__global__ void __launch_bounds__(XCfg<P>::NTH) __attribute__((amdgpu_waves_per_eu(6)))
+k_xrow(const FieldArgs ai, const FieldArgs af, float a_last) {
+    constexpr int GI = XCfg<P>::GI, GL = XCfg<P>::GL, NTH = XCfg<P>::NTH;
+    extern __shared__ cf lds[];
+    __shared__ double red[(NTH / 64 > 0 ? NTH / 64 : 1) * 6];
+    __shared__ long long rbs[2 * GI];
+    const Resolved rsi = resolve(ai);
+    if ((ai.flags & EPI_CHECK_DONE) && rsi.done) return;
+    row_bases<GI>(ai, xcd_remap(blockIdx.x, gridDim.x) * GI, rbs);
+    __syncthreads();
+    RegionLut* lut_l = reinterpret_cast<RegionLut*>(lds + GI * GL);
+    xinv_part<P, true>(ai, rsi, lds, rbs, lut_l, red);
+    __syncthreads();
+    // the next stage's pointers only now (short live ranges across the first part)
+    const Resolved rsf = resolve(af);
+    xfwd_part<P, true>(af, rsf, lds, rbs, lut_l, nullptr, a_last);
 }
 
 // ---------------------------------------------------------------------------
@@ -610,109 +797,6 @@ __global__ void __launch_bounds__(Col3Cfg<P>::NTH, 4) k_col3(const ColArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-template <int P>
-__global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
-    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI, NTH = XCfg<P>::NTH;
-    constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL, KH = XCfg<P>::KH;
-    constexpr int MH = PPT / 2 + 1;
-    extern __shared__ cf lds[];
-    __shared__ double red[(NTH / 64 > 0 ? NTH / 64 : 1) * 6];
-    __shared__ long long rbs[2 * GI];
-    const Resolved rs = resolve(a);
-    if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
-    const int tid = threadIdx.x;
-    const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int pair0 = blk * GI;
-    cf* gbuf = lds + g * GL;
-    cf* buf = gbuf + slot * SEQ;
-    row_bases<GI>(a, pair0, rbs);
-    __syncthreads();
-
-    // the region table goes to LDS (after the row-pair area) for the epilogue
-    RegionLut* lut_l = reinterpret_cast<RegionLut*>(lds + GI * GL);
-    constexpr int NL4 = NREG * (int)(sizeof(RegionLut) / sizeof(float4)), NLI = (NL4 + NTH - 1) / NTH;
-    float4 lt[NLI];
-#pragma unroll
-    for (int i = 0; i < NLI; ++i)
-        lt[i] = tid + NTH * i < NL4 ? reinterpret_cast<const float4*>(a.lut)[tid + NTH * i]
-                                    : make_float4(0.f, 0.f, 0.f, 0.f);
-
-    // read the half spectra of the row pairs in contiguous runs into
-    // [kx][row][component]: every load of the thread first, then the LDS writes
-    const Staged<P> sc(tid);
-    constexpr int NIT = Staged<P>::NIT;
-    cf tmp[NIT];
-    int li[NIT];
-#pragma unroll
-    for (int i = 0; i < NIT; ++i) {
-        long long off;
-        sc.at(a, rbs, i, li[i], off);
-        tmp[i] = off >= 0 ? a.spec[off] : mkc(0.f, 0.f);
-    }
-#pragma unroll
-    for (int i = 0; i < NIT; ++i)
-        if (i < NIT - 1 || sc.kq0 + Staged<P>::KS * i < Staged<P>::GI * KH) lds[li[i]] = tmp[i];
-#pragma unroll
-    for (int i = 0; i < NLI; ++i)
-        if (tid + NTH * i < NL4) reinterpret_cast<float4*>(lut_l)[tid + NTH * i] = lt[i];
-    __syncthreads();
-    // slot s = u + i w (slot 0: x, y of row a; slot 1: x, y of row b; slot 2: z of
-    // rows a and b); the DC and Nyquist bins of a real signal are real
-    const int iu = slot == 2 ? 2 : slot * 3, iw = slot == 2 ? 5 : slot * 3 + 1;
-    cf U[MH], W[MH];
-#pragma unroll
-    for (int m = 0; m < MH; ++m) {
-        const int k = t + TPF * m;
-        const int kc = 2 * k <= P ? k : 0;
-        U[m] = gbuf[kc * 6 + iu];
-        W[m] = gbuf[kc * 6 + iw];
-        if (k == 0 || 2 * k == P) {
-            U[m].y = 0.f;
-            W[m].y = 0.f;
-        }
-    }
-    __syncthreads();
-    // Hermitian extension: Z[k] = u + i w, Z[P-k] = conj u + i conj w for k <= P/2
-#pragma unroll
-    for (int m = 0; m < MH; ++m) {
-        const int k = t + TPF * m;
-        if (2 * k > P) continue;
-        const cf u = U[m], w = W[m];
-        buf[lds_pad(k)] = mkc(u.x - w.y, u.y + w.x);
-        if (k != 0 && 2 * k != P) buf[lds_pad(P - k)] = mkc(u.x + w.y, w.x - u.y);
-    }
-    __syncthreads();
-    cf v[1][PPT];
-#pragma unroll
-    for (int m = 0; m < PPT; ++m) v[0][m] = buf[lds_pad(t + TPF * m)];
-    RegFft<P, TPF, 1, true>::run(v, buf, a.tw, a.twshift, t);
-    // only x < nx <= P/2 is kept
-    constexpr int MOUT = P >= 2 ? PPT / 2 : PPT;
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < MOUT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
-    __syncthreads();
-
-    // per-cell epilogue over the 2 GI rows of this workgroup
-    EpiAcc acc;
-    epi_init(acc);
-    const float* mp = a.sd.nk > 0 ? a.ms : a.m0;
-    for (int idx = tid; idx < 2 * GI * a.nx; idx += NTH) {
-        const int rr = idx / a.nx, x = idx - rr * a.nx;
-        const int row = 2 * pair0 + rr;
-        if (row >= a.nrows) continue;
-        const cf* b3 = lds + (rr >> 1) * GL;
-        const cf v01 = b3[(rr & 1) * SEQ + lds_pad(x)];
-        const cf v2 = b3[2 * SEQ + lds_pad(x)];
-        const int z = row / a.ny, y = row - z * a.ny;
-        epilogue(a, rs, lut_l, mp, (long long)row * a.nx + x, x, y, z,
-                 make_float3(v01.x, v01.y, (rr & 1) ? v2.y : v2.x), acc);
-    }
-    if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NTH>(a, acc, red, blk);
-}
-
-// ---------------------------------------------------------------------------
 // Launch helpers: dispatch the run-time padded length to a template instance.
 
 // Dynamic LDS of each pass (bytes per workgroup).
@@ -745,6 +829,15 @@ static hipError_t xinv_p(const FieldArgs& a, hipStream_t s, int* nb_out, hipEven
     const int nb = x_blocks<P>(a.nrows);
     if (nb_out) *nb_out = nb;
     hipExtLaunchKernelGGL((k_xinv<P>), dim3(nb), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0, a);
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t xrow_p(const FieldArgs& ai, const FieldArgs& af, float a_last, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
+    const size_t lds = x_lds<P>();
+    hipExtLaunchKernelGGL((k_xrow<P>), dim3(x_blocks<P>(ai.nrows)), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0,
+                          ai, af, a_last);
     return hipGetLastError();
 }
 
@@ -782,6 +875,8 @@ template <int P>
 static hipError_t configure_x(void) {
     hipError_t e = allow_lds<P>((const void*)k_xfwd<P>, x_lds<P>());
     if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P>, x_lds<P>());
+    if constexpr (P >= 8)
+        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P>, x_lds<P>());
     return e;
 }
 
@@ -855,6 +950,20 @@ hipError_t launch_xfwd(int px, const FieldArgs& a, hipStream_t s, hipEvent_t e0,
 #define M(p) \
     case p:  \
         return xfwd_p<p>(a, s, e0, e1);
+        MM_CASES(M)
+#undef M
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_xrow(int px, const FieldArgs& ai, const FieldArgs& af, float a_last, hipStream_t s,
+                       hipEvent_t e0, hipEvent_t e1) {
+    switch (px) {
+#define M(p)                                                                       \
+    case p:                                                                        \
+        if constexpr (p >= 8) return xrow_p<p>(ai, af, a_last, s, e0, e1);          \
+        return hipErrorInvalidValue;
         MM_CASES(M)
 #undef M
         default:

@@ -22,6 +22,8 @@ struct TimingClass {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
 };
 constexpr size_t TIMING_POOL = 4096;
+// launch classes: 0 x-forward, 1 column passes, 2 x-inverse, 3 fused x-inverse + x-forward
+constexpr int NTIMING = 4;
 
 // Butcher tableaux (section "Dynamics"): row s holds a_{s+1, j}, j <= s.
 struct Tableau {
@@ -116,7 +118,8 @@ struct mm_ctx {
     cf* spec = nullptr;
     float* khat = nullptr;
     float* kbuf = nullptr;
-    float* ms = nullptr;
+    float* ms = nullptr;   // stage state
+    float* ms2 = nullptr;  // second stage-state buffer of the fused passes
     DevState* st = nullptr;
     double* partials = nullptr;
     DevState* hst = nullptr;  // pinned host mirror of st
@@ -125,7 +128,7 @@ struct mm_ctx {
     const float* fsal_m = nullptr;
     int fsal_precess = -1;
     int fsal_solver = 0;
-    TimingClass timing[3];
+    TimingClass timing[NTIMING];
 };
 
 namespace {
@@ -138,7 +141,7 @@ hipError_t dalloc(mm_ctx* c, void** p, size_t bytes) {
 
 void free_all(mm_ctx* c) {
     void* ptrs[] = {c->region, c->params64, c->lut, c->ptab, c->tw, c->spec,
-                    c->khat,   c->kbuf,     c->ms,  c->st,   c->partials};
+                    c->khat,   c->kbuf,     c->ms,  c->ms2,  c->st, c->partials};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hst) (void)hipHostFree(c->hst);
@@ -203,79 +206,90 @@ struct Timed {
     }
 };
 
+// The column (y / z) passes between the two x passes of a field evaluation.
+int run_cols(mm_ctx* c, bool check_done) {
+    hipStream_t s = c->stream;
+    ColArgs ca;
+    memset(&ca, 0, sizeof(ca));
+    ca.spec = c->spec;
+    ca.tw = c->tw;
+    ca.twshift = c->twshift;
+    ca.st = c->st;
+    ca.check_done = check_done ? 1 : 0;
+    ca.khat = c->khat;
+    ca.kyh = c->py / 2 + 1;
+    ca.kzh = c->pz / 2 + 1;
+    ca.pa = c->py;
+    Timed t(c, 1);
+    if (c->pz > 1) {
+        // y transforms of every (z, kx) column, in place (ny rows -> py rows)
+        ca.pos_stride = 3;
+        ca.col_stride = c->colstride;
+        ca.ncol = c->kx;
+        ca.outer_stride = c->zstride;
+        ca.nouter = c->nz;
+        const bool ypass = c->py > 1;
+        if (ypass) {
+            ca.n_in = c->ny;
+            ca.n_out = c->py;
+            MM_TRY(launch_col(c->py, COL_FWD, ca, 6, s, t.e1, nullptr));
+        }
+        // z convolution of every (kx, ky) column; tiles of adjacent ky
+        ca.pos_stride = c->zstride;
+        ca.col_stride = 3;
+        ca.ncol = c->py;
+        ca.outer_stride = c->colstride;
+        ca.nouter = c->kx;
+        ca.n_in = c->nz;
+        ca.n_out = c->nz;
+        MM_TRY(launch_col(c->pz, COL_CONV, ca, 6, s, ypass ? nullptr : t.e1, ypass ? nullptr : t.e2));
+        if (ypass) {
+            ca.pos_stride = 3;
+            ca.col_stride = c->colstride;
+            ca.ncol = c->kx;
+            ca.outer_stride = c->zstride;
+            ca.nouter = c->nz;
+            ca.n_in = c->py;
+            ca.n_out = c->ny;
+            MM_TRY(launch_col(c->py, COL_INV, ca, 6, s, nullptr, t.e2));
+        }
+    } else {
+        // 2D: y convolution of every kx column; the DC and Nyquist columns
+        // (both real along y) share the first workgroup
+        ca.pos_stride = 3;
+        ca.col_stride = c->colstride;
+        ca.ncol = c->px >= 2 ? c->px / 2 : 1;
+        ca.pack_col = c->px >= 2 ? c->px / 2 : 0;
+        ca.outer_stride = 0;
+        ca.nouter = 1;
+        ca.n_in = c->ny;
+        ca.n_out = c->ny;
+        MM_TRY(launch_col(c->py, COL_CONV, ca, 4, s, t.e1, t.e2));
+    }
+    return MM_OK;
+}
+
+int run_xfwd(mm_ctx* c, const FieldArgs& a) {
+    Timed t(c, 0);
+    MM_TRY(launch_xfwd(c->px, a, c->stream, t.e1, t.e2));
+    return MM_OK;
+}
+
+int run_xinv(mm_ctx* c, const FieldArgs& a, int* nblocks_out) {
+    Timed t(c, 2);
+    MM_TRY(launch_xinv(c->px, a, c->stream, nblocks_out, t.e1, t.e2));
+    return MM_OK;
+}
+
 // One field evaluation (section "Landau-Lifshitz torque": B_eff and torque).
 int run_field(mm_ctx* c, FieldArgs& a, int* nblocks_out) {
     hipStream_t s = c->stream;
     if (c->demag_on) {
         if (!c->khat_ready) return MM_ESTATE;
         a.flags |= EPI_HAS_DEMAG;
-        {
-            Timed t(c, 0);
-            MM_TRY(launch_xfwd(c->px, a, s, t.e1, t.e2));
-        }
-        ColArgs ca;
-        memset(&ca, 0, sizeof(ca));
-        ca.spec = c->spec;
-        ca.tw = c->tw;
-        ca.twshift = c->twshift;
-        ca.st = c->st;
-        ca.check_done = (a.flags & EPI_CHECK_DONE) ? 1 : 0;
-        ca.khat = c->khat;
-        ca.kyh = c->py / 2 + 1;
-        ca.kzh = c->pz / 2 + 1;
-        ca.pa = c->py;
-        {
-            Timed t(c, 1);
-            if (c->pz > 1) {
-                // y transforms of every (z, kx) column, in place (ny rows -> py rows)
-                ca.pos_stride = 3;
-                ca.col_stride = c->colstride;
-                ca.ncol = c->kx;
-                ca.outer_stride = c->zstride;
-                ca.nouter = c->nz;
-                const bool ypass = c->py > 1;
-                if (ypass) {
-                    ca.n_in = c->ny;
-                    ca.n_out = c->py;
-                    MM_TRY(launch_col(c->py, COL_FWD, ca, 6, s, t.e1, nullptr));
-                }
-                // z convolution of every (kx, ky) column; tiles of adjacent ky
-                ca.pos_stride = c->zstride;
-                ca.col_stride = 3;
-                ca.ncol = c->py;
-                ca.outer_stride = c->colstride;
-                ca.nouter = c->kx;
-                ca.n_in = c->nz;
-                ca.n_out = c->nz;
-                MM_TRY(launch_col(c->pz, COL_CONV, ca, 6, s, ypass ? nullptr : t.e1, ypass ? nullptr : t.e2));
-                if (ypass) {
-                    ca.pos_stride = 3;
-                    ca.col_stride = c->colstride;
-                    ca.ncol = c->kx;
-                    ca.outer_stride = c->zstride;
-                    ca.nouter = c->nz;
-                    ca.n_in = c->py;
-                    ca.n_out = c->ny;
-                    MM_TRY(launch_col(c->py, COL_INV, ca, 6, s, nullptr, t.e2));
-                }
-            } else {
-                // 2D: y convolution of every kx column; the DC and Nyquist columns
-                // (both real along y) share the first workgroup
-                ca.pos_stride = 3;
-                ca.col_stride = c->colstride;
-                ca.ncol = c->px >= 2 ? c->px / 2 : 1;
-                ca.pack_col = c->px >= 2 ? c->px / 2 : 0;
-                ca.outer_stride = 0;
-                ca.nouter = 1;
-                ca.n_in = c->ny;
-                ca.n_out = c->ny;
-                MM_TRY(launch_col(c->py, COL_CONV, ca, 4, s, t.e1, t.e2));
-            }
-        }
-        {
-            Timed t(c, 2);
-            MM_TRY(launch_xinv(c->px, a, s, nblocks_out, t.e1, t.e2));
-        }
+        MM_CHECK(run_xfwd(c, a));
+        MM_CHECK(run_cols(c, (a.flags & EPI_CHECK_DONE) != 0));
+        MM_CHECK(run_xinv(c, a, nblocks_out));
     } else {
         if (a.sd.nk > 0) MM_TRY(launch_combine(a, s));
         MM_TRY(launch_local(a, s, nblocks_out));
@@ -315,35 +329,84 @@ int eval_first(mm_ctx* c, const float* m, int precess) {
     return run_field(c, a, nullptr);
 }
 
+// Field arguments of stage s of tableau tb: combine over the non-zero a_sj,
+// torque into logical derivative s, error norm on the last stage.
+FieldArgs stage_args(mm_ctx* c, float* m, const Tableau& tb, int s, int precess, bool check_done) {
+    const int S = tb.stages;
+    FieldArgs a = base_args(c, m);
+    StageDesc& sd = a.sd;
+    sd.nk = 0;
+    for (int j = 0; j < s; ++j)
+        if (tb.a[s][j] != 0.0) {
+            sd.kidx[sd.nk] = j;
+            sd.a[sd.nk] = (float)tb.a[s][j];
+            ++sd.nk;
+        }
+    sd.out_k = s;
+    a.flags = EPI_TORQUE | (precess ? EPI_PRECESS : 0) | (check_done ? EPI_CHECK_DONE : 0);
+    if (s == S - 1) {
+        sd.nerr = 0;
+        for (int j = 0; j < S; ++j)
+            if (tb.e[j] != 0.0) {
+                sd.eidx[sd.nerr] = j;
+                sd.e[sd.nerr] = (float)tb.e[j];
+                ++sd.nerr;
+            }
+        a.flags |= EPI_ERR;
+    }
+    return a;
+}
+
 // One attempt of an embedded pair: stages 2..S, controller, finalisation.
+// With the magnetostatic term (and px >= 8) the x-inverse pass of every inner
+// stage and the x-forward pass of the next one run as one fused pass; the
+// stage state then alternates between two buffers.
 int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done) {
     const int S = tb.stages;
-    for (int s = 1; s < S; ++s) {
-        FieldArgs a = base_args(c, m);
-        StageDesc& sd = a.sd;
-        sd.nk = 0;
-        for (int j = 0; j < s; ++j)
-            if (tb.a[s][j] != 0.0) {
-                sd.kidx[sd.nk] = j;
-                sd.a[sd.nk] = (float)tb.a[s][j];
-                ++sd.nk;
+    float* fin_ms = c->ms;
+    if (c->demag_on && c->px >= 8 && S > 2) {
+        if (!c->khat_ready) return MM_ESTATE;
+        float* buf[2] = {c->ms, c->ms2};
+        int cur = 0;
+        FieldArgs a = stage_args(c, m, tb, 1, precess, check_done);
+        a.flags |= EPI_HAS_DEMAG;
+        a.ms = buf[cur];
+        MM_CHECK(run_xfwd(c, a));
+        MM_CHECK(run_cols(c, check_done));
+        for (int s = 1; s < S - 1; ++s) {
+            FieldArgs ai = stage_args(c, m, tb, s, precess, check_done);
+            ai.flags |= EPI_HAS_DEMAG;
+            ai.ms = buf[cur];
+            FieldArgs af = stage_args(c, m, tb, s + 1, precess, check_done);
+            af.flags |= EPI_HAS_DEMAG;
+            af.ms = buf[cur ^ 1];
+            // the k_s term (always the last one listed) comes from the fused pass
+            float a_last = 0.f;
+            if (af.sd.nk > 0 && af.sd.kidx[af.sd.nk - 1] == s) {
+                a_last = af.sd.a[af.sd.nk - 1];
+                --af.sd.nk;
             }
-        sd.out_k = s;
-        a.flags = EPI_TORQUE | (precess ? EPI_PRECESS : 0) | (check_done ? EPI_CHECK_DONE : 0);
-        if (s == S - 1) {
-            sd.nerr = 0;
-            for (int j = 0; j < S; ++j)
-                if (tb.e[j] != 0.0) {
-                    sd.eidx[sd.nerr] = j;
-                    sd.e[sd.nerr] = (float)tb.e[j];
-                    ++sd.nerr;
-                }
-            a.flags |= EPI_ERR;
+            {
+                Timed t(c, 3);
+                MM_TRY(launch_xrow(c->px, ai, af, a_last, c->stream, t.e1, t.e2));
+            }
+            cur ^= 1;
+            MM_CHECK(run_cols(c, check_done));
         }
-        MM_CHECK(run_field(c, a, nullptr));
+        FieldArgs al = stage_args(c, m, tb, S - 1, precess, check_done);
+        al.flags |= EPI_HAS_DEMAG;
+        al.ms = buf[cur];
+        MM_CHECK(run_xinv(c, al, nullptr));
+        fin_ms = buf[cur];
+    } else {
+        for (int s = 1; s < S; ++s) {
+            FieldArgs a = stage_args(c, m, tb, s, precess, check_done);
+            MM_CHECK(run_field(c, a, nullptr));
+        }
     }
     MM_TRY(launch_controller(c->st, S - 1, S - 1, check_done ? 1 : 0, c->stream));
     FieldArgs f = base_args(c, m);
+    f.ms = fin_ms;
     MM_TRY(launch_finalize(f, c->stream));
     return MM_OK;
 }
@@ -481,6 +544,7 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
     A((void**)&c->khat, (size_t)c->khat_elems * sizeof(float));
     A((void**)&c->kbuf, (size_t)MAXK * 3 * c->ncell * sizeof(float));
     A((void**)&c->ms, (size_t)3 * c->ncell * sizeof(float));
+    A((void**)&c->ms2, (size_t)3 * c->ncell * sizeof(float));
     A((void**)&c->st, sizeof(DevState));
     A((void**)&c->partials, (size_t)maxblk * 4 * sizeof(double));
     if (st == MM_OK && hipHostMalloc((void**)&c->hst, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
@@ -774,7 +838,7 @@ int mm_exchange_dump(mm_ctx* c, float* out_dev) {
 }
 
 int mm_timing_enable(mm_ctx* c, int32_t which, int32_t enable) {
-    if (!c || which < 0 || which > 2) return MM_EINVAL;
+    if (!c || which < 0 || which >= NTIMING) return MM_EINVAL;
     TimingClass& t = c->timing[which];
     MM_TRY(hipStreamSynchronize(c->stream));
     t.used = 0;
@@ -800,7 +864,7 @@ int mm_timing_enable(mm_ctx* c, int32_t which, int32_t enable) {
 }
 
 int mm_timing_read(mm_ctx* c, int32_t which, int64_t* launches, double* total_ms) {
-    if (!c || which < 0 || which > 2 || !launches || !total_ms) return MM_EINVAL;
+    if (!c || which < 0 || which >= NTIMING || !launches || !total_ms) return MM_EINVAL;
     MM_TRY(hipStreamSynchronize(c->stream));
     double tot = 0.0;
     const TimingClass& t = c->timing[which];

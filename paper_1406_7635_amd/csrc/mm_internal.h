@@ -111,6 +111,12 @@ hipError_t launch_xinv(int px, const FieldArgs& a, hipStream_t s, int* nblocks_o
                        hipEvent_t e1 = nullptr);
 hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t s, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
+// Fused x-inverse of one stage and x-forward of the next (px >= 8): ai is the
+// finishing stage (reads m_s from ai.ms), af the next one (its combine holds
+// every term but the last, a_last k_s, which comes from the finishing stage;
+// m_{s+1} goes to af.ms, which must differ from ai.ms).
+hipError_t launch_xrow(int px, const FieldArgs& ai, const FieldArgs& af, float a_last, hipStream_t s,
+                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 int xinv_blocks(int px, int nrows);
 // Raise the dynamic-LDS limit of every pass a grid of padded size px x py x pz
 // launches (once per context, on the current device).
