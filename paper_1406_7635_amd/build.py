@@ -21,7 +21,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
-SOURCES = ["kernels_fft.hip", "kernels_local.hip", "kernels_demag.hip", "mm_api.cpp"]
+SOURCES = ["kernels_fft.hip", "kernels_mfma.hip", "kernels_local.hip", "kernels_demag.hip", "mm_api.cpp"]
 
 
 def _compile(src):

@@ -120,6 +120,8 @@ struct mm_ctx {
     float* kbuf = nullptr;
     float* ms = nullptr;   // stage state
     float* ms2 = nullptr;  // second stage-state buffer of the fused passes
+    void* dft_tab = nullptr;  // split DFT matrices of the matrix-core y convolution
+    int conv_prec = MM_PREC_FP32;
     DevState* st = nullptr;
     double* partials = nullptr;
     DevState* hst = nullptr;  // pinned host mirror of st
@@ -141,7 +143,7 @@ hipError_t dalloc(mm_ctx* c, void** p, size_t bytes) {
 
 void free_all(mm_ctx* c) {
     void* ptrs[] = {c->region, c->params64, c->lut, c->ptab, c->tw, c->spec,
-                    c->khat,   c->kbuf,     c->ms,  c->ms2,  c->st, c->partials};
+                    c->khat,   c->kbuf,     c->ms,  c->ms2,  c->st, c->partials, c->dft_tab};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hst) (void)hipHostFree(c->hst);
@@ -264,7 +266,12 @@ int run_cols(mm_ctx* c, bool check_done) {
         ca.nouter = 1;
         ca.n_in = c->ny;
         ca.n_out = c->ny;
-        MM_TRY(launch_col(c->py, COL_CONV, ca, 4, s, t.e1, t.e2));
+        if (c->conv_prec != MM_PREC_FP32) {
+            ca.dft_tab = c->dft_tab;
+            MM_TRY(launch_colm(c->py, c->conv_prec, ca, s, t.e1, t.e2));
+        } else {
+            MM_TRY(launch_col(c->py, COL_CONV, ca, 4, s, t.e1, t.e2));
+        }
     }
     return MM_OK;
 }
@@ -545,6 +552,7 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
     A((void**)&c->kbuf, (size_t)MAXK * 3 * c->ncell * sizeof(float));
     A((void**)&c->ms, (size_t)3 * c->ncell * sizeof(float));
     A((void**)&c->ms2, (size_t)3 * c->ncell * sizeof(float));
+    A((void**)&c->dft_tab, (size_t)2 * DFT_TABLE_BYTES);
     A((void**)&c->st, sizeof(DevState));
     A((void**)&c->partials, (size_t)maxblk * 4 * sizeof(double));
     if (st == MM_OK && hipHostMalloc((void**)&c->hst, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
@@ -555,6 +563,8 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
         if (e == hipSuccess) e = launch_prepare_tables(c->params64, c->lut, c->ptab, c->stream);
         if (e == hipSuccess) e = launch_twiddles(c->tw, c->pt, c->stream);
         if (e == hipSuccess) e = configure_field_kernels(c->px, c->py, c->pz);
+        if (e == hipSuccess) e = launch_dft_tables(c->dft_tab, c->stream);
+        if (e == hipSuccess) e = configure_colm();
         if (e == hipSuccess)
             e = launch_set_state(c->st, 0.0, 1e-14, INFINITY, 1e-5, 0.8, 0.0, 0.0, 4, 1, 1, 0, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -835,6 +845,16 @@ int mm_exchange_dump(mm_ctx* c, float* out_dev) {
     if (!c || !out_dev) return MM_EINVAL;
     FieldArgs a = base_args(c, nullptr);
     return map_err(launch_exchange_dump(a, out_dev, c->stream));
+}
+
+int mm_set_conv_precision(mm_ctx* c, int32_t prec) {
+    if (!c) return MM_EINVAL;
+    if (prec != MM_PREC_FP32 && prec != MM_PREC_BF16 && prec != MM_PREC_FP16) return MM_EINVAL;
+    if (prec != MM_PREC_FP32 && !(c->pz == 1 && c->py == 2048 && c->px >= 2)) return MM_EUNSUPPORTED;
+    MM_TRY(hipStreamSynchronize(c->stream));
+    c->conv_prec = prec;
+    c->fsal_valid = false;
+    return MM_OK;
 }
 
 int mm_timing_enable(mm_ctx* c, int32_t which, int32_t enable) {

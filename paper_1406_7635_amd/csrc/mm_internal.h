@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/mm.h"
 #include "fft_core.h"
 
 namespace mm {
@@ -100,6 +101,7 @@ struct ColArgs {
     int twshift;
     const DevState* st;
     int check_done;
+    const void* dft_tab;          // matrix-core variant: split DFT matrices of its precision
 };
 
 // ---- launchers (kernels_fft.hip) -------------------------------------------
@@ -111,6 +113,15 @@ hipError_t launch_xinv(int px, const FieldArgs& a, hipStream_t s, int* nblocks_o
                        hipEvent_t e1 = nullptr);
 hipError_t launch_col(int p, int mode, const ColArgs& a, int ncomp, hipStream_t s, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
+// Matrix-core y convolution (2D, P = 2048) with split-precision DFT stages;
+// prec MM_PREC_BF16 / MM_PREC_FP16.  launch_dft_tables fills the per-context
+// table of split DFT matrices (2 x DFT_TABLE_BYTES).
+constexpr int DFT_TABLE_BYTES = 256 * 64;
+hipError_t launch_colm(int p, int prec, const ColArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
+hipError_t launch_dft_tables(void* tab, hipStream_t s);
+hipError_t configure_colm(void);
+
 // Fused x-inverse of one stage and x-forward of the next (px >= 8): ai is the
 // finishing stage (reads m_s from ai.ms), af the next one (its combine holds
 // every term but the last, a_last k_s, which comes from the finishing stage;

@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MM_LIBRARY") or os.path.join(_HERE, "libmm.so")
 NREG = 256
 NPAIR = NREG * (NREG + 1) // 2
+PREC = {"fp32": 0, "bf16": 1, "fp16": 2}  # mm_precision
 
 c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
@@ -73,6 +74,7 @@ EXPORTS = {
     "mm_demag_tensor_dump": (c_int32, [c_void_p, c_void_p]),
     "mm_demag_kernel_dump": (c_int32, [c_void_p, c_void_p]),
     "mm_exchange_dump": (c_int32, [c_void_p, c_void_p]),
+    "mm_set_conv_precision": (c_int32, [c_void_p, c_int32]),
     "mm_timing_enable": (c_int32, [c_void_p, c_int32, c_int32]),
     "mm_timing_read": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int64), ctypes.POINTER(c_double)]),
     "mm_destroy": (None, [c_void_p]),
@@ -284,6 +286,12 @@ class Context:
         out = self._torch.empty((6, nz, ny, nx), dtype=self._torch.float32, device=self.device)
         _check(load().mm_exchange_dump(self._h, _ptr(out)), "mm_exchange_dump")
         return out
+
+    def set_conv_precision(self, prec):
+        """DFT arithmetic of the y convolution: 'fp32', or 'bf16' / 'fp16' split
+        precision on the matrix cores (2D grids with padded y length 2048)."""
+        _check(load().mm_set_conv_precision(self._h, PREC[prec] if isinstance(prec, str) else int(prec)),
+               "mm_set_conv_precision")
 
     def timing_enable(self, which, enable=True):
         _check(load().mm_timing_enable(self._h, int(which), 1 if enable else 0), "mm_timing_enable")
