@@ -134,6 +134,39 @@ def cpu_baseline(case, budget_s=12.0):
                       "%.1f s" % (n, case["grid"][0], case["grid"][1], case["grid"][2], el)}
 
 
+def mfma_variants(ctx, m, opts, ncell, steps):
+    """The same RK45 attempts with the y-convolution DFT stages on the matrix
+    cores (BF16 / FP16 split precision): throughput, column-pass duration and
+    the relative B_demag difference to the FP32 path at the current state (the
+    error against the FP64 oracle is established by the parity tests)."""
+    import torch
+
+    res = {}
+    ctx.set_conv_precision("fp32")
+    _, b32 = ctx.beff(m, want_demag=True)
+    b32 = b32.double()
+    for prec in ("bf16", "fp16"):
+        ctx.set_conv_precision(prec)
+        _, bd = ctx.beff(m, want_demag=True)
+        diff = float((bd.double() - b32).abs().max() / b32.abs().max())
+        mm_ = m.clone()
+        t, dt, _ = ctx.run(mm_, float("inf"), dt=1e-14, max_attempts=20, opts=opts)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        t, dt, st = ctx.run(mm_, float("inf"), t=t, dt=dt, max_attempts=steps, opts=opts)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ctx.timing_enable(1)
+        ctx.run(mm_, float("inf"), t=t, dt=dt, max_attempts=max(1, steps // 4), opts=opts)
+        n, ms = ctx.timing_read(1)
+        ctx.timing_enable(1, False)
+        res["mfma_" + prec] = {"value": ncell * st["evals"] / wall, "ms_per_step": 1e3 * wall / steps,
+                               "column_conv_avg_us": 1e3 * ms / max(n, 1), "demag_rel_diff_vs_fp32": diff,
+                               "dtype": prec + " split (hi*hi + hi*lo + lo*hi), f32 accumulate"}
+    ctx.set_conv_precision("fp32")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +252,7 @@ def main():
                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant},
         "kernels": per,
     }
+    out["variants"] = mfma_variants(ctx, m, opts, ncell, args.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     else:

@@ -112,7 +112,7 @@ constexpr int MPL = 2048 + 64;  // floats per plane
 
 struct ColmCfg {
     static constexpr int P = 2048;
-    static constexpr int NTH = 256;
+    static constexpr int NTH = 512;
     static constexpr int KHP = P / 2 + 1;
     // three components x (re, im) planes, then the K^ rows of the column
     static constexpr size_t LDS = 6 * MPL * sizeof(float) + KHP * sizeof(float4);
@@ -130,6 +130,33 @@ __device__ inline void dft_tile(float* re, float* im, int tile, const DftEntry<P
                                 int twsh, int lane, float scale) {
     const int c = lane & 15, g = lane >> 4, part = g >> 1, half = g & 1;
     const float* src = part ? im : re;
+    // output positions and twiddles of this lane's rows 4 g + r of column c;
+    // the twiddle loads go out first so their latency overlaps the GEMMs
+    constexpr bool TWID = STEP != (INV ? 1 : 3);
+    int pos[4];
+    cf wv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 4 * g + r;
+        int m = 0;  // twiddle exponent of w = exp(-2 pi i / 2048)
+        if (STEP == 1) {
+            const int q = tile * 16 + c;
+            pos[r] = pidx(128 * row + q);
+            m = q * row;
+        } else if (STEP == 2) {
+            const int v = tile * 16 + c, k1 = v >> 3, n3 = v & 7;
+            pos[r] = pidx(k1 * 128 + 8 * row + n3);
+            // forward: w^(16 n3 k2), k2 = row; inverse (before step 1'): w^-((8 n2 + n3) k1), n2 = row
+            m = INV ? (8 * row + n3) * k1 : 16 * n3 * row;
+        } else {
+            const int p = row >> 3, d = row & 7;
+            const int V = tile * 32 + 16 * p + c;
+            pos[r] = pidx(V * 8 + d);
+            // inverse (before step 2'): w^-(16 n3 k2), n3 = d, k2 = V % 16
+            m = 16 * d * (V & 15);
+        }
+        if (TWID) wv[r] = tw[(m & 2047) << twsh];
+    }
     // vector of this lane's column and the address of its digit d
     auto addr = [&](int d) -> int {
         if (STEP == 1) return pidx(128 * d + tile * 16 + c);
@@ -143,12 +170,13 @@ __device__ inline void dft_tile(float* re, float* im, int tile, const DftEntry<P
     if (STEP == 3) {
         const int V = tile * 32 + 16 * half + c;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = src[pidx(V * 8 + e)] * scale;
+        for (int e = 0; e < 8; ++e) x[e] = Low<PREC>::SCALE ? src[pidx(V * 8 + e)] * scale : src[pidx(V * 8 + e)];
     } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int d = 8 * half + e;
-            x[e] = (ZERO_HI && half) ? 0.f : src[addr(d)] * scale;
+            const float v = (ZERO_HI && half) ? 0.f : src[addr(d)];
+            x[e] = Low<PREC>::SCALE ? v * scale : v;
         }
     }
     typename Low<PREC>::T8 bh, bl;
@@ -164,35 +192,16 @@ __device__ inline void dft_tile(float* re, float* im, int tile, const DftEntry<P
     // lane holds output rows 4 g + r of column c
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int row = 4 * g + r;
         float vr = yr[r], vi = yi[r];
-        int pos, m = 0;  // position and twiddle exponent (of w = exp(-2 pi i / 2048))
-        if (STEP == 1) {
-            const int q = tile * 16 + c;
-            pos = pidx(128 * row + q);
-            if (!INV) m = q * row;
-        } else if (STEP == 2) {
-            const int v = tile * 16 + c, k1 = v >> 3, n3 = v & 7;
-            pos = pidx(k1 * 128 + 8 * row + n3);
-            // forward: w^(16 n3 k2), k2 = row; inverse (before step 1'): w^-((8 n2 + n3) k1), n2 = row
-            m = INV ? (8 * row + n3) * k1 : 16 * n3 * row;
-        } else {
-            const int p = row >> 3, d = row & 7;
-            const int V = tile * 32 + 16 * p + c;
-            pos = pidx(V * 8 + d);
-            // inverse (before step 2'): w^-(16 n3 k2), n3 = d, k2 = V % 16
-            if (INV) m = 16 * d * (V & 15);
-        }
-        if (STEP != (INV ? 1 : 3)) {
-            const cf w0 = tw[(m & 2047) << twsh];
-            const cf w = INV ? cconj(w0) : w0;
+        if (TWID) {
+            const cf w = INV ? cconj(wv[r]) : wv[r];
             const float tr = vr * w.x - vi * w.y;
             vi = vr * w.y + vi * w.x;
             vr = tr;
         }
-        if (INV && STEP == 1 && row >= 8) continue;  // rows y >= 1024 are cropped
-        re[pos] = vr;
-        im[pos] = vi;
+        if (INV && STEP == 1 && 4 * g + r >= 8) continue;  // rows y >= 1024 are cropped
+        re[pos[r]] = vr;
+        im[pos[r]] = vi;
     }
 }
 
