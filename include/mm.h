@@ -259,6 +259,74 @@ int mm_timing_read(mm_ctx *c, int32_t which, int64_t *launches, double *total_ms
 typedef enum { MM_PREC_FP32 = 0, MM_PREC_BF16 = 1, MM_PREC_FP16 = 2 } mm_precision;
 int mm_set_conv_precision(mm_ctx *c, int32_t prec);
 
+/* ---- Ensembles ------------------------------------------------------------
+ * An ensemble advances many independent grids together (each with its own
+ * size, cell size, region map, region tables, time step and solver state):
+ * every pass of a Runge-Kutta stage is one launch over the tiles of all
+ * members, the attempt is replayed as a HIP graph, and the number of
+ * persistent workgroups of each pass can be tuned on the device.  Per member
+ * the arithmetic is that of a single context (section "Magnetostatic field"
+ * for the convolution, section "Dynamics" and "Adaptive time step" for the
+ * solver); only the scheduling differs.
+ *
+ * Layout: the members' arrays are stored back to back in member order.  With
+ * ncell_i = nx_i ny_i nz_i and off_i = ncell_0 + ... + ncell_{i-1}, member i's
+ * region map is bytes [off_i, off_i + ncell_i) of the ensemble's uint8 region
+ * array and its vector fields (m, B_eff) are floats [3 off_i, 3 off_i +
+ * 3 ncell_i) of an FP32 array, [3][nz][ny][nx] within that range.
+ *
+ * Supported members: padded lengths 64 <= px, py <= 1024 (17 <= nx, ny <=
+ * 512) and nz <= 8; at most 65535 members.  Others give MM_EUNSUPPORTED.
+ * The ensemble works on a stream of its own; every call first waits for the
+ * work already enqueued on the stream given at creation, and that stream
+ * waits for the ensemble's work before anything enqueued on it later.
+ * mm_batch_run and mm_batch_stats synchronise. */
+typedef struct mm_batch mm_batch;
+
+/* grids[n], params[n] (host arrays); region_dev: the concatenated region maps
+ * (device, caller-owned, copied).  Allocates every buffer (the ensemble owns
+ * them until mm_batch_destroy) and builds each member's region tables.  The
+ * demagnetising kernels need mm_batch_demag_kernel_init. */
+int mm_batch_create(mm_batch **out, int32_t n, const mm_grid *grids, const mm_params *params,
+                    const uint8_t *region_dev, void *hip_stream);
+/* FP64 Newell tensors and FP32 kernel spectra of every member, as
+ * mm_demag_kernel_init does for one grid (synchronises). */
+int mm_batch_demag_kernel_init(mm_batch *b);
+/* Cell offset (off_i above) and cell count of member i. */
+int mm_batch_member(mm_batch *b, int32_t i, int64_t *cell_offset, int64_t *ncell);
+/* B_eff of every member at m_dev into beff_dev (both concatenated FP32). */
+int mm_batch_beff(mm_batch *b, const float *m_dev, float *beff_dev);
+/* (Re)start every member at time t0 with step dt0 towards t_end with the
+ * adaptive solver `solver` (45: Dormand-Prince, 23: Bogacki-Shampine):
+ * counters cleared, the first derivative recomputed by the next run. */
+int mm_batch_start(mm_batch *b, int32_t solver, double t0, double dt0, double t_end, const mm_solver_opts *o);
+/* Attempt steps of every running member (a member stops when it reaches
+ * t_end, or with an error status) until none runs or max_attempts attempts
+ * have been made.  m_dev: the concatenated states, updated in place.
+ * *attempts_out: attempts made; *active_out: members still running.
+ * Synchronises.  The stepping is device-controlled; every attempt is one
+ * replay of a captured graph when graphs are enabled (the default). */
+int mm_batch_run(mm_batch *b, float *m_dev, int64_t max_attempts, int64_t *attempts_out, int32_t *active_out);
+/* Counters, time and step of member i after the last run; its status in
+ * *status (MM_OK, MM_ENONFINITE or MM_ESTEP).  Synchronises. */
+int mm_batch_stats(mm_batch *b, int32_t i, mm_run_stats *out, int32_t *status);
+/* enable = 0: launch every kernel of an attempt directly instead of
+ * replaying a graph (same kernels, same results). */
+int mm_batch_set_graph(mm_batch *b, int32_t enable);
+/* Persistent workgroups of batched pass `pass` (0 x passes, 1 2D y
+ * convolution, 2 3D y transforms, 3/4/5 3D z convolution for padded z length
+ * 4/8/16, 6 finalisation): grid > 0 (rounded up to a multiple of 8), or 0 for
+ * one workgroup per tile.  mm_batch_get_grid reads the current value. */
+int mm_batch_set_grid(mm_batch *b, int32_t pass, int32_t grid);
+int mm_batch_get_grid(mm_batch *b, int32_t pass, int32_t *grid);
+/* Time every pass of one attempt at m_dev for a few persistent grid sizes
+ * (whole-chip multiples of the pass's resident workgroups, and one
+ * workgroup per tile) and keep the fastest.  Overwrites the stage buffers
+ * (the next run recomputes the first derivative); m_dev is only read.
+ * Synchronises. */
+int mm_batch_autotune(mm_batch *b, const float *m_dev);
+void mm_batch_destroy(mm_batch *b);
+
 void mm_destroy(mm_ctx *c);
 const char *mm_strerror(int status);
 

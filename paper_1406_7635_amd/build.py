@@ -21,7 +21,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
-SOURCES = ["kernels_fft.hip", "kernels_mfma.hip", "kernels_local.hip", "kernels_demag.hip", "mm_api.cpp"]
+SOURCES = ["kernels_fft.hip", "kernels_mfma.hip", "kernels_batch.hip", "kernels_local.hip", "kernels_demag.hip",
+           "mm_api.cpp", "mm_batch.cpp"]
 
 
 def _compile(src):

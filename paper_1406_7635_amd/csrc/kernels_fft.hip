@@ -1,382 +1,12 @@
-// kernels_fft.hip -- the FP32 magnetostatic convolution passes.
-//
-// Section "Magnetostatic field": B_demag = K * M evaluated with the
-// convolution theorem on a grid zero-padded to px x py x pz.
-//
-// Spectrum layout (complex64): element (z, kx, y, c) at
-//   z * zstride + kx * colstride + y * 3 + c,  colstride = 3 * ycount,
-// ycount = py in 3D (the y transforms run in place), ny in 2D.  Every column
-// along y is contiguous, so the column passes read and write whole columns.
-//
-// The three real components of two x-rows a, b travel as three complex
-// "slots": slot 0 = Mx_a + i My_a, slot 1 = Mx_b + i My_b, slot 2 = Mz_a + i Mz_b.
-// Each thread owns one slot (or one component in the column passes), so a
-// row pair or a column is spread over three thread groups.
-//
-// Passes:
-//   x-forward : one slot of one row pair per thread group: stage combine
-//               m_s = m0 + dt sum a k, M = Msat[region] m_s, FFT along x of
-//               the zero-padded rows, separation of the two real transforms
-//               X = (Z[k] + conj Z[P-k])/2, Y = (Z[k] - conj Z[P-k])/(2i);
-//   column    : per column, one thread group per component: FFT along y (3D:
-//               forward and inverse around the z pass), or forward FFT,
-//               B^_i = sum_j K^_ij M^_j through LDS (K^ real symmetric, one
-//               octant stored, mirror signs applied), inverse FFT.  In 2D the
-//               DC and Nyquist columns (both real along y) share one complex
-//               column;
-//   x-inverse : the three slots of a row pair: Hermitian extension, inverse
-//               FFT, crop, then the per-cell epilogue (exchange, anisotropy,
-//               Zeeman, torque, error norm, energies).
-// The 1/(px py pz) normalisation and -mu0 are folded into K^.
+// kernels_fft.hip -- the FP32 magnetostatic convolution passes of one grid:
+// the kernels around the device bodies of fft_passes.h, with a workgroup per
+// tile (the dispatch index mapped XCD-aware), and their launchers.
 #include <hip/hip_ext.h>
 
-#include "field_epilogue.h"
+#include "fft_passes.h"
 
 namespace mm {
 
-template <int P>
-struct Cfg {
-    static constexpr int PPT = P < 8 ? P : (P >= 4096 ? 16 : 8);  // points per thread
-    static constexpr int TPF = P / PPT;                           // threads per sequence
-    static constexpr int G = TPF >= 256 ? 1 : 256 / TPF;          // sequences per 256 threads
-};
-
-// x passes: the 3 slots of GI row pairs per workgroup.  GL = LDS elements per
-// row pair: the three exchange sequences, reused afterwards as the staging
-// area [kx][row][component] through which the spectrum is written / read in
-// contiguous runs (rows a, b are adjacent in the spectrum when a is even).
-template <int P>
-struct XCfg {
-    static constexpr int GI = Cfg<P>::TPF >= 256 ? 1 : (Cfg<P>::TPF >= 128 ? 2 : 256 / Cfg<P>::TPF);
-    static constexpr int NTH = 3 * GI * Cfg<P>::TPF;
-    static constexpr int KH = P / 2 + 1;
-    static constexpr int GL = 3 * seq_len(P) > 6 * KH ? 3 * seq_len(P) : 6 * KH;
-};
-
-// columns: the 3 components of T columns per workgroup
-template <int P>
-struct ColCfg {
-    static constexpr int T = Cfg<P>::TPF >= 256 ? 1 : (Cfg<P>::TPF >= 128 ? 2 : 256 / Cfg<P>::TPF);
-    static constexpr int NTH = 3 * T * Cfg<P>::TPF;
-};
-
-// 2D convolution: the K^ octant rows (xx, yy, zz, xy) of the workgroup's T
-// columns, staged in LDS after the exchange buffers (bytes)
-template <int P>
-constexpr size_t khat_lds() {
-    return (size_t)ColCfg<P>::T * (P / 2 + 1) * sizeof(float4);
-}
-
-__device__ inline long long row_base(const FieldArgs& a, int row) {
-    const int z = row / a.ny, y = row - z * a.ny;
-    return (long long)z * a.zstride + 3LL * y;
-}
-
-// Spectrum offsets of the 2 GI rows of a workgroup (-1 past the grid), into
-// LDS by the first threads; the cooperative copies read them after a barrier.
-template <int GI>
-__device__ inline void row_bases(const FieldArgs& a, int pair0, long long* rbs) {
-    if (threadIdx.x < 2 * GI) {
-        const int row = 2 * pair0 + (int)threadIdx.x;
-        rbs[threadIdx.x] = row < a.nrows ? row_base(a, row) : -1;
-    }
-}
-
-// Cooperative copy between a workgroup's staged half spectra
-// [pair][kx][row][component] (6 complex per kx) in LDS and the spectrum:
-// thread tid handles the elements u = tid + NTH i.  NTH is a multiple of 6, so
-// the (row, component) of a thread's elements is fixed and kx advances by
-// NTH/6 per step; offsets need no division per element.
-template <int P>
-struct Staged {
-    static constexpr int GI = XCfg<P>::GI, NTH = XCfg<P>::NTH, KH = XCfg<P>::KH, GL = XCfg<P>::GL;
-    static constexpr int TOT = GI * KH * 6, NIT = (TOT + NTH - 1) / NTH, KS = NTH / 6;
-    static_assert(NTH % 6 == 0, "workgroup size must be a multiple of 6");
-    int comp, h, kq0;
-    __device__ explicit Staged(int tid) {
-        const int rc = tid % 6;
-        h = rc >= 3 ? 1 : 0;
-        comp = rc - 3 * h;
-        kq0 = tid / 6;
-    }
-    // element i of the thread: LDS index, and spectrum offset (-1: no element,
-    // or its row is past the grid)
-    __device__ void at(const FieldArgs& a, const long long* rbs, int i, int& lidx, long long& off) const {
-        const int kq = kq0 + KS * i;
-        const int gg = GI == 1 ? 0 : kq / KH;
-        const int k = kq - gg * KH;
-        lidx = gg * GL + 6 * k + 3 * h + comp;
-        const bool in = i < NIT - 1 || kq < GI * KH;
-        const long long rb = rbs[2 * gg + h];
-        off = (in && rb >= 0) ? rb + (long long)k * a.colstride + comp : -1;
-    }
-};
-
-// ---------------------------------------------------------------------------
-// x passes.  Both stage the region table in LDS after the row-pair area.
-template <int P>
-struct XLut {
-    static constexpr int NTH = XCfg<P>::NTH;
-    static constexpr int NL4 = NREG * (int)(sizeof(RegionLut) / sizeof(float4));
-    static constexpr int NLI = (NL4 + NTH - 1) / NTH;
-    float4 lt[NLI];
-    __device__ void load(const FieldArgs& a, int tid) {
-#pragma unroll
-        for (int i = 0; i < NLI; ++i)
-            lt[i] = tid + NTH * i < NL4 ? reinterpret_cast<const float4*>(a.lut)[tid + NTH * i]
-                                        : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    __device__ void store(RegionLut* lut_l, int tid) const {
-#pragma unroll
-        for (int i = 0; i < NLI; ++i)
-            if (tid + NTH * i < NL4) reinterpret_cast<float4*>(lut_l)[tid + NTH * i] = lt[i];
-    }
-};
-
-// In the fused pass the torque of the finished stage is handed to the next
-// stage's combine through LDS: component c of a row pair's two rows ([row][x],
-// floats) in the upper half of slot buffer c, which the x-inverse results
-// (x < nx <= P/2, the lower half) leave free.  Needs P >= 2.
-template <int P>
-__device__ inline float* ks_stage(cf* gbuf, int c) {
-    return reinterpret_cast<float*>(gbuf + c * seq_len(P) + seq_len(P) / 2);
-}
-
-// Forward x pass of one workgroup: stage combine m_s = m0 + dt sum a k (FUSED:
-// plus dt a_last k_last, k_last from LDS), M = Msat[region] m_s, FFT of the
-// zero-padded rows, separation of the two real transforms, staged coalesced
-// spectrum write.  The region table is in LDS at lut_l once the first barrier
-// has passed (the non-fused pass writes it from lut after issuing its loads).
-template <int P, bool FUSED>
-__device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
-                                 RegionLut* lut_l, const XLut<P>* lut, float a_last) {
-    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI;
-    constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL;
-    constexpr int MH = PPT / 2 + 1;
-    int tid = threadIdx.x;
-    // in the fused pass, derive every index afresh here (nothing of the first
-    // part stays live across the boundary)
-    if constexpr (FUSED) asm volatile("" : "+v"(tid)::"memory");
-    const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
-    const int pair0 = xcd_remap(blockIdx.x, gridDim.x) * GI;
-    const int pair = pair0 + g;
-    const int ra = 2 * pair, rb = ra + 1;
-    const bool va = ra < a.nrows, vb = rb < a.nrows;
-    cf* gbuf = lds + g * GL;
-    cf* buf = gbuf + slot * SEQ;
-    const long long n = a.ncell;
-
-    // slot 0: (x, y) of row a, slot 1: (x, y) of row b, slot 2: z of rows a and b
-    const int r0 = slot == 1 ? rb : ra;
-    const bool v0 = slot == 1 ? vb : va;
-    const int c0 = slot == 2 ? 2 : 0;
-    const int r1 = slot == 0 ? ra : rb;
-    const bool v1 = slot == 0 ? va : vb;
-    const int c1 = slot == 2 ? 2 : 1;
-    const int rr0 = slot == 1 ? 1 : 0, rr1 = slot == 0 ? 0 : 1;  // rows within the pair
-
-    // Only x < P/2 can hold cells (P >= 2 nx - 1); rows and columns past the
-    // grid are clamped for the loads and masked afterwards, so every load of
-    // the thread is issued before the first one is used.
-    constexpr int MV = PPT > 1 ? PPT / 2 : 1;
-    const int r0c = v0 ? r0 : 0, r1c = v1 ? r1 : 0;
-    cf v[1][PPT];
-#pragma unroll
-    for (int m = MV; m < PPT; ++m) v[0][m] = mkc(0.f, 0.f);
-    unsigned int idx0[MV], idx1[MV];  // byte offsets into the [3][ncell] arrays
-    int g0[MV], g1[MV];
-#pragma unroll
-    for (int m = 0; m < MV; ++m) {
-        const int x = t + TPF * m;
-        const int xc = x < a.nx ? x : a.nx - 1;
-        const unsigned int cell0 = (unsigned int)(r0c * a.nx + xc), cell1 = (unsigned int)(r1c * a.nx + xc);
-        idx0[m] = (c0 * (unsigned int)n + cell0) << 2;
-        idx1[m] = (c1 * (unsigned int)n + cell1) << 2;
-        g0[m] = a.region[cell0];
-        g1[m] = a.region[cell1];
-    }
-    // two batches (one per component) bound the loads in flight per thread
-    float sv[2 * MV];
-    {
-        float s0[MV], s1[MV];
-        stage_batch(a, rs, idx0, s0);
-        stage_batch(a, rs, idx1, s1);
-#pragma unroll
-        for (int m = 0; m < MV; ++m) {
-            sv[m] = s0[m];
-            sv[MV + m] = s1[m];
-        }
-    }
-    if constexpr (FUSED) {
-        // the last term of the combine, k of the stage the x-inverse part of
-        // this workgroup just finished (after the barrier that published it)
-        const float* k0 = ks_stage<P>(gbuf, c0);
-        const float* k1 = ks_stage<P>(gbuf, c1);
-        const float w = rs.dt * a_last;
-#pragma unroll
-        for (int m = 0; m < MV; ++m) {
-            const int x = t + TPF * m;
-            const int xc = x < a.nx ? x : a.nx - 1;
-            sv[m] += w * k0[rr0 * a.nx + xc];
-            sv[MV + m] += w * k1[rr1 * a.nx + xc];
-        }
-    } else {
-        lut->store(lut_l, tid);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int m = 0; m < MV; ++m) {
-        const int x = t + TPF * m;
-        const bool in = x < a.nx;
-        if (a.sd.nk > 0 || FUSED) {
-            if (in && v0) sto(a.ms, idx0[m], sv[m]);
-            if (in && v1) sto(a.ms, idx1[m], sv[MV + m]);
-        }
-        const float re = (in && v0) ? lut_l[g0[m]].a.x * sv[m] : 0.f;
-        const float im = (in && v1) ? lut_l[g1[m]].a.x * sv[MV + m] : 0.f;
-        v[0][m] = mkc(re, im);
-    }
-    // x >= nx is zero padding (nx <= P/2)
-    RegFft<P, TPF, 1, false, (P >= 2)>::run(v, buf, a.tw, a.twshift, t);
-
-    // separate the two real transforms of this slot
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < PPT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
-    __syncthreads();
-    cf X[MH], Y[MH];
-#pragma unroll
-    for (int m = 0; m < MH; ++m) {
-        const int k = t + TPF * m;
-        const cf z = v[0][m < PPT ? m : 0];
-        const cf w = cconj(buf[lds_pad((P - k) & (P - 1))]);
-        const cf d = z - w;
-        X[m] = 0.5f * (z + w);
-        Y[m] = mkc(0.5f * d.y, -0.5f * d.x);
-    }
-    __syncthreads();
-    // stage [kx][row][component] and write the runs of 6 complex per kx
-#pragma unroll
-    for (int m = 0; m < MH; ++m) {
-        const int k = t + TPF * m;
-        if (2 * k > P) continue;
-        if (slot == 2) {
-            gbuf[k * 6 + 2] = X[m];
-            gbuf[k * 6 + 5] = Y[m];
-        } else {
-            gbuf[k * 6 + slot * 3] = X[m];
-            gbuf[k * 6 + slot * 3 + 1] = Y[m];
-        }
-    }
-    __syncthreads();
-    const Staged<P> sc(tid);
-#pragma unroll
-    for (int i = 0; i < Staged<P>::NIT; ++i) {
-        int li;
-        long long off;
-        sc.at(a, rbs, i, li, off);
-        if (off >= 0) a.spec[off] = lds[li];
-    }
-}
-
-// Inverse x pass of one workgroup: staged coalesced spectrum read, Hermitian
-// extension, inverse FFT, crop, per-cell epilogue (FUSED: the torque also to
-// LDS for the next stage's combine), reductions.  The region table goes to
-// LDS at lut_l.
-template <int P, bool FUSED>
-__device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
-                                 RegionLut* lut_l, double* red) {
-    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI, NTH = XCfg<P>::NTH;
-    constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL;
-    constexpr int MH = PPT / 2 + 1;
-    const int tid = threadIdx.x;
-    const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int pair0 = blk * GI;
-    cf* gbuf = lds + g * GL;
-    cf* buf = gbuf + slot * SEQ;
-
-    XLut<P> lut;
-    lut.load(a, tid);
-    // read the half spectra of the row pairs in contiguous runs into
-    // [kx][row][component]: every load of the thread first, then the LDS writes
-    const Staged<P> sc(tid);
-    constexpr int NIT = Staged<P>::NIT;
-    cf tmp[NIT];
-    int li[NIT];
-#pragma unroll
-    for (int i = 0; i < NIT; ++i) {
-        long long off;
-        sc.at(a, rbs, i, li[i], off);
-        tmp[i] = off >= 0 ? a.spec[off] : mkc(0.f, 0.f);
-    }
-#pragma unroll
-    for (int i = 0; i < NIT; ++i)
-        if (i < NIT - 1 || sc.kq0 + Staged<P>::KS * i < Staged<P>::GI * XCfg<P>::KH) lds[li[i]] = tmp[i];
-    lut.store(lut_l, tid);
-    __syncthreads();
-    // slot s = u + i w (slot 0: x, y of row a; slot 1: x, y of row b; slot 2: z of
-    // rows a and b); the DC and Nyquist bins of a real signal are real
-    const int iu = slot == 2 ? 2 : slot * 3, iw = slot == 2 ? 5 : slot * 3 + 1;
-    cf U[MH], W[MH];
-#pragma unroll
-    for (int m = 0; m < MH; ++m) {
-        const int k = t + TPF * m;
-        const int kc = 2 * k <= P ? k : 0;
-        U[m] = gbuf[kc * 6 + iu];
-        W[m] = gbuf[kc * 6 + iw];
-        if (k == 0 || 2 * k == P) {
-            U[m].y = 0.f;
-            W[m].y = 0.f;
-        }
-    }
-    __syncthreads();
-    // Hermitian extension: Z[k] = u + i w, Z[P-k] = conj u + i conj w for k <= P/2
-#pragma unroll
-    for (int m = 0; m < MH; ++m) {
-        const int k = t + TPF * m;
-        if (2 * k > P) continue;
-        const cf u = U[m], w = W[m];
-        buf[lds_pad(k)] = mkc(u.x - w.y, u.y + w.x);
-        if (k != 0 && 2 * k != P) buf[lds_pad(P - k)] = mkc(u.x + w.y, w.x - u.y);
-    }
-    __syncthreads();
-    cf v[1][PPT];
-#pragma unroll
-    for (int m = 0; m < PPT; ++m) v[0][m] = buf[lds_pad(t + TPF * m)];
-    RegFft<P, TPF, 1, true>::run(v, buf, a.tw, a.twshift, t);
-    // only x < nx <= P/2 is kept
-    constexpr int MOUT = P >= 2 ? PPT / 2 : PPT;
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < MOUT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
-    __syncthreads();
-
-    // per-cell epilogue over the 2 GI rows of this workgroup
-    EpiAcc acc;
-    epi_init(acc);
-    const float* mp = a.sd.nk > 0 || FUSED ? a.ms : a.m0;
-    for (int idx = tid; idx < 2 * GI * a.nx; idx += NTH) {
-        const int rr = idx / a.nx, x = idx - rr * a.nx;
-        const int row = 2 * pair0 + rr;
-        if (row >= a.nrows) continue;
-        cf* b3 = lds + (rr >> 1) * GL;
-        const cf v01 = b3[(rr & 1) * SEQ + lds_pad(x)];
-        const cf v2 = b3[2 * SEQ + lds_pad(x)];
-        const int z = row / a.ny, y = row - z * a.ny;
-        const float3 tq = epilogue(a, rs, lut_l, mp, (long long)row * a.nx + x, x, y, z,
-                                   make_float3(v01.x, v01.y, (rr & 1) ? v2.y : v2.x), acc);
-        if constexpr (FUSED) {
-            const int o = (rr & 1) * a.nx + x;
-            ks_stage<P>(b3, 0)[o] = tq.x;
-            ks_stage<P>(b3, 1)[o] = tq.y;
-            ks_stage<P>(b3, 2)[o] = tq.z;
-        }
-    }
-    // the fused pass serves inner stages only (no error norm, no reductions)
-    if constexpr (!FUSED)
-        if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NTH>(a, acc, red, blk);
-}
 
 template <int P>
 __global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
@@ -385,10 +15,11 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
     __shared__ long long rbs[2 * GI];
     const Resolved rs = resolve(a);
     if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
-    row_bases<GI>(a, xcd_remap(blockIdx.x, gridDim.x) * GI, rbs);
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    row_bases<GI>(a, blk * GI, rbs, threadIdx.x);
     XLut<P> lut;
     lut.load(a, threadIdx.x);
-    xfwd_part<P, false>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), &lut, 0.f);
+    xfwd_part<P, false>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), &lut, 0.f, blk, threadIdx.x);
 }
 
 template <int P>
@@ -399,9 +30,10 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
     __shared__ long long rbs[2 * GI];
     const Resolved rs = resolve(a);
     if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
-    row_bases<GI>(a, xcd_remap(blockIdx.x, gridDim.x) * GI, rbs);
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    row_bases<GI>(a, blk * GI, rbs, threadIdx.x);
     __syncthreads();
-    xinv_part<P, false>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), red);
+    xinv_part<P, false>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), red, blk, threadIdx.x);
 }
 
 // Fused pass: the x-inverse of stage s (torque k_s, read m_s from ai.ms)
@@ -417,397 +49,34 @@ k_xrow(const FieldArgs ai, const FieldArgs af, float a_last) {
     __shared__ long long rbs[2 * GI];
     const Resolved rsi = resolve(ai);
     if ((ai.flags & EPI_CHECK_DONE) && rsi.done) return;
-    row_bases<GI>(ai, xcd_remap(blockIdx.x, gridDim.x) * GI, rbs);
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    row_bases<GI>(ai, blk * GI, rbs, threadIdx.x);
     __syncthreads();
     RegionLut* lut_l = reinterpret_cast<RegionLut*>(lds + GI * GL);
-    xinv_part<P, true>(ai, rsi, lds, rbs, lut_l, red);
+    xinv_part<P, true>(ai, rsi, lds, rbs, lut_l, red, blk, threadIdx.x);
     __syncthreads();
     // the next stage's pointers only now (short live ranges across the first part)
     const Resolved rsf = resolve(af);
-    xfwd_part<P, true>(af, rsf, lds, rbs, lut_l, nullptr, a_last);
+    xfwd_part<P, true>(af, rsf, lds, rbs, lut_l, nullptr, a_last, blk, threadIdx.x);
 }
 
-// ---------------------------------------------------------------------------
-// Column pass.  Threads: (column ci < T, component s < 3, t < TPF); with
-// CFAST the column index varies fastest over the lanes (strided columns, so
-// neighbouring lanes read neighbouring columns), else t does (contiguous
-// columns).
+
 template <int P, int MODE, int NC, bool CFAST>
 __global__ void __launch_bounds__(ColCfg<P>::NTH) k_col(const ColArgs a) {
-    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, T = ColCfg<P>::T;
-    constexpr int SEQ = seq_len(P);
     extern __shared__ cf lds[];
-    if (a.check_done && a.st->done) return;
-    const int tid = threadIdx.x;
-    int ci, s, t;
-    if (CFAST) {
-        s = tid % 3;
-        ci = (tid / 3) % T;
-        t = tid / (3 * T);
-    } else {
-        t = tid % TPF;
-        s = (tid / TPF) % 3;
-        ci = tid / (3 * TPF);
-    }
-    const int ntile = (a.ncol + T - 1) / T;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int o = blk / ntile, tile = blk - o * ntile;
-    const int c = tile * T + ci;
-    const bool valid = c < a.ncol;
-    // 2D convolution: column 0 carries kx = 0 (real part) and kx = px/2 (imaginary part)
-    const bool packed = MODE == COL_CONV && NC == 4 && a.pack_col > 0 && c == 0;
-    cf* base = a.spec + (long long)o * a.outer_stride + (long long)(valid ? c : 0) * a.col_stride;
-    cf* baseN = a.spec + (long long)a.pack_col * a.col_stride;
-    cf* bufs = lds + ci * 3 * SEQ;
-    cf* buf = bufs + s * SEQ;
-
-    // A padded axis has P >= 2 n: the forward transforms read only q < P/2
-    // (the rest is zero padding) and the cropped outputs are q < P/2.
-    constexpr bool HIN = MODE != COL_INV && P >= 2;
-    constexpr int MIN = HIN ? PPT / 2 : PPT;
-    constexpr int MOUT = (MODE != COL_FWD && P >= 2) ? PPT / 2 : PPT;
-    cf v[1][PPT];
-#pragma unroll
-    for (int m = 0; m < PPT; ++m) {
-        const int q = t + TPF * m;
-        const bool ld = m < MIN && valid && q < a.n_in;
-        const long long off = (long long)q * a.pos_stride + s;
-        cf x = ld ? base[off] : mkc(0.f, 0.f);
-        if (packed) x = mkc(x.x, ld ? baseN[off].x : 0.f);
-        v[0][m] = x;
-    }
-    // 2D convolution: the K^ rows of the workgroup's columns go to LDS now, so
-    // their latency overlaps that of the column loads (K^ column kx is
-    // contiguous: (P/2 + 1) rows of 4 floats)
-    constexpr int KHP = P / 2 + 1;
-    float4* lk = reinterpret_cast<float4*>(lds + T * 3 * SEQ);
-    if constexpr (MODE == COL_CONV && NC == 4) {
-        constexpr int TOT = T * KHP, NTH = ColCfg<P>::NTH, NIT = (TOT + NTH - 1) / NTH;
-        const float4* kh = reinterpret_cast<const float4*>(a.khat);
-        const int c0 = (blk - o * ntile) * T;
-        float4 kt[NIT];
-#pragma unroll
-        for (int i = 0; i < NIT; ++i) {
-            const int e = tid + NTH * i;
-            const int ce = e / KHP, r = e - ce * KHP;
-            const bool in = (i < NIT - 1 || e < TOT) && c0 + ce < a.ncol;
-            kt[i] = in ? kh[(long long)(c0 + ce) * KHP + r] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int i = 0; i < NIT; ++i) {
-            const int e = tid + NTH * i;
-            if (i < NIT - 1 || e < TOT) lk[e] = kt[i];
-        }
-    }
-    RegFft<P, TPF, 1, MODE == COL_INV, HIN>::run(v, buf, a.tw, a.twshift, t);
-
-    if (MODE == COL_CONV) {
-        // all three components of this column through LDS
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < PPT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
-        __syncthreads();
-        // 2D: column c is kx and the transform runs along y.
-        // 3D: outer o is kx, column c is ky, the transform runs along z.
-        int kx = NC == 6 ? o : c;
-        asm volatile("" : "+v"(kx));  // load K^ here, not before the forward transform
-        int kyh = 0;
-        bool fa = false;
-        if (NC == 6) {
-            kyh = c;
-            if (2 * c > a.pa) {
-                kyh = a.pa - c;
-                fa = true;
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < PPT; ++m) {
-            const int q = t + TPF * m;
-            int qh = q;
-            bool fq = false;
-            if (2 * q > P) {
-                qh = P - q;
-                fq = true;
-            }
-            // row s of the symmetric K^ at (kxx, ky, q), with the mirror signs
-            // (2D: column kxx == c of this thread is staged in LDS)
-            auto krow = [&](int kxx) {
-                float3 r = make_float3(0.f, 0.f, 0.f);
-                if (!valid) return r;
-                float k0, k1, k2, kxy, kxz = 0.f, kyz = 0.f;
-                if (NC == 4 && kxx == c) {
-                    const float4 k4 = lk[ci * KHP + qh];
-                    k0 = k4.x;
-                    k1 = k4.y;
-                    k2 = k4.z;
-                    kxy = k4.w;
-                } else {
-                    const float* K = a.khat + (((long long)kxx * a.kyh + kyh) * a.kzh + qh) * NC;
-                    k0 = K[0];
-                    k1 = K[1];
-                    k2 = K[2];
-                    kxy = K[3];
-                    if (NC == 6) {
-                        kxz = K[4];
-                        kyz = K[5];
-                    }
-                }
-                if (NC == 6) {
-                    if (fq) {  // z: xz and yz are odd in z
-                        kxz = -kxz;
-                        kyz = -kyz;
-                    }
-                    if (fa) {  // y: xy and yz are odd in y
-                        kxy = -kxy;
-                        kyz = -kyz;
-                    }
-                } else if (fq) {  // y: xy is odd in y
-                    kxy = -kxy;
-                }
-                if (s == 0)
-                    r = make_float3(k0, kxy, kxz);
-                else if (s == 1)
-                    r = make_float3(kxy, k1, kyz);
-                else
-                    r = make_float3(kxz, kyz, k2);
-                return r;
-            };
-            const cf m0 = bufs[lds_pad(q)], m1 = bufs[SEQ + lds_pad(q)], m2 = bufs[2 * SEQ + lds_pad(q)];
-            if (!packed) {
-                const float3 K = krow(kx);
-                v[0][m] = K.x * m0 + K.y * m1 + K.z * m2;
-            } else {
-                // Z = A0 + i AN with A0, AN real along y: A0^(k) = (Z(k) + conj Z(-k))/2,
-                // AN^(k) = (Z(k) - conj Z(-k))/(2i); both field columns stay real, so
-                // B0^ + i BN^ recombines them.
-                const int qn = (P - q) & (P - 1);
-                const cf n0 = cconj(bufs[lds_pad(qn)]), n1 = cconj(bufs[SEQ + lds_pad(qn)]),
-                         n2 = cconj(bufs[2 * SEQ + lds_pad(qn)]);
-                const cf a00 = 0.5f * (m0 + n0), a01 = 0.5f * (m1 + n1), a02 = 0.5f * (m2 + n2);
-                const cf d0 = m0 - n0, d1 = m1 - n1, d2 = m2 - n2;
-                const cf an0 = mkc(0.5f * d0.y, -0.5f * d0.x), an1 = mkc(0.5f * d1.y, -0.5f * d1.x),
-                         an2 = mkc(0.5f * d2.y, -0.5f * d2.x);
-                const float3 K0 = krow(0), KN = krow(a.pack_col);
-                const cf b0 = K0.x * a00 + K0.y * a01 + K0.z * a02;
-                const cf bn = KN.x * an0 + KN.y * an1 + KN.z * an2;
-                v[0][m] = mkc(b0.x - bn.y, b0.y + bn.x);
-            }
-        }
-        RegFft<P, TPF, 1, true>::run(v, buf, a.tw, a.twshift, t);
-    }
-
-    int t2 = t;
-    asm volatile("" : "+v"(t2));  // form the store addresses here, not at load time
-#pragma unroll
-    for (int m = 0; m < MOUT; ++m) {
-        const int q = t2 + TPF * m;
-        if (valid && q < a.n_out) {
-            const long long off = (long long)q * a.pos_stride + s;
-            if (!packed) {
-                base[off] = v[0][m];
-            } else {
-                base[off] = mkc(v[0][m].x, 0.f);
-                baseN[off] = mkc(v[0][m].y, 0.f);
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// 2D convolution, one thread group per column carrying all three components
-// (three sequences through one LDS exchange buffer).  The K^ product is then
-// local to the thread, and the twiddles and exchange addresses of a stage
-// serve all three components.  Workgroup: T columns of TPF threads; LDS per
-// column: the exchange buffer, then a region that holds the column's K^ rows
-// (or, in the workgroup of the packed DC/Nyquist column, a second buffer).
-template <int P>
-struct Col3Cfg {
-    static constexpr int TPF = Cfg<P>::TPF;
-    static constexpr int T = TPF >= 256 ? 1 : 256 / TPF;
-    static constexpr int NTH = T * TPF;
-    static constexpr int SEQ = seq_len(P);
-    static constexpr int KHP = P / 2 + 1;
-    // complex elements per column: buffer + max(K^ rows (2 cf each), buffer)
-    static constexpr int CL = SEQ + (2 * KHP > SEQ ? 2 * KHP : SEQ);
-};
-
-template <int P>
-constexpr size_t col3_lds() {
-    return (size_t)Col3Cfg<P>::T * Col3Cfg<P>::CL * sizeof(cf);
+    col_body<P, MODE, NC, CFAST>(a, xcd_remap(blockIdx.x, gridDim.x), lds, threadIdx.x);
 }
 
 template <int P>
 __global__ void __launch_bounds__(Col3Cfg<P>::NTH, 4) k_col3(const ColArgs a) {
-    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, T = Col3Cfg<P>::T, NTH = Col3Cfg<P>::NTH;
-    constexpr int SEQ = Col3Cfg<P>::SEQ, KHP = Col3Cfg<P>::KHP, CL = Col3Cfg<P>::CL, MH = PPT / 2;
     extern __shared__ cf lds[];
-    if (a.check_done && a.st->done) return;
-    const int tid = threadIdx.x;
-    const int t = tid % TPF, ci = tid / TPF;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int c0 = blk * T, c = c0 + ci;
-    const bool valid = c < a.ncol;
-    const bool wg_packed = a.pack_col > 0 && blk == 0;  // uniform over the workgroup
-    const bool packed = wg_packed && ci == 0;
-    cf* buf = lds + ci * CL;
-    cf* reg2 = buf + SEQ;
-    const cf* base = a.spec + (long long)(valid ? c : 0) * a.col_stride;
-    const cf* baseN = a.spec + (long long)a.pack_col * a.col_stride;
-
-    // rows y < ny <= P/2 hold data; the rest is zero padding
-    cf v[3][PPT];
-#pragma unroll
-    for (int m = 0; m < PPT; ++m) {
-        const int q = t + TPF * m;
-        const bool ld = m < MH && valid && q < a.n_in;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            cf x = ld ? base[3LL * q + k] : mkc(0.f, 0.f);
-            if (packed) x = mkc(x.x, ld ? baseN[3LL * q + k].x : 0.f);
-            v[k][m] = x;
-        }
-    }
-    // the K^ rows of every column of the workgroup into LDS (their latency
-    // overlaps that of the column loads); column kx is contiguous
-    {
-        constexpr int TOT = T * KHP, NIT = (TOT + NTH - 1) / NTH;
-        const float4* kh = reinterpret_cast<const float4*>(a.khat);
-        float4 kt[NIT];
-#pragma unroll
-        for (int i = 0; i < NIT; ++i) {
-            const int e = tid + NTH * i;
-            const int ce = e / KHP, r = e - ce * KHP;
-            const bool in = (i < NIT - 1 || e < TOT) && c0 + ce < a.ncol;
-            kt[i] = in ? kh[(long long)(c0 + ce) * KHP + r] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int i = 0; i < NIT; ++i) {
-            const int e = tid + NTH * i;
-            const int ce = e / KHP, r = e - ce * KHP;
-            if (i < NIT - 1 || e < TOT) reinterpret_cast<float4*>(lds + ce * CL + SEQ)[r] = kt[i];
-        }
-    }
-    RegFft<P, TPF, 3, false, true>::run(v, buf, a.tw, a.twshift, t);
-
-    // B^ = K^ M^ (2D: K^ = [[xx, xy, 0], [xy, yy, 0], [0, 0, zz]], xy odd in y)
-    if (!wg_packed) {
-        const float4* lk = reinterpret_cast<const float4*>(reg2);
-#pragma unroll
-        for (int m = 0; m < PPT; ++m) {
-            const int q = t + TPF * m;
-            const bool fq = 2 * q > P;
-            const float4 k4 = lk[fq ? P - q : q];
-            const float kxy = fq ? -k4.w : k4.w;
-            const cf mx = v[0][m], my = v[1][m];
-            v[0][m] = k4.x * mx + kxy * my;
-            v[1][m] = kxy * mx + k4.y * my;
-            v[2][m] = k4.z * v[2][m];
-        }
-    } else {
-        // Packed column Z = A0 + i AN (A0: kx = 0, AN: kx = px/2, both real along
-        // y): B = K0 A0 + i KN AN = Kp Z(q) + Km conj Z(-q), Kp = (K0 + KN)/2,
-        // Km = (K0 - KN)/2.  Z(-q) comes through LDS: z first (one buffer), then
-        // x and y together (two buffers).
-        auto kpm = [&](int q, float4& kp, float4& km) {
-            const bool fq = 2 * q > P;
-            const int qh = fq ? P - q : q;
-            float4 k0 = reinterpret_cast<const float4*>(a.khat)[qh];
-            float4 kn = reinterpret_cast<const float4*>(a.khat)[(long long)a.pack_col * KHP + qh];
-            if (fq) {
-                k0.w = -k0.w;
-                kn.w = -kn.w;
-            }
-            kp = make_float4(0.5f * (k0.x + kn.x), 0.5f * (k0.y + kn.y), 0.5f * (k0.z + kn.z), 0.5f * (k0.w + kn.w));
-            km = make_float4(0.5f * (k0.x - kn.x), 0.5f * (k0.y - kn.y), 0.5f * (k0.z - kn.z), 0.5f * (k0.w - kn.w));
-        };
-        __syncthreads();
-        if (packed) {
-#pragma unroll
-            for (int m = 0; m < PPT; ++m) buf[lds_pad(t + TPF * m)] = v[2][m];
-        }
-        __syncthreads();
-        if (packed) {
-#pragma unroll
-            for (int m = 0; m < PPT; ++m) {
-                const int q = t + TPF * m;
-                float4 kp, km;
-                kpm(q, kp, km);
-                const cf zr = cconj(buf[lds_pad((P - q) & (P - 1))]);
-                v[2][m] = kp.z * v[2][m] + km.z * zr;
-            }
-        }
-        __syncthreads();
-        if (packed) {
-#pragma unroll
-            for (int m = 0; m < PPT; ++m) {
-                buf[lds_pad(t + TPF * m)] = v[0][m];
-                reg2[lds_pad(t + TPF * m)] = v[1][m];
-            }
-        }
-        __syncthreads();
-        if (packed) {
-#pragma unroll
-            for (int m = 0; m < PPT; ++m) {
-                const int q = t + TPF * m;
-                const int qn = (P - q) & (P - 1);
-                float4 kp, km;
-                kpm(q, kp, km);
-                const cf xr = cconj(buf[lds_pad(qn)]), yr = cconj(reg2[lds_pad(qn)]);
-                const cf zx = v[0][m], zy = v[1][m];
-                v[0][m] = kp.x * zx + kp.w * zy + km.x * xr + km.w * yr;
-                v[1][m] = kp.w * zx + kp.y * zy + km.w * xr + km.y * yr;
-            }
-        } else {
-            const float4* lk = reinterpret_cast<const float4*>(reg2);
-#pragma unroll
-            for (int m = 0; m < PPT; ++m) {
-                const int q = t + TPF * m;
-                const bool fq = 2 * q > P;
-                const float4 k4 = lk[fq ? P - q : q];
-                const float kxy = fq ? -k4.w : k4.w;
-                const cf mx = v[0][m], my = v[1][m];
-                v[0][m] = k4.x * mx + kxy * my;
-                v[1][m] = kxy * mx + k4.y * my;
-                v[2][m] = k4.z * v[2][m];
-            }
-        }
-    }
-    RegFft<P, TPF, 3, true>::run(v, buf, a.tw, a.twshift, t);
-
-    // rows y < ny <= P/2 are kept
-    cf* out = a.spec + (long long)(valid ? c : 0) * a.col_stride;
-    cf* outN = a.spec + (long long)a.pack_col * a.col_stride;
-    int t2 = t;
-    asm volatile("" : "+v"(t2));  // form the store addresses here, not at load time
-#pragma unroll
-    for (int m = 0; m < MH; ++m) {
-        const int q = t2 + TPF * m;
-        if (valid && q < a.n_out) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                if (!packed) {
-                    out[3LL * q + k] = v[k][m];
-                } else {
-                    out[3LL * q + k] = mkc(v[k][m].x, 0.f);
-                    outN[3LL * q + k] = mkc(v[k][m].y, 0.f);
-                }
-            }
-        }
-    }
+    col3_body<P>(a, xcd_remap(blockIdx.x, gridDim.x), lds, threadIdx.x);
 }
+
 
 // ---------------------------------------------------------------------------
 // Launch helpers: dispatch the run-time padded length to a template instance.
 
-// Dynamic LDS of each pass (bytes per workgroup).
-template <int P>
-constexpr size_t x_lds() {
-    return (size_t)XCfg<P>::GI * XCfg<P>::GL * sizeof(cf) + NREG * sizeof(RegionLut);
-}
-template <int P, int MODE, int NC>
-constexpr size_t col_lds() {
-    return (size_t)ColCfg<P>::T * 3 * seq_len(P) * sizeof(cf) + (MODE == COL_CONV && NC == 4 ? khat_lds<P>() : 0);
-}
 
 template <int P>
 static int x_blocks(int nrows) {
@@ -856,12 +125,6 @@ static hipError_t col3_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEven
     hipExtLaunchKernelGGL((k_col3<P>), dim3((unsigned)nb), dim3(Col3Cfg<P>::NTH), (uint32_t)col3_lds<P>(), s, e0, e1,
                           0, a);
     return hipGetLastError();
-}
-
-// the three-components-per-thread 2D convolution serves 64 <= P <= 2048
-template <int P>
-constexpr bool use_col3() {
-    return P >= 64 && P <= 2048;
 }
 
 #define MM_CASES(M) M(1) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048) M(4096)

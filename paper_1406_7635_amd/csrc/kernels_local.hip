@@ -4,6 +4,7 @@
 
 #include "../../include/mm.h"
 #include "field_epilogue.h"
+#include "step_control.h"
 
 namespace mm {
 
@@ -130,33 +131,13 @@ hipError_t launch_llg(const FieldArgs& a, const float* beff, float* tau, int pre
 }
 
 // ---------------------------------------------------------------------------
-// Solver state and the adaptive step controller (section "Adaptive time
-// step"): eps = dt max|sum (b - b*) k|; accept when eps <= MaxErr; next dt =
-// dt * clamp(headroom (MaxErr/eps)^(1/(q+1)), 0.1, 2) (2 when eps = 0),
-// clamped to [dt_min, dt_max] and clipped so the run lands on t_end.
+// Solver state of one context and its adaptive step controller (the update
+// rules are in step_control.h).
 __global__ void k_set_state(DevState* st, double t, double dt, double t_end, double max_err,
                             double headroom, double dt_min, double dt_max, int order_low,
                             int reset_counters, int init_perm, long long target_steps) {
-    st->t = t;
-    st->dt = dt;
-    st->t_end = t_end;
-    st->max_err = max_err;
-    st->headroom = headroom;
-    st->dt_min = dt_min;
-    st->dt_max = dt_max;
-    st->order_low = order_low;
-    st->err_bits = 0u;
-    st->tq_bits = 0u;
-    st->accepted = 0;
-    st->done = 0;
-    st->target_steps = target_steps;
-    if (reset_counters) {
-        st->steps = st->rejects = st->evals = 0;
-        st->status = 0;
-        st->err = 0.0;
-    }
-    if (init_perm)
-        for (int i = 0; i < 8; ++i) st->perm[i] = i;
+    set_state(st, t, dt, t_end, max_err, headroom, dt_min, dt_max, order_low, reset_counters, init_perm,
+              target_steps);
 }
 
 hipError_t launch_set_state(DevState* st, double t, double dt, double t_end, double max_err,
@@ -179,52 +160,7 @@ hipError_t launch_reset_accum(DevState* st, hipStream_t s) {
 }
 
 __global__ void k_controller(DevState* st, int last_k, int evals, int check_done) {
-    if (check_done && st->done) {
-        st->accepted = 0;  // a no-op attempt after the run ended: nothing to finalise
-        return;
-    }
-    const double emax = (double)__uint_as_float(st->err_bits);
-    const double dt = st->dt;
-    const double err = dt * emax;
-    st->err = err;
-    st->err_bits = 0u;
-    st->evals += evals;
-    if (!isfinite(err)) {
-        st->accepted = 0;
-        st->rejects += 1;
-        st->status = -5;  // MM_ENONFINITE
-        st->done = 1;
-        return;
-    }
-    const bool acc = err <= st->max_err;
-    double fac = 2.0;
-    if (err > 0.0) {
-        fac = st->headroom * pow(st->max_err / err, 1.0 / (double)(st->order_low + 1));
-        fac = fmin(2.0, fmax(0.1, fac));
-    }
-    const bool clipped = isfinite(st->t_end) && (st->t + dt >= st->t_end);
-    if (acc) {
-        st->t = clipped ? st->t_end : st->t + dt;
-        st->steps += 1;
-        if (last_k > 0) {
-            const int tmp = st->perm[0];
-            st->perm[0] = st->perm[last_k];
-            st->perm[last_k] = tmp;
-        }
-    } else {
-        st->rejects += 1;
-    }
-    st->accepted = acc ? 1 : 0;
-    double dtn = dt * fac;
-    if (st->dt_max > 0.0) dtn = fmin(dtn, st->dt_max);
-    if (dtn < st->dt_min) {
-        st->status = -6;  // MM_ESTEP
-        st->done = 1;
-    }
-    if (acc && clipped) st->done = 1;
-    if (st->target_steps > 0 && st->steps >= st->target_steps) st->done = 1;
-    if (isfinite(st->t_end) && st->t + dtn > st->t_end && st->t < st->t_end) dtn = st->t_end - st->t;
-    st->dt = dtn;
+    controller_update(st, last_k, evals, check_done);
 }
 
 hipError_t launch_controller(DevState* st, int last_k, int evals, int check_done, hipStream_t s) {

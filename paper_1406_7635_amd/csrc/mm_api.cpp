@@ -9,6 +9,8 @@
 
 #include "../../include/mm.h"
 #include "mm_internal.h"
+#include "api_common.h"
+#include "tableau.h"
 
 using namespace mm;
 
@@ -24,80 +26,6 @@ struct TimingClass {
 constexpr size_t TIMING_POOL = 4096;
 // launch classes: 0 x-forward, 1 column passes, 2 x-inverse, 3 fused x-inverse + x-forward
 constexpr int NTIMING = 4;
-
-// Butcher tableaux (section "Dynamics"): row s holds a_{s+1, j}, j <= s.
-struct Tableau {
-    int stages;        // derivatives per step including the first-same-as-last one
-    int order_low;     // order of the embedded (error) solution
-    double a[7][6];
-    double e[7];       // b_j - b*_j
-};
-
-const Tableau DP45 = {
-    7, 4,
-    {{0, 0, 0, 0, 0, 0},
-     {1.0 / 5, 0, 0, 0, 0, 0},
-     {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
-     {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
-     {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
-     {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
-     {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}},
-    {35.0 / 384 - 5179.0 / 57600, 0, 500.0 / 1113 - 7571.0 / 16695, 125.0 / 192 - 393.0 / 640,
-     -2187.0 / 6784 + 92097.0 / 339200, 11.0 / 84 - 187.0 / 2100, -1.0 / 40}};
-
-const Tableau BS23 = {
-    4, 2,
-    {{0, 0, 0, 0, 0, 0},
-     {1.0 / 2, 0, 0, 0, 0, 0},
-     {0, 3.0 / 4, 0, 0, 0, 0},
-     {2.0 / 9, 1.0 / 3, 4.0 / 9, 0, 0, 0},
-     {0, 0, 0, 0, 0, 0},
-     {0, 0, 0, 0, 0, 0},
-     {0, 0, 0, 0, 0, 0}},
-    {2.0 / 9 - 7.0 / 24, 1.0 / 3 - 1.0 / 4, 4.0 / 9 - 1.0 / 3, -1.0 / 8, 0, 0, 0}};
-
-int pad_len(int n) {
-    if (n == 1) return 1;
-    int p = 1;
-    while (p < 2 * n - 1) p <<= 1;
-    return p;
-}
-
-int map_err(hipError_t e) {
-    if (e == hipSuccess) return MM_OK;
-    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return MM_ENOMEM;
-    return MM_EDEVICE;
-}
-
-#define MM_TRY(expr)                      \
-    do {                                  \
-        const hipError_t e_ = (expr);     \
-        if (e_ != hipSuccess) return map_err(e_); \
-    } while (0)
-
-#define MM_CHECK(expr)                    \
-    do {                                  \
-        const int s_ = (expr);            \
-        if (s_ != MM_OK) return s_;       \
-    } while (0)
-
-bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
-
-int validate_params(const mm_params* p) {
-    if (!p) return MM_EINVAL;
-    for (int i = 0; i < NREG; ++i) {
-        const double v[5] = {p->msat[i], p->aex[i], p->alpha[i], p->ku1[i], p->ku2[i]};
-        for (double x : v)
-            if (!isfinite(x)) return MM_EINVAL;
-        if (p->msat[i] < 0.0 || p->alpha[i] < 0.0 || p->aex[i] < 0.0) return MM_EINVAL;
-        for (int k = 0; k < 3; ++k)
-            if (!isfinite(p->anis_u[i][k]) || !isfinite(p->bext[i][k])) return MM_EINVAL;
-    }
-    for (int i = 0; i < MM_NPAIRS; ++i)
-        if (!isfinite(p->exch_scale[i])) return MM_EINVAL;
-    if (!isfinite(p->gamma_ll) || p->gamma_ll < 0.0) return MM_EINVAL;
-    return MM_OK;
-}
 
 }  // namespace
 
@@ -339,28 +267,10 @@ int eval_first(mm_ctx* c, const float* m, int precess) {
 // Field arguments of stage s of tableau tb: combine over the non-zero a_sj,
 // torque into logical derivative s, error norm on the last stage.
 FieldArgs stage_args(mm_ctx* c, float* m, const Tableau& tb, int s, int precess, bool check_done) {
-    const int S = tb.stages;
     FieldArgs a = base_args(c, m);
-    StageDesc& sd = a.sd;
-    sd.nk = 0;
-    for (int j = 0; j < s; ++j)
-        if (tb.a[s][j] != 0.0) {
-            sd.kidx[sd.nk] = j;
-            sd.a[sd.nk] = (float)tb.a[s][j];
-            ++sd.nk;
-        }
-    sd.out_k = s;
+    const bool last = fill_stage(tb, s, a.sd);
     a.flags = EPI_TORQUE | (precess ? EPI_PRECESS : 0) | (check_done ? EPI_CHECK_DONE : 0);
-    if (s == S - 1) {
-        sd.nerr = 0;
-        for (int j = 0; j < S; ++j)
-            if (tb.e[j] != 0.0) {
-                sd.eidx[sd.nerr] = j;
-                sd.e[sd.nerr] = (float)tb.e[j];
-                ++sd.nerr;
-            }
-        a.flags |= EPI_ERR;
-    }
+    if (last) a.flags |= EPI_ERR;
     return a;
 }
 

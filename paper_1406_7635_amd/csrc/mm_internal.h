@@ -134,6 +134,60 @@ int xinv_blocks(int px, int nrows);
 hipError_t configure_field_kernels(int px, int py, int pz);
 enum ColMode { COL_FWD = 0, COL_INV = 1, COL_CONV = 2 };
 
+// ---- batched ensemble (kernels_batch.hip) ----------------------------------
+// An ensemble of independent grids shares one work list per pass.  The
+// ensemble's arrays are the members' arrays back to back; BMember locates
+// member i in them (its [3][ncell] vector fields at 3 cell_off floats, its
+// region map at cell_off bytes, its stage derivatives at MAXK 3 cell_off
+// floats, its spectrum at spec_off and kernel spectrum at khat_off elements,
+// its region tables at i NREG entries, its pair table at i NREG^2 floats, its
+// solver state at entry i).  The kernels take the base pointers and stage
+// descriptor in FieldArgs / ColArgs and derive each member's arguments.
+struct BMember {
+    int nx, ny, nz, nrows;
+    int px, py, pz, kx;
+    long long cell_off;
+    long long spec_off;
+    long long khat_off;
+    long long colstride, zstride;
+    float idx2, idy2, idz2, cellvol;
+};
+// Work list of one batched pass: item = (member << 16) | tile.
+struct BatchList {
+    const BMember* mem;
+    const unsigned int* items;
+    int nitems;
+};
+enum BatchPass { BP_X = 0, BP_C3 = 1, BP_Y = 2, BP_Z4 = 3, BP_Z8 = 4, BP_Z16 = 5, BP_F = 6, BP_N = 7 };
+enum BatchXKind { BX_FWD = 0, BX_ROW = 1, BX_INV = 2 };
+enum BatchColKind { BC_CONV2 = 0, BC_YFWD = 1, BC_YINV = 2, BC_ZCONV = 3 };
+// Padded lengths the batched passes serve: 64 <= px, py <= 1024, pz in {1, 4, 8, 16}.
+bool batch_supported(int px, int py, int pz);
+// Tiles (work items) of member m in pass p; 0 when the pass does not apply to it.
+int batch_tiles(int pass, const BMember& m);
+// Workgroups of pass p that fit on one compute unit at once.
+hipError_t batch_resident(int pass, int* per_cu);
+hipError_t configure_batch_kernels(void);
+// Every launcher takes the pass's work list and its number of persistent
+// workgroups (a multiple of 8).  x passes: fi (and ff for the fused pass)
+// hold the base pointers, stage descriptor and flags.
+hipError_t launch_bx(int kind, const BatchList& l, int grid, const FieldArgs& fi, const FieldArgs& ff, float a_last,
+                     hipStream_t s);
+// Column passes; base holds the spectrum, kernel and state base pointers, the
+// twiddles and check_done.  2D y convolution of the members with nz = 1:
+hipError_t launch_bcol3(const BatchList& l, int grid, const ColArgs& base, hipStream_t s);
+// y transforms (forward, or inverse) of the members with nz > 1:
+hipError_t launch_bcoly(int inverse, const BatchList& l, int grid, const ColArgs& base, hipStream_t s);
+// z convolution of the members of one padded z length (pass BP_Z4 / BP_Z8 / BP_Z16):
+hipError_t launch_bzconv(int pass, const BatchList& l, int grid, const ColArgs& base, hipStream_t s);
+hipError_t launch_bfinalize(const BatchList& l, int grid, const float* ms, float* m, const DevState* st,
+                            hipStream_t s);
+hipError_t launch_bcontroller(DevState* st, int n, int last_k, int evals, int check_done, int* active,
+                              hipStream_t s);
+hipError_t launch_bset_state(DevState* st, int n, double t, double dt, double t_end, double max_err,
+                             double headroom, double dt_min, double dt_max, int order_low, int reset_counters,
+                             int init_perm, hipStream_t s);
+
 // ---- launchers (kernels_local.hip) -----------------------------------------
 hipError_t launch_prepare_tables(const double* params64, RegionLut* lut, float* ptab,
                                  hipStream_t s);

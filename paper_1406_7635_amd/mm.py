@@ -77,6 +77,19 @@ EXPORTS = {
     "mm_set_conv_precision": (c_int32, [c_void_p, c_int32]),
     "mm_timing_enable": (c_int32, [c_void_p, c_int32, c_int32]),
     "mm_timing_read": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int64), ctypes.POINTER(c_double)]),
+    "mm_batch_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Params),
+                                  c_void_p, c_void_p]),
+    "mm_batch_demag_kernel_init": (c_int32, [c_void_p]),
+    "mm_batch_member": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64)]),
+    "mm_batch_beff": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "mm_batch_start": (c_int32, [c_void_p, c_int32, c_double, c_double, c_double, ctypes.POINTER(SolverOpts)]),
+    "mm_batch_run": (c_int32, [c_void_p, c_void_p, c_int64, ctypes.POINTER(c_int64), ctypes.POINTER(c_int32)]),
+    "mm_batch_stats": (c_int32, [c_void_p, c_int32, ctypes.POINTER(RunStats), ctypes.POINTER(c_int32)]),
+    "mm_batch_set_graph": (c_int32, [c_void_p, c_int32]),
+    "mm_batch_set_grid": (c_int32, [c_void_p, c_int32, c_int32]),
+    "mm_batch_get_grid": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int32)]),
+    "mm_batch_autotune": (c_int32, [c_void_p, c_void_p]),
+    "mm_batch_destroy": (None, [c_void_p]),
     "mm_destroy": (None, [c_void_p]),
     "mm_strerror": (ctypes.c_char_p, [c_int32]),
 }
@@ -300,3 +313,127 @@ class Context:
         n, ms = c_int64(), c_double()
         _check(load().mm_timing_read(self._h, int(which), ctypes.byref(n), ctypes.byref(ms)), "mm_timing_read")
         return n.value, ms.value
+
+
+BATCH_PASSES = ("x", "conv2d", "y", "z4", "z8", "z16", "finalize")  # mm_batch_set_grid pass ids
+
+
+class Batch:
+    """An ensemble of independent grids advanced together (mm_batch_*).
+
+    members: list of dicts with "grid" (nx, ny, nz), "cell" (dx, dy, dz),
+    "region" uint8 [nz, ny, nx] and "params" (dict of region tables).  State
+    and field tensors are the members' [3, nz, ny, nx] arrays back to back
+    (member i at floats [3 off_i, 3 off_i + 3 ncell_i))."""
+
+    def __init__(self, members, stream=None):
+        import torch
+
+        self._torch = torch
+        lib = load()
+        n = len(members)
+        self.n = n
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        grids = (Grid * n)()
+        params = (Params * n)()
+        regs = []
+        self.grids = []
+        for i, mb in enumerate(members):
+            nx, ny, nz = (int(v) for v in mb["grid"])
+            grids[i] = Grid(nx, ny, nz, *(float(v) for v in mb["cell"]), (c_int32 * 3)(0, 0, 0))
+            params[i] = params_struct(mb["params"])
+            r = np.ascontiguousarray(mb["region"], dtype=np.uint8)
+            if r.shape != (nz, ny, nx):
+                raise ValueError("member %d: region must have shape %s" % (i, (nz, ny, nx)))
+            regs.append(r.reshape(-1))
+            self.grids.append((nx, ny, nz))
+        self._region = torch.from_numpy(np.concatenate(regs)).to(self.device)
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handle = c_void_p()
+        _check(lib.mm_batch_create(ctypes.byref(handle), n, grids, params, _ptr(self._region),
+                                   c_void_p(self._stream.cuda_stream)), "mm_batch_create")
+        self._h = handle
+        self.offsets, self.ncells = [], []
+        for i in range(n):
+            off, nc = c_int64(), c_int64()
+            _check(lib.mm_batch_member(self._h, i, ctypes.byref(off), ctypes.byref(nc)), "mm_batch_member")
+            self.offsets.append(off.value)
+            self.ncells.append(nc.value)
+        self.ncell = sum(self.ncells)
+        _check(lib.mm_batch_demag_kernel_init(self._h), "mm_batch_demag_kernel_init")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, m, name="m"):
+        t = self._torch
+        if not isinstance(m, t.Tensor) or m.dtype != t.float32 or m.device != self.device \
+                or m.numel() != 3 * self.ncell or not m.is_contiguous():
+            raise ValueError("%s must be a contiguous float32 tensor of %d elements on %s"
+                             % (name, 3 * self.ncell, self.device))
+        return m
+
+    def new_field(self):
+        return self._torch.empty(3 * self.ncell, dtype=self._torch.float32, device=self.device)
+
+    def member(self, t, i):
+        """View of member i's [3, nz, ny, nx] block of an ensemble array."""
+        nx, ny, nz = self.grids[i]
+        o = 3 * self.offsets[i]
+        return t[o:o + 3 * self.ncells[i]].view(3, nz, ny, nx)
+
+    def pack(self, arrays):
+        """Ensemble array from the members' [3, nz, ny, nx] arrays (numpy or tensors)."""
+        out = self.new_field()
+        for i, a in enumerate(arrays):
+            self.member(out, i).copy_(self._torch.as_tensor(np.asarray(a, dtype=np.float32)))
+        return out
+
+    def beff(self, m):
+        b = self.new_field()
+        _check(load().mm_batch_beff(self._h, _ptr(self._vec(m)), _ptr(b)), "mm_batch_beff")
+        return b
+
+    def start(self, solver=45, t0=0.0, dt0=1e-14, t_end=float("inf"), opts=None):
+        o = opts if opts is not None else solver_opts()
+        _check(load().mm_batch_start(self._h, int(solver), float(t0), float(dt0), float(t_end), ctypes.byref(o)),
+               "mm_batch_start")
+
+    def run(self, m, max_attempts):
+        """Attempt steps of every running member; returns (attempts, members still running)."""
+        na, act = c_int64(), c_int32()
+        _check(load().mm_batch_run(self._h, _ptr(self._vec(m)), int(max_attempts), ctypes.byref(na),
+                                   ctypes.byref(act)), "mm_batch_run")
+        return na.value, act.value
+
+    def stats(self, i):
+        st, status = RunStats(), c_int32()
+        _check(load().mm_batch_stats(self._h, int(i), ctypes.byref(st), ctypes.byref(status)), "mm_batch_stats")
+        d = {k: getattr(st, k) for k, _ in RunStats._fields_}
+        d["status"] = status.value
+        return d
+
+    def set_graph(self, enable):
+        _check(load().mm_batch_set_graph(self._h, 1 if enable else 0), "mm_batch_set_graph")
+
+    def set_grid(self, pass_, grid):
+        p = BATCH_PASSES.index(pass_) if isinstance(pass_, str) else int(pass_)
+        _check(load().mm_batch_set_grid(self._h, p, int(grid)), "mm_batch_set_grid")
+
+    def get_grid(self, pass_):
+        p = BATCH_PASSES.index(pass_) if isinstance(pass_, str) else int(pass_)
+        g = c_int32()
+        _check(load().mm_batch_get_grid(self._h, p, ctypes.byref(g)), "mm_batch_get_grid")
+        return g.value
+
+    def autotune(self, m):
+        _check(load().mm_batch_autotune(self._h, _ptr(self._vec(m))), "mm_batch_autotune")
+        return {name: self.get_grid(i) for i, name in enumerate(BATCH_PASSES)}

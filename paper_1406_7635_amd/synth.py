@@ -184,3 +184,25 @@ def random_problem(grid, cell, seed, nregions=3, ku=True, field=True, vacuum=Fal
         p["msat"][nregions - 1] = 0.0
     return {"name": "random%dx%dx%d" % grid, "grid": grid, "cell": cell, "region": region,
             "params": p, "m0": random_sphere(grid, seed + 1000)}
+
+
+def ensemble(n=512, seed=4, sizes=(32, 64, 128, 256), layers=(1, 2), t_end=1e-9):
+    """Ensemble of n independent simulations: nx, ny drawn independently from
+    `sizes`, nz from `layers`, cubic cells of U(2, 5) nm, one region with Msat
+    ~ U(4e5, 1.2e6), Aex ~ U(5e-12, 2e-11), alpha ~ U(0.005, 0.5), no applied
+    field, m0 random on the sphere (member i from sub-seed 1000 seed + i);
+    DP45 with MaxErr 1e-5 to t_end.  Returns the list of member dicts."""
+    rng = _rng(seed)
+    members = []
+    for i in range(n):
+        nx, ny = (int(v) for v in rng.choice(sizes, 2))
+        nz = int(rng.choice(layers))
+        d = float(rng.uniform(2e-9, 5e-9))
+        p = material(float(rng.uniform(4e5, 1.2e6)), float(rng.uniform(5e-12, 2e-11)),
+                     alpha=float(rng.uniform(0.005, 0.5)))
+        grid = (nx, ny, nz)
+        members.append({"name": "member%d" % i, "grid": grid, "cell": (d, d, d),
+                        "region": np.zeros((nz, ny, nx), dtype=np.uint8), "params": p,
+                        "m0": random_sphere(grid, 1000 * seed + i), "solver": "rk45", "max_err": 1e-5,
+                        "t_end": t_end})
+    return members
