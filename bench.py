@@ -167,6 +167,85 @@ def mfma_variants(ctx, m, opts, ncell, steps):
     return res
 
 
+def ensemble_attempt_bytes(members):
+    """Algorithmic HBM bytes of one Dormand-Prince attempt of every member of
+    an ensemble (the pass model above, per member: x-forward, five fused
+    x passes, x-inverse with the error norm, finalisation; six column stages:
+    the y convolution in 2D, the one-pass y/z convolution of thin 3D grids,
+    else y-forward + z convolution + y-inverse)."""
+    def pad(n):
+        return 1 if n == 1 else 1 << (2 * n - 2).bit_length()
+
+    tot = 0.0
+    for c in members:
+        nx, ny, nz = c["grid"]
+        px, py, pz = pad(nx), pad(ny), pad(nz)
+        kx = px // 2 + 1
+        n = nx * ny * nz
+        spec = 3 * 8 * kx * ny * nz
+        x = ((12 + 1 + 12 + 12) * n + spec) + 5 * (2 * spec + (12 + 1 + 12 + 12 + 12 * DP45_XROW_K + 12) * n) \
+            + (spec + (12 + 1 + 12 * 5 + 12) * n) + 24 * n
+        if pz == 1:
+            col = 2 * spec + 4 * 4 * kx * (py // 2 + 1)
+        elif pz in (4, 8) and py * pz <= 4096:
+            # thin grid: one pass per kx column (y FFT, z DFT with K^, inverse y FFT)
+            col = 2 * spec + 4 * 6 * kx * (py // 2 + 1) * (pz // 2 + 1)
+        else:
+            yf = 3 * 8 * kx * nz * (ny + py)
+            zc = 2 * 3 * 8 * kx * py * nz + 4 * 6 * kx * (py // 2 + 1) * (pz // 2 + 1)
+            col = 2 * yf + zc
+        tot += x + 6 * col
+    return tot
+
+
+def ensemble_variant(steps, warmup, n=512):
+    """The 512-member ensemble (nx, ny in {32..256}, nz in {1, 2}, DP45): every
+    pass one persistent launch over all members, attempts replayed as a graph,
+    persistent grids tuned first; also the same attempts with one workgroup per
+    tile and with direct launches."""
+    import torch
+
+    from paper_1406_7635_amd import mm, synth
+
+    members = synth.ensemble(n=n, seed=4)
+    b = mm.Batch(members)
+    ncell = np.array(b.ncells, dtype=np.float64)
+    m = b.pack([c["m0"] for c in members])
+    b.start(45, 0.0, 1e-14, members[0]["t_end"], mm.solver_opts(max_err=1e-5))
+
+    def timed(k):
+        s0 = b.stats_all()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        na, act = b.run(m, k)
+        wall = time.perf_counter() - w0
+        s1 = b.stats_all()
+        cell_evals = float(np.sum(ncell * (s1["evals"] - s0["evals"])))
+        return cell_evals / wall, wall, na, act, int(np.sum(s1["steps"] - s0["steps"])), \
+            int(np.sum(s1["rejects"] - s0["rejects"]))
+
+    b.run(m, max(1, warmup))
+    untuned = timed(max(1, steps // 4))
+    grids = b.autotune(m)
+    b.run(m, max(1, warmup))
+    val, wall, na, act, acc, rej = timed(steps)
+    b.set_graph(False)
+    direct = timed(max(1, steps // 4))
+    b.set_graph(True)
+    bytes_att = ensemble_attempt_bytes(members)
+    gbs = bytes_att * na / wall / 1e9
+    b.close()
+    return {"value": val, "unit": "Beff evals*cells/s", "members": n, "cells": int(ncell.sum()),
+            "attempts": na, "ms_per_attempt": 1e3 * wall / na, "accepted_steps": acc, "rejected_steps": rej,
+            "running_after": act, "alg_bytes_per_attempt": bytes_att, "alg_GBs": gbs,
+            "alg_frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "persistent_grids": grids,
+            "untuned_value": untuned[0], "direct_launch_value": direct[0],
+            "workload": "512 independent sims: nx, ny from {32,64,128,256}, nz from {1,2}, cubic cells "
+                        "U(2,5) nm, Msat U(4e5,1.2e6), Aex U(5e-12,2e-11), alpha U(0.005,0.5), random m0, "
+                        "no field; DP45 MaxErr 1e-5 towards 1 ns (timed window of %d attempts)" % steps,
+            "dtype": "f32"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +253,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=1024, help="film edge in cells")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble variant")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="only the batched-ensemble variant (one JSON line; for profiling)")
     ap.add_argument("--traffic", default=TRAFFIC_FILE,
                     help="rocprofv3 traffic summary with measured HBM bytes per launch")
     ap.add_argument("--copy-probe", action="store_true",
@@ -197,6 +279,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4,
                           "launches": 10}))
+        return
+    if args.ensemble_only:
+        print(json.dumps(ensemble_variant(max(4, args.steps // 10), max(2, args.warmup // 5))))
         return
     case = synth.vortex_film(seed=2, n=args.n)
     ncell = int(np.prod(case["grid"]))
@@ -253,6 +338,9 @@ def main():
         "kernels": per,
     }
     out["variants"] = mfma_variants(ctx, m, opts, ncell, args.steps)
+    ctx.close()
+    if not args.no_ensemble:
+        out["variants"]["ensemble"] = ensemble_variant(max(4, args.steps // 10), max(2, args.warmup // 5))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     else:

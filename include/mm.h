@@ -310,13 +310,17 @@ int mm_batch_run(mm_batch *b, float *m_dev, int64_t max_attempts, int64_t *attem
 /* Counters, time and step of member i after the last run; its status in
  * *status (MM_OK, MM_ENONFINITE or MM_ESTEP).  Synchronises. */
 int mm_batch_stats(mm_batch *b, int32_t i, mm_run_stats *out, int32_t *status);
+/* The same for every member at once: out[n], status[n] (status may be NULL). */
+int mm_batch_stats_all(mm_batch *b, mm_run_stats *out, int32_t *status);
 /* enable = 0: launch every kernel of an attempt directly instead of
  * replaying a graph (same kernels, same results). */
 int mm_batch_set_graph(mm_batch *b, int32_t enable);
 /* Persistent workgroups of batched pass `pass` (0 x passes, 1 2D y
  * convolution, 2 3D y transforms, 3/4/5 3D z convolution for padded z length
- * 4/8/16, 6 finalisation): grid > 0 (rounded up to a multiple of 8), or 0 for
- * one workgroup per tile.  mm_batch_get_grid reads the current value. */
+ * 4/8/16, 6/7 thin-grid 3D convolution (y FFT, z DFT, inverse y FFT in one
+ * pass) for padded z length 4/8, 8 finalisation): grid > 0 (rounded up to a
+ * multiple of 8), or 0 for one workgroup per tile.  mm_batch_get_grid reads
+ * the current value. */
 int mm_batch_set_grid(mm_batch *b, int32_t pass, int32_t grid);
 int mm_batch_get_grid(mm_batch *b, int32_t pass, int32_t *grid);
 /* Time every pass of one attempt at m_dev for a few persistent grid sizes

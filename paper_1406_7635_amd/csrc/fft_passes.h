@@ -559,6 +559,146 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
 }
 
 // ---------------------------------------------------------------------------
+// 3D convolution of a thin grid (a few layers) in one pass per kx column:
+// forward FFT along y of the three components of every z plane (the nz
+// planes' sequences side by side in LDS), then for each ky the transform along
+// the short z axis as a direct DFT of its nz non-zero planes, the K^ product
+// at every kz (K^ octant with the mirror signs of both folded axes) and the
+// inverse DFT back to the nz planes, then the inverse FFT along y.  The
+// spectrum keeps ny rows per column (ycount = ny); the padded y and z
+// lengths live only on chip.
+//
+// Threads: for each of T kx columns, 3 PZ/2 thread groups (plane z, component
+// c; planes z >= nz idle) of TPF threads.  Serves PZ in {4, 8} (nz from 2 to
+// 4) and PY PZ <= 4096: the workgroup is 768 threads and its exchange LDS
+// 55 KB for every such pair.  (More layers keep the three-pass path: the z
+// step's registers would not fit.)
+template <int PY, int PZ>
+struct YzCfg {
+    static constexpr int TPF = Cfg<PY>::TPF, PPT = Cfg<PY>::PPT;
+    static constexpr int NZM = PZ / 2;           // planes a thread group set can hold
+    static constexpr int G = 3 * NZM;            // thread groups per column
+    static constexpr int TK = G * TPF;           // threads per column
+    static constexpr int T = 768 / TK;           // columns per workgroup
+    static constexpr int NTH = T * TK;
+    static constexpr int SEQ = seq_len(PY);
+};
+
+template <int PY, int PZ>
+constexpr bool use_yz() {
+    return (PZ == 4 || PZ == 8) && PY >= 16 && PY * PZ <= 4096;
+}
+
+template <int PY, int PZ>
+constexpr size_t yz_lds() {
+    return (size_t)YzCfg<PY, PZ>::T * YzCfg<PY, PZ>::G * YzCfg<PY, PZ>::SEQ * sizeof(cf);
+}
+
+// a: spec, col_stride (between kx columns), outer_stride (between z planes),
+// ncol (= kx count), nouter (= nz), n_in (= ny), khat, kyh, kzh, pa (= py).
+template <int PY, int PZ>
+__device__ inline void yz_body(const ColArgs& a, int blk, cf* lds, int tid) {
+    using C = YzCfg<PY, PZ>;
+    constexpr int TPF = C::TPF, PPT = C::PPT, NZM = C::NZM, G = C::G, TK = C::TK, T = C::T, SEQ = C::SEQ;
+    constexpr int MH = PPT / 2;
+    static_assert(use_yz<PY, PZ>() && C::NTH == 768, "thin-grid convolution shape");
+    if (a.check_done && a.st->done) return;
+    const int kc = tid / TK, r = tid - kc * TK;
+    const int g = r / TPF, t = r - g * TPF;
+    const int z = g / 3, c = g - 3 * z;
+    const int nz = a.nouter;
+    const int kx = blk * T + kc;
+    const bool valid = kx < a.ncol && z < nz;
+    cf* col = a.spec + (long long)(kx < a.ncol ? kx : 0) * a.col_stride + (long long)(z < nz ? z : 0) * a.outer_stride + c;
+    cf* buf = lds + (kc * G + g) * SEQ;
+
+    // forward y transform of plane z, component c (rows y < ny <= PY/2)
+    cf v[1][PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int q = t + TPF * m;
+        v[0][m] = (m < MH && valid && q < a.n_in) ? col[3LL * q] : mkc(0.f, 0.f);
+    }
+    RegFft<PY, TPF, 1, false, true>::run(v, buf, a.tw, a.twshift, t);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
+    __syncthreads();
+
+    // along z, one ky at a time: direct DFT of the nz planes, K^ product per
+    // kz, inverse DFT to the nz planes
+    if (kx < a.ncol) {
+        cf wz[PZ];  // exp(-2 pi i j / PZ)
+        const int sh = a.twshift - ilog2(PZ);
+#pragma unroll
+        for (int j = 0; j < PZ; ++j) wz[j] = a.tw[j << sh];
+        cf* cb = lds + kc * G * SEQ;
+        for (int ky = r; ky < PY; ky += TK) {
+            const bool fa = 2 * ky > PY;
+            const int kyh = fa ? PY - ky : ky;
+            const float* K0 = a.khat + ((long long)kx * a.kyh + kyh) * a.kzh * 6;
+            cf X[3][NZM], Y[3][NZM];
+#pragma unroll
+            for (int zz = 0; zz < NZM; ++zz)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    X[cc][zz] = zz < nz ? cb[(3 * zz + cc) * SEQ + lds_pad(ky)] : mkc(0.f, 0.f);
+                    Y[cc][zz] = mkc(0.f, 0.f);
+                }
+#pragma unroll
+            for (int kz = 0; kz < PZ; ++kz) {
+                cf M[3];
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    M[cc] = X[cc][0];
+#pragma unroll
+                    for (int zz = 1; zz < NZM; ++zz) M[cc] = M[cc] + cmul(X[cc][zz], wz[(kz * zz) % PZ]);
+                }
+                const bool fq = 2 * kz > PZ;
+                const float* K = K0 + (fq ? PZ - kz : kz) * 6;
+                float kxy = K[3], kxz = K[4], kyz = K[5];
+                if (fq) {  // xz and yz are odd in z
+                    kxz = -kxz;
+                    kyz = -kyz;
+                }
+                if (fa) {  // xy and yz are odd in y
+                    kxy = -kxy;
+                    kyz = -kyz;
+                }
+                const cf B0 = K[0] * M[0] + kxy * M[1] + kxz * M[2];
+                const cf B1 = kxy * M[0] + K[1] * M[1] + kyz * M[2];
+                const cf B2 = kxz * M[0] + kyz * M[1] + K[2] * M[2];
+#pragma unroll
+                for (int zz = 0; zz < NZM; ++zz) {
+                    const cf w = cconj(wz[(kz * zz) % PZ]);
+                    Y[0][zz] = Y[0][zz] + cmul(B0, w);
+                    Y[1][zz] = Y[1][zz] + cmul(B1, w);
+                    Y[2][zz] = Y[2][zz] + cmul(B2, w);
+                }
+            }
+#pragma unroll
+            for (int zz = 0; zz < NZM; ++zz)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                    if (zz < nz) cb[(3 * zz + cc) * SEQ + lds_pad(ky)] = Y[cc][zz];
+        }
+    }
+    __syncthreads();
+
+    // inverse y transform; rows y < ny are kept
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) v[0][m] = buf[lds_pad(t + TPF * m)];
+    RegFft<PY, TPF, 1, true>::run(v, buf, a.tw, a.twshift, t);
+    int t2 = t;
+    asm volatile("" : "+v"(t2));  // form the store addresses here, not at load time
+#pragma unroll
+    for (int m = 0; m < MH; ++m) {
+        const int q = t2 + TPF * m;
+        if (valid && q < a.n_in) col[3LL * q] = v[0][m];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 2D convolution, one thread group per column carrying all three components
 // (three sequences through one LDS exchange buffer).  The K^ product is then
 // local to the thread, and the twiddles and exchange addresses of a stage

@@ -40,6 +40,11 @@ MB_XCASES(M)
 #define M(p) static_assert(ColCfg<p>::NTH == BX_NTH, "z shape");
 MB_ZCASES(M)
 #undef M
+#define M(p)                                                                                     \
+    static_assert(!use_yz<p, 4>() || (YzCfg<p, 4>::NTH == BX_NTH && yz_lds<p, 4>() == yz_lds<64, 4>()), "yz");  \
+    static_assert(!use_yz<p, 8>() || (YzCfg<p, 8>::NTH == BX_NTH && yz_lds<p, 8>() == yz_lds<64, 8>()), "yz");
+MB_XCASES(M)
+#undef M
 
 template <class T>
 using const_as = const __attribute__((address_space(4))) T;
@@ -119,7 +124,16 @@ __device__ inline ColArgs member_col(const ColArgs& b, const BMember& mb, int i,
     a.kzh = mb.pz / 2 + 1;
     a.pa = mb.py;
     a.pack_col = 0;
-    if (kind == BC_ZCONV) {
+    if (kind == BC_YZ) {
+        // thin 3D member: y FFT, z DFT with K^, inverse y FFT per kx column
+        a.pos_stride = 3;
+        a.col_stride = mb.colstride;
+        a.ncol = mb.kx;
+        a.outer_stride = mb.zstride;
+        a.nouter = mb.nz;
+        a.n_in = mb.ny;
+        a.n_out = mb.ny;
+    } else if (kind == BC_ZCONV) {
         // z convolution of every (kx, ky) column; tiles of adjacent ky
         a.pos_stride = mb.zstride;
         a.col_stride = 3;
@@ -268,6 +282,32 @@ __global__ void __launch_bounds__(BX_NTH) k_bzconv(const BatchList l, const ColA
     }
 }
 
+// thin 3D members of one padded z length (y FFT, z DFT with K^, inverse y FFT)
+template <int PZ>
+__global__ void __launch_bounds__(BX_NTH) __attribute__((amdgpu_waves_per_eu(PZ == 4 ? 6 : 1)))
+k_byz(const BatchList l, const ColArgs b) {
+    extern __shared__ cf lds[];
+    const ItemRange r = item_range(l.nitems);
+    for (int it = r.it; it < r.end; it += r.step) {
+        const unsigned int item = uload(l.items + it);
+        const int i = (int)(item >> 16), blk = (int)(item & 0xffffu);
+        const BMember mb = uload(l.mem + i);
+        const ColArgs a = member_col(b, mb, i, BC_YZ);
+        __syncthreads();
+        const int tid = opaque_tid();
+        switch (mb.py) {
+#define M(q)                                                   \
+    case q:                                                    \
+        if constexpr (use_yz<q, PZ>()) yz_body<q, PZ>(a, blk, lds, tid); \
+        break;
+            MB_XCASES(M)
+#undef M
+            default:
+                break;
+        }
+    }
+}
+
 // After the controllers: members whose step was accepted take m0 <- m_s/|m_s|.
 __global__ void __launch_bounds__(NT) k_bfinalize(const BatchList l, const float* __restrict__ ms,
                                                   float* __restrict__ m, const DevState* __restrict__ st) {
@@ -361,6 +401,33 @@ int col_t(int p) {
     }
 }
 
+// kx columns per workgroup of the thin-grid pass
+int yz_t(int py, int pz) {
+    switch (pz) {
+#define MT(pzv)                                                           \
+    case pzv:                                                             \
+        switch (py) {                                                     \
+            MB_XCASES(MT##pzv)                                            \
+            default:                                                      \
+                return 0;                                                 \
+        }
+#define MTB(q, pzv)                                                       \
+    case q:                                                               \
+        if constexpr (use_yz<q, pzv>()) return YzCfg<q, pzv>::T;          \
+        return 0;
+#define MT4(q) MTB(q, 4)
+#define MT8(q) MTB(q, 8)
+        MT(4)
+        MT(8)
+#undef MT4
+#undef MT8
+#undef MTB
+#undef MT
+        default:
+            return 0;
+    }
+}
+
 int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 // kernel, block size and dynamic LDS of each batched pass
@@ -384,6 +451,10 @@ PassShape pass_shape(int pass) {
             return {(const void*)k_bzconv<8>, BX_NTH, col_lds<8, COL_CONV, 6>()};
         case BP_Z16:
             return {(const void*)k_bzconv<16>, BX_NTH, col_lds<16, COL_CONV, 6>()};
+        case BP_YZ4:
+            return {(const void*)k_byz<4>, BX_NTH, yz_lds<64, 4>()};
+        case BP_YZ8:
+            return {(const void*)k_byz<8>, BX_NTH, yz_lds<64, 8>()};
         case BP_F:
             return {(const void*)k_bfinalize, NT, 0};
         default:
@@ -408,12 +479,17 @@ int batch_tiles(int pass, const BMember& m) {
         case BP_C3:
             return m.pz == 1 ? cdiv(m.px / 2, col3_t(m.py)) : 0;
         case BP_Y:
-            return m.pz > 1 ? cdiv(m.kx, col_t(m.py)) * m.nz : 0;
+            return m.pz > 1 && !yz_supported(m.py, m.pz) ? cdiv(m.kx, col_t(m.py)) * m.nz : 0;
         case BP_Z4:
         case BP_Z8:
         case BP_Z16: {
             const int pz = pass == BP_Z4 ? 4 : (pass == BP_Z8 ? 8 : 16);
-            return m.pz == pz ? cdiv(m.py, col_t(pz)) * m.kx : 0;
+            return m.pz == pz && !yz_supported(m.py, m.pz) ? cdiv(m.py, col_t(pz)) * m.kx : 0;
+        }
+        case BP_YZ4:
+        case BP_YZ8: {
+            const int pz = pass == BP_YZ4 ? 4 : 8;
+            return m.pz == pz && yz_supported(m.py, m.pz) ? cdiv(m.kx, yz_t(m.py, pz)) : 0;
         }
         case BP_F:
             return cdiv((long long)m.nx * m.ny * m.nz, NT);
@@ -495,6 +571,23 @@ hipError_t launch_bzconv(int pass, const BatchList& l, int grid, const ColArgs& 
             break;
         case BP_Z16:
             hipLaunchKernelGGL(k_bzconv<16>, dim3(grid), dim3(BX_NTH), ps.lds, s, l, base);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_byz(int pass, const BatchList& l, int grid, const ColArgs& base, hipStream_t s) {
+    if (l.nitems <= 0) return hipSuccess;
+    if (check_grid(l, grid) != hipSuccess) return hipErrorInvalidValue;
+    const PassShape ps = pass_shape(pass);
+    switch (pass) {
+        case BP_YZ4:
+            hipLaunchKernelGGL(k_byz<4>, dim3(grid), dim3(BX_NTH), ps.lds, s, l, base);
+            break;
+        case BP_YZ8:
+            hipLaunchKernelGGL(k_byz<8>, dim3(grid), dim3(BX_NTH), ps.lds, s, l, base);
             break;
         default:
             return hipErrorInvalidValue;

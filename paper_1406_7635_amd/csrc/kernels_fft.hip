@@ -73,6 +73,14 @@ __global__ void __launch_bounds__(Col3Cfg<P>::NTH, 4) k_col3(const ColArgs a) {
     col3_body<P>(a, xcd_remap(blockIdx.x, gridDim.x), lds, threadIdx.x);
 }
 
+// two workgroups per CU for the two-layer case (the z step of more layers
+// needs the registers of one)
+template <int PY, int PZ>
+__global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(PZ == 4 ? 6 : 1))) k_yz(const ColArgs a) {
+    extern __shared__ cf lds[];
+    yz_body<PY, PZ>(a, xcd_remap(blockIdx.x, gridDim.x), lds, threadIdx.x);
+}
+
 
 // ---------------------------------------------------------------------------
 // Launch helpers: dispatch the run-time padded length to a template instance.
@@ -119,6 +127,14 @@ static hipError_t col_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent
     return hipGetLastError();
 }
 
+template <int PY, int PZ>
+static hipError_t yz_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int nb = (a.ncol + YzCfg<PY, PZ>::T - 1) / YzCfg<PY, PZ>::T;
+    hipExtLaunchKernelGGL((k_yz<PY, PZ>), dim3(nb), dim3(YzCfg<PY, PZ>::NTH), (uint32_t)yz_lds<PY, PZ>(), s, e0, e1,
+                          0, a);
+    return hipGetLastError();
+}
+
 template <int P>
 static hipError_t col3_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const long long nb = (a.ncol + Col3Cfg<P>::T - 1) / Col3Cfg<P>::T;
@@ -141,6 +157,64 @@ static hipError_t configure_x(void) {
     if constexpr (P >= 8)
         if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P>, x_lds<P>());
     return e;
+}
+
+// Dispatch (py, pz) of the thin-grid convolution to f.template operator()<PY, PZ>();
+// returns hipErrorInvalidValue for pairs it does not serve.
+template <class F>
+static hipError_t yz_dispatch(int py, int pz, const F& f) {
+    switch (pz) {
+#define MZ(pzv)                                                                 \
+    case pzv:                                                                   \
+        switch (py) {                                                           \
+            MM_CASES(MY##pzv)                                                   \
+            default:                                                            \
+                return hipErrorInvalidValue;                                    \
+        }
+#define MYB(q, pzv)                                                             \
+    case q:                                                                     \
+        if constexpr (use_yz<q, pzv>()) return f.template operator()<q, pzv>(); \
+        return hipErrorInvalidValue;
+#define MY4(q) MYB(q, 4)
+#define MY8(q) MYB(q, 8)
+        MZ(4)
+        MZ(8)
+#undef MY4
+#undef MY8
+#undef MYB
+#undef MZ
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+struct YzNop {
+    template <int PY, int PZ>
+    hipError_t operator()() const {
+        return hipSuccess;
+    }
+};
+struct YzLaunch {
+    const ColArgs& a;
+    hipStream_t s;
+    hipEvent_t e0, e1;
+    template <int PY, int PZ>
+    hipError_t operator()() const {
+        return yz_p<PY, PZ>(a, s, e0, e1);
+    }
+};
+struct YzConfigure {
+    template <int PY, int PZ>
+    hipError_t operator()() const {
+        return hipFuncSetAttribute((const void*)k_yz<PY, PZ>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)yz_lds<PY, PZ>());
+    }
+};
+
+bool yz_supported(int py, int pz) { return yz_dispatch(py, pz, YzNop{}) == hipSuccess; }
+
+hipError_t launch_yz(int py, int pz, const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    return yz_dispatch(py, pz, YzLaunch{a, s, e0, e1});
 }
 
 template <int P>
@@ -183,6 +257,7 @@ hipError_t configure_field_kernels(int px, int py, int pz) {
             return hipErrorInvalidValue;
     }
     if (e != hipSuccess || pz == 1) return e;
+    if (yz_supported(py, pz)) return yz_dispatch(py, pz, YzConfigure{});
     switch (pz) {
 #define M(p)                    \
     case p:                     \

@@ -35,6 +35,7 @@ struct mm_ctx {
     int nx = 0, ny = 0, nz = 0, nrows = 0;
     double dx = 0, dy = 0, dz = 0;
     int px = 1, py = 1, pz = 1, kx = 1, ncomp = 4;
+    bool yz = false;  // thin 3D grid: y FFT, z DFT with K^ and inverse y FFT in one pass
     long long ncell = 0, colstride = 0, zstride = 0, spec_elems = 0, khat_elems = 0;
     int pt = 1, twshift = 0;
     bool demag_on = true, khat_ready = false;
@@ -151,7 +152,17 @@ int run_cols(mm_ctx* c, bool check_done) {
     ca.kzh = c->pz / 2 + 1;
     ca.pa = c->py;
     Timed t(c, 1);
-    if (c->pz > 1) {
+    if (c->yz) {
+        // thin 3D grid: one pass per kx column over all planes
+        ca.pos_stride = 3;
+        ca.col_stride = c->colstride;
+        ca.ncol = c->kx;
+        ca.outer_stride = c->zstride;
+        ca.nouter = c->nz;
+        ca.n_in = c->ny;
+        ca.n_out = c->ny;
+        MM_TRY(launch_yz(c->py, c->pz, ca, s, t.e1, t.e2));
+    } else if (c->pz > 1) {
         // y transforms of every (z, kx) column, in place (ny rows -> py rows)
         ca.pos_stride = 3;
         ca.col_stride = c->colstride;
@@ -433,7 +444,9 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
     }
     c->kx = c->px / 2 + 1;
     c->ncomp = (c->pz > 1) ? 6 : 4;
-    const long long ycount = (c->pz > 1) ? c->py : c->ny;
+    c->yz = c->pz > 1 && yz_supported(c->py, c->pz);
+    // rows per spectrum column: py when the y transforms run in place, else ny
+    const long long ycount = (c->pz > 1 && !c->yz) ? c->py : c->ny;
     c->colstride = 3LL * ycount;
     c->zstride = (long long)c->kx * c->colstride;
     c->spec_elems = c->zstride * c->nz;

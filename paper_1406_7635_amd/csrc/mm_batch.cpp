@@ -24,7 +24,7 @@ struct mm_batch {
     std::vector<BMember> hmem;
     std::vector<mm_grid> hgrid;
     long long ncell = 0, spec_elems = 0, khat_elems = 0;
-    bool has2d = false, has3d = false;
+    bool has2d = false;
     int pt = 1, twshift = 0;
     // device buffers
     BMember* mem = nullptr;
@@ -141,7 +141,9 @@ int run_cols(mm_batch* b, bool check_done) {
     const ColArgs c = base_col(b, check_done);
     hipStream_t s = b->stream;
     if (b->has2d) MM_TRY(launch_bcol3(list(b, BP_C3), grid_of(b, BP_C3), c, s));
-    if (b->has3d) {
+    for (int p : {BP_YZ4, BP_YZ8})
+        if (b->nitems[p] > 0) MM_TRY(launch_byz(p, list(b, p), grid_of(b, p), c, s));
+    if (b->nitems[BP_Y] > 0) {
         MM_TRY(launch_bcoly(0, list(b, BP_Y), grid_of(b, BP_Y), c, s));
         for (int p : {BP_Z4, BP_Z8, BP_Z16})
             if (b->nitems[p] > 0) MM_TRY(launch_bzconv(p, list(b, p), grid_of(b, p), c, s));
@@ -304,7 +306,8 @@ int mm_batch_create(mm_batch** out, int32_t n, const mm_grid* grids, const mm_pa
         m.cell_off = b->ncell;
         m.spec_off = b->spec_elems;
         m.khat_off = b->khat_elems;
-        m.colstride = 3LL * (m.pz > 1 ? m.py : m.ny);
+        // rows per spectrum column: py when the y transforms run in place, else ny
+        m.colstride = 3LL * (m.pz > 1 && !yz_supported(m.py, m.pz) ? m.py : m.ny);
         m.zstride = (long long)m.kx * m.colstride;
         m.idx2 = (float)(1.0 / (g.dx * g.dx));
         m.idy2 = (float)(1.0 / (g.dy * g.dy));
@@ -314,10 +317,7 @@ int mm_batch_create(mm_batch** out, int32_t n, const mm_grid* grids, const mm_pa
         b->ncell += nc;
         b->spec_elems += m.zstride * m.nz;
         b->khat_elems += (long long)m.kx * (m.py / 2 + 1) * (m.pz / 2 + 1) * (m.pz > 1 ? 6 : 4);
-        if (m.pz > 1)
-            b->has3d = true;
-        else
-            b->has2d = true;
+        if (m.pz == 1) b->has2d = true;
         if (m.px > b->pt) b->pt = m.px;
         if (m.py > b->pt) b->pt = m.py;
         if (m.pz > b->pt) b->pt = m.pz;
@@ -520,6 +520,23 @@ int mm_batch_stats(mm_batch* b, int32_t i, mm_run_stats* out, int32_t* status) {
     return leave(b);
 }
 
+int mm_batch_stats_all(mm_batch* b, mm_run_stats* out, int32_t* status) {
+    if (!b || !out) return MM_EINVAL;
+    MM_CHECK(enter(b));
+    MM_CHECK(sync_states(b));
+    for (int i = 0; i < b->n; ++i) {
+        const DevState& s = b->hst[i];
+        out[i].steps = s.steps;
+        out[i].rejects = s.rejects;
+        out[i].evals = s.evals + (s.steps + s.rejects > 0 ? 1 : 0);
+        out[i].t = s.t;
+        out[i].dt = s.dt;
+        out[i].err = s.err;
+        if (status) status[i] = s.status;
+    }
+    return leave(b);
+}
+
 int mm_batch_set_graph(mm_batch* b, int32_t enable) {
     if (!b) return MM_EINVAL;
     b->use_graph = enable != 0;
@@ -575,6 +592,9 @@ int mm_batch_autotune(mm_batch* b, const float* m_dev) {
             case BP_Z8:
             case BP_Z16:
                 return launch_bzconv(p, list(b, p), g, c, b->stream);
+            case BP_YZ4:
+            case BP_YZ8:
+                return launch_byz(p, list(b, p), g, c, b->stream);
             default:
                 return hipSuccess;
         }

@@ -128,6 +128,11 @@ hipError_t configure_colm(void);
 // m_{s+1} goes to af.ms, which must differ from ai.ms).
 hipError_t launch_xrow(int px, const FieldArgs& ai, const FieldArgs& af, float a_last, hipStream_t s,
                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Thin-grid 3D convolution (y FFT, z DFT with the K^ product, inverse y FFT
+// in one pass per kx column; the spectrum keeps ny rows): padded lengths
+// (py, pz) with pz in {4, 8}, py >= 16 and py pz <= 4096.
+bool yz_supported(int py, int pz);
+hipError_t launch_yz(int py, int pz, const ColArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 int xinv_blocks(int px, int nrows);
 // Raise the dynamic-LDS limit of every pass a grid of padded size px x py x pz
 // launches (once per context, on the current device).
@@ -158,9 +163,20 @@ struct BatchList {
     const unsigned int* items;
     int nitems;
 };
-enum BatchPass { BP_X = 0, BP_C3 = 1, BP_Y = 2, BP_Z4 = 3, BP_Z8 = 4, BP_Z16 = 5, BP_F = 6, BP_N = 7 };
+enum BatchPass {
+    BP_X = 0,     // x passes
+    BP_C3 = 1,    // 2D y convolution
+    BP_Y = 2,     // 3D y transforms (members without the thin-grid pass)
+    BP_Z4 = 3,    // 3D z convolution, padded z length 4 / 8 / 16
+    BP_Z8 = 4,
+    BP_Z16 = 5,
+    BP_YZ4 = 6,   // thin-grid 3D convolution, padded z length 4 / 8
+    BP_YZ8 = 7,
+    BP_F = 8,     // finalisation
+    BP_N = 9
+};
 enum BatchXKind { BX_FWD = 0, BX_ROW = 1, BX_INV = 2 };
-enum BatchColKind { BC_CONV2 = 0, BC_YFWD = 1, BC_YINV = 2, BC_ZCONV = 3 };
+enum BatchColKind { BC_CONV2 = 0, BC_YFWD = 1, BC_YINV = 2, BC_ZCONV = 3, BC_YZ = 4 };
 // Padded lengths the batched passes serve: 64 <= px, py <= 1024, pz in {1, 4, 8, 16}.
 bool batch_supported(int px, int py, int pz);
 // Tiles (work items) of member m in pass p; 0 when the pass does not apply to it.
@@ -180,6 +196,8 @@ hipError_t launch_bcol3(const BatchList& l, int grid, const ColArgs& base, hipSt
 hipError_t launch_bcoly(int inverse, const BatchList& l, int grid, const ColArgs& base, hipStream_t s);
 // z convolution of the members of one padded z length (pass BP_Z4 / BP_Z8 / BP_Z16):
 hipError_t launch_bzconv(int pass, const BatchList& l, int grid, const ColArgs& base, hipStream_t s);
+// thin-grid 3D convolution of the members of one padded z length (pass BP_YZ4 / BP_YZ8):
+hipError_t launch_byz(int pass, const BatchList& l, int grid, const ColArgs& base, hipStream_t s);
 hipError_t launch_bfinalize(const BatchList& l, int grid, const float* ms, float* m, const DevState* st,
                             hipStream_t s);
 hipError_t launch_bcontroller(DevState* st, int n, int last_k, int evals, int check_done, int* active,

@@ -85,6 +85,7 @@ EXPORTS = {
     "mm_batch_start": (c_int32, [c_void_p, c_int32, c_double, c_double, c_double, ctypes.POINTER(SolverOpts)]),
     "mm_batch_run": (c_int32, [c_void_p, c_void_p, c_int64, ctypes.POINTER(c_int64), ctypes.POINTER(c_int32)]),
     "mm_batch_stats": (c_int32, [c_void_p, c_int32, ctypes.POINTER(RunStats), ctypes.POINTER(c_int32)]),
+    "mm_batch_stats_all": (c_int32, [c_void_p, ctypes.POINTER(RunStats), ctypes.POINTER(c_int32)]),
     "mm_batch_set_graph": (c_int32, [c_void_p, c_int32]),
     "mm_batch_set_grid": (c_int32, [c_void_p, c_int32, c_int32]),
     "mm_batch_get_grid": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int32)]),
@@ -315,7 +316,7 @@ class Context:
         return n.value, ms.value
 
 
-BATCH_PASSES = ("x", "conv2d", "y", "z4", "z8", "z16", "finalize")  # mm_batch_set_grid pass ids
+BATCH_PASSES = ("x", "conv2d", "y", "z4", "z8", "z16", "yz4", "yz8", "finalize")  # mm_batch_set_grid pass ids
 
 
 class Batch:
@@ -420,6 +421,14 @@ class Batch:
         d = {k: getattr(st, k) for k, _ in RunStats._fields_}
         d["status"] = status.value
         return d
+
+    def stats_all(self):
+        """Per-member counters as arrays (steps, rejects, evals, t, dt, err, status)."""
+        st, status = (RunStats * self.n)(), (c_int32 * self.n)()
+        _check(load().mm_batch_stats_all(self._h, st, status), "mm_batch_stats_all")
+        out = {k: np.array([getattr(s, k) for s in st]) for k, _ in RunStats._fields_}
+        out["status"] = np.array(list(status))
+        return out
 
     def set_graph(self, enable):
         _check(load().mm_batch_set_graph(self._h, 1 if enable else 0), "mm_batch_set_graph")

@@ -146,7 +146,7 @@ def test_batch_tuned_grids_same_result(gpu):
     grids = b.autotune(m)
     log("  tuned grids", grids)
     for name, g in grids.items():
-        assert g > 0 and g % 8 == 0, name
+        assert g >= 0 and g % 8 == 0, name  # 0: a pass no member uses
     # a small persistent grid as well: every workgroup walks many tiles
     b.set_grid("x", 8)
     m2 = b.pack([c["m0"] for c in members])
