@@ -15,7 +15,6 @@ fraction of the dominant kernel.
 Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -33,15 +32,19 @@ CSRC = os.path.join(ROOT, "paper_1406_7635_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "film1024_rk45_hbm_traffic.txt")
 
 
+# the sources the single-grid field kernels are compiled from (kernels,
+# device bodies, FFT core, epilogue, argument structures)
+PLAIN_KERNEL_SOURCES = ("kernels_fft.hip", "fft_passes.h", "fft_core.h", "field_epilogue.h", "mm_internal.h")
+
+
 def kernel_source_digest():
-    """SHA-256 over every HIP/C++ source and header of the library: measured
+    """SHA-256 over the sources of the single-grid field kernels: measured
     traffic is only reported while the kernels are the ones it was taken on."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(os.path.basename(f).encode())
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+    for name in PLAIN_KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
