@@ -206,3 +206,29 @@ def ensemble(n=512, seed=4, sizes=(32, 64, 128, 256), layers=(1, 2), t_end=1e-9)
                         "m0": random_sphere(grid, 1000 * seed + i), "solver": "rk45", "max_err": 1e-5,
                         "t_end": t_end})
     return members
+
+
+# Spectral neural operator (the surrogate of the magnetostatic field): 32
+# channels, kept modes kx = 0..15, ky = -8..7, four layers.  Flat weight order:
+# P[32][3], p[32], then per layer R[16 ky][16 kx][32 o][32 c][re, im], W[32][32],
+# b[32], then Q[3][32], q[3].
+SNO_C, SNO_KX, SNO_KY, SNO_LAYERS = 32, 16, 16, 4
+SNO_NWEIGHTS = SNO_C * 3 + SNO_C + SNO_LAYERS * (SNO_KY * SNO_KX * SNO_C * SNO_C * 2 + SNO_C * SNO_C + SNO_C) \
+    + 3 * SNO_C + 3
+
+
+def sno_random_weights(seed, scale=1.0):
+    """Seeded surrogate weights in the flat order above: pointwise weights
+    N(0, 1/fan_in), spectral weights N(0, 1) / C per real and imaginary part,
+    small biases; float32."""
+    rng = _rng(seed)
+    c = SNO_C
+    parts = [rng.standard_normal((c, 3)) / np.sqrt(3.0) * scale, 0.1 * rng.standard_normal(c)]
+    for _ in range(SNO_LAYERS):
+        parts.append(rng.standard_normal((SNO_KY, SNO_KX, c, c, 2)) * scale / c)
+        parts.append(rng.standard_normal((c, c)) / np.sqrt(c) * scale)
+        parts.append(0.1 * rng.standard_normal(c))
+    parts += [rng.standard_normal((3, c)) / np.sqrt(c) * scale, 0.01 * rng.standard_normal(3)]
+    out = np.concatenate([np.ravel(a) for a in parts]).astype(np.float32)
+    assert out.size == SNO_NWEIGHTS
+    return out
