@@ -331,6 +331,31 @@ int mm_batch_get_grid(mm_batch *b, int32_t pass, int32_t *grid);
 int mm_batch_autotune(mm_batch *b, const float *m_dev);
 void mm_batch_destroy(mm_batch *b);
 
+/* ---- Surrogate of the magnetostatic field ---------------------------------
+ * A spectral neural operator (not part of the paper's method: a learned
+ * stand-in for the convolution of section "Magnetostatic field") maps m on an
+ * nx x ny x 1 grid to a prediction of B_demag:
+ *   lift      h_c = sum_j P[c][j] m_j + p[c]                         (32 channels)
+ *   4 layers  hhat_c(k) = sum_{x,y} h_c exp(-2 pi i (kx x/nx + ky y/ny)) for the kept
+ *             modes kx = 0..15, ky = -8..7; ghat_o(k) = sum_c R[ky+8][kx][o][c] hhat_c(k);
+ *             g_o = Re sum_k w_kx ghat_o(k) exp(+2 pi i (...)) / (nx ny) (w_0 = 1, else 2);
+ *             h_o <- GELU(g_o + sum_c W[o][c] h_c + b[o]) with GELU(z) = z (1 + erf(z/sqrt 2))/2
+ *   project   B_j = out_scale (sum_c Q[j][c] h_c + q[j])
+ * weights: host FP32 array of MM_SNO_NWEIGHTS values in the order P[32][3],
+ * p[32], then per layer R[16][16][32][32][re,im], W[32][32], b[32], then
+ * Q[3][32], q[3]; stored on the device rounded to BF16 (nearest even), all
+ * arithmetic FP32.  32 <= nx <= 512, 16 <= ny <= 4096, else MM_EUNSUPPORTED;
+ * a wrong count gives MM_EINVAL.  Work is enqueued on hip_stream. */
+#define MM_SNO_NWEIGHTS 2101603
+typedef struct mm_sno mm_sno;
+int mm_sno_create(mm_sno **out, int32_t nx, int32_t ny, const float *weights, int64_t nweights,
+                  double out_scale, void *hip_stream);
+/* Replace the weights (synchronises the stream first). */
+int mm_sno_set_weights(mm_sno *s, const float *weights, int64_t nweights);
+/* Predicted B_demag [3][ny][nx] of m [3][ny][nx] (device pointers). */
+int mm_sno_eval(mm_sno *s, const float *m_dev, float *b_dev);
+void mm_sno_destroy(mm_sno *s);
+
 void mm_destroy(mm_ctx *c);
 const char *mm_strerror(int status);
 

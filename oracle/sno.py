@@ -95,7 +95,7 @@ def mode_matrices(nx, ny, kx=KX, ky=KY):
 
 def forward_modes(h, fx, fy):
     """hhat[c, j, kx] = sum_{y,x} h[c, y, x] Fy[j, y] Fx[kx, x] for fields h[c, ny, nx]."""
-    return np.einsum("jy,cyx,kx->cjk", fy, h, fx)
+    return np.einsum("jy,cyx,kx->cjk", fy, h, fx, optimize=True)
 
 
 def inverse_modes(g_hat, fx, fy, nx, ny):
@@ -103,7 +103,7 @@ def inverse_modes(g_hat, fx, fy, nx, ny):
     g[c, y, x] = Re sum_{j,kx} w_kx ghat[c, j, kx] conj(Fy[j, y]) conj(Fx[kx, x]) / (nx ny)."""
     wk = np.full(fx.shape[0], 2.0)
     wk[0] = 1.0
-    z = np.einsum("cjk,jy,kx->cyx", g_hat * wk[None, None, :], np.conj(fy), np.conj(fx))
+    z = np.einsum("cjk,jy,kx->cyx", g_hat * wk[None, None, :], np.conj(fy), np.conj(fx), optimize=True)
     return z.real / (nx * ny)
 
 

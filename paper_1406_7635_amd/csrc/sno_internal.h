@@ -1,0 +1,43 @@
+// sno_internal.h -- device arguments and launchers of the spectral neural
+// operator (kernels_sno.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mm {
+
+constexpr int SNO_C = 32;       // channels
+constexpr int SNO_KX = 16;      // kept kx = 0 .. 15
+constexpr int SNO_KY = 16;      // kept ky = -8 .. 7
+constexpr int SNO_LAYERS = 4;
+// flat weight layout: P[32][3], p[32], per layer R[16][16][32][32][2], W[32][32], b[32], then Q[3][32], q[3]
+constexpr long long SNO_LAYER_W = (long long)SNO_KY * SNO_KX * SNO_C * SNO_C * 2 + SNO_C * SNO_C + SNO_C;
+constexpr long long SNO_NWEIGHTS = SNO_C * 3 + SNO_C + SNO_LAYERS * SNO_LAYER_W + 3 * SNO_C + 3;
+
+struct SnoArgs {
+    int nx, ny, n;                 // grid, n = nx ny
+    float scale;                   // output units (B = scale * projection)
+    const uint16_t* lift;          // BF16 weights, pointers into one array
+    const uint16_t* lift_b;
+    const uint16_t* spec[SNO_LAYERS];
+    const uint16_t* pw[SNO_LAYERS];
+    const uint16_t* pw_b[SNO_LAYERS];
+    const uint16_t* proj;
+    const uint16_t* proj_b;
+    const float2* twx;             // exp(-2 pi i m / nx), m < nx
+    const float2* twy;             // exp(-2 pi i m / ny), m < ny
+    float* h0;                     // activations [32][ny][nx] (two buffers)
+    float* h1;
+    float2* H1;                    // [32][ny][16] after the x transform
+    float2* Hh;                    // [32][16][16] kept modes
+    float2* Gh;                    // [32][16][16] mixed modes
+    float2* G1;                    // [32][ny][16] after the inverse y transform
+};
+
+hipError_t sno_twiddles(float2* tw, int n, hipStream_t s);
+// the whole forward pass: m [3][n] -> out [3][n]
+hipError_t sno_forward(const SnoArgs& a, const float* m, float* out, hipStream_t s);
+size_t sno_dftx_lds(int nx);
+
+}  // namespace mm

@@ -91,6 +91,11 @@ EXPORTS = {
     "mm_batch_get_grid": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int32)]),
     "mm_batch_autotune": (c_int32, [c_void_p, c_void_p]),
     "mm_batch_destroy": (None, [c_void_p]),
+    "mm_sno_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, c_int32, c_void_p, c_int64, c_double,
+                                c_void_p]),
+    "mm_sno_set_weights": (c_int32, [c_void_p, c_void_p, c_int64]),
+    "mm_sno_eval": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "mm_sno_destroy": (None, [c_void_p]),
     "mm_destroy": (None, [c_void_p]),
     "mm_strerror": (ctypes.c_char_p, [c_int32]),
 }
@@ -446,3 +451,50 @@ class Batch:
     def autotune(self, m):
         _check(load().mm_batch_autotune(self._h, _ptr(self._vec(m))), "mm_batch_autotune")
         return {name: self.get_grid(i) for i, name in enumerate(BATCH_PASSES)}
+
+
+SNO_NWEIGHTS = 2101603  # MM_SNO_NWEIGHTS
+
+
+class Surrogate:
+    """The spectral neural operator (mm_sno_*): predicted B_demag of m on an
+    nx x ny x 1 grid, B = out_scale * network(m).  weights: the flat FP32
+    array (numpy), rounded to BF16 by the library."""
+
+    def __init__(self, nx, ny, weights, out_scale, stream=None):
+        import torch
+
+        self._torch = torch
+        self.grid = (int(nx), int(ny), 1)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        h = c_void_p()
+        _check(load().mm_sno_create(ctypes.byref(h), int(nx), int(ny), w.ctypes.data_as(c_void_p), w.size,
+                                    float(out_scale), c_void_p(self._stream.cuda_stream)), "mm_sno_create")
+        self._h = h
+
+    def set_weights(self, weights):
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        _check(load().mm_sno_set_weights(self._h, w.ctypes.data_as(c_void_p), w.size), "mm_sno_set_weights")
+
+    def __call__(self, m, out=None):
+        nx, ny, _ = self.grid
+        t = self._torch
+        if not isinstance(m, t.Tensor) or m.dtype != t.float32 or m.numel() != 3 * nx * ny \
+                or not m.is_contiguous() or m.device != self.device:
+            raise ValueError("m must be a contiguous float32 tensor of 3 x %d x %d on %s" % (ny, nx, self.device))
+        b = out if out is not None else t.empty((3, 1, ny, nx), dtype=t.float32, device=self.device)
+        _check(load().mm_sno_eval(self._h, _ptr(m), _ptr(b)), "mm_sno_eval")
+        return b
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mm_sno_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
