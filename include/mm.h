@@ -355,6 +355,19 @@ int mm_sno_set_weights(mm_sno *s, const float *weights, int64_t nweights);
 /* Predicted B_demag [3][ny][nx] of m [3][ny][nx] (device pointers). */
 int mm_sno_eval(mm_sno *s, const float *m_dev, float *b_dev);
 void mm_sno_destroy(mm_sno *s);
+/* Let mm_run with solver 45 (magnetostatic term on, nz = 1, the surrogate's
+ * grid equal to the context's) take B_demag from the surrogate at the inner
+ * stages 2..6 of every Dormand-Prince attempt.  The last stage, at the new
+ * state, is always exact; there the surrogate's prediction is compared with
+ * the exact field, err = max_cells |B_sur - B_exact| / max_cells |B_exact|,
+ * and if err > tol (or is not finite) the attempt is rejected with dt kept and
+ * the rest of that mm_run call uses the exact path (fallback).  The surrogate
+ * must outlive its use; s = NULL detaches it.  Allocates two field buffers
+ * the first time.  Synchronises. */
+int mm_set_surrogate(mm_ctx *c, const mm_sno *s, double tol);
+/* Accepted steps taken with surrogate stages since mm_set_surrogate,
+ * fallbacks since the last solver restart, err of the last checked attempt. */
+int mm_surrogate_stats(mm_ctx *c, int64_t *sur_steps, int64_t *fallbacks, double *last_err);
 
 void mm_destroy(mm_ctx *c);
 const char *mm_strerror(int status);

@@ -85,7 +85,9 @@ hipError_t launch_combine(const FieldArgs& a, hipStream_t s) {
 }
 
 // Field pass without the magnetostatic term: one thread per cell.
-__global__ void __launch_bounds__(NT) k_local(const FieldArgs a) {
+// Field pass without the convolution: one thread per cell; the magnetostatic
+// field is zero, or taken from bd_in (the surrogate's prediction).
+__global__ void __launch_bounds__(NT) k_local(const FieldArgs a, const float* __restrict__ bd_in) {
     __shared__ double red[(NT / 64) * 6];
     const Resolved rs = resolve(a);
     if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
@@ -97,15 +99,80 @@ __global__ void __launch_bounds__(NT) k_local(const FieldArgs a) {
         const long long r = i / a.nx;
         const int y = (int)(r % a.ny), z = (int)(r / a.ny);
         const float* mp = a.sd.nk > 0 ? a.ms : a.m0;
-        epilogue(a, rs, a.lut, mp, i, x, y, z, make_float3(0.f, 0.f, 0.f), acc);
+        const float3 bd = bd_in ? ld3(bd_in, a.ncell, i) : make_float3(0.f, 0.f, 0.f);
+        epilogue(a, rs, a.lut, mp, i, x, y, z, bd, acc);
     }
     if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NT>(a, acc, red, blockIdx.x);
 }
 
-hipError_t launch_local(const FieldArgs& a, hipStream_t s, int* nblocks_out) {
+hipError_t launch_local(const FieldArgs& a, hipStream_t s, int* nblocks_out, const float* bd_in) {
     const int nb = (int)((a.ncell + NT - 1) / NT);
     if (nblocks_out) *nblocks_out = nb;
-    hipLaunchKernelGGL(k_local, dim3(nb), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL(k_local, dim3(nb), dim3(NT), 0, s, a, bd_in);
+    return hipGetLastError();
+}
+
+// max over cells of |b_sur - b_exact| and of |b_exact| (atomics on the float
+// bits of non-negative values)
+__global__ void __launch_bounds__(NT) k_sur_check(const float* __restrict__ bs, const float* __restrict__ be,
+                                                  long long n, DevState* st) {
+    __shared__ float red[2][NT / 64];
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    float dn = 0.f, en = 0.f;
+    if (i < n) {
+        const float3 s3 = ld3(bs, n, i), e3 = ld3(be, n, i);
+        const float3 d = f3sub(s3, e3);
+        dn = sqrtf(f3dot(d, d));
+        en = sqrtf(f3dot(e3, e3));
+        if (!(dn == dn)) dn = INFINITY;  // a NaN prediction fails the check
+    }
+    dn = wave_max(dn);
+    en = wave_max(en);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wave] = dn;
+        red[1][wave] = en;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float a = 0.f, b = 0.f;
+        for (int w = 0; w < NT / 64; ++w) {
+            a = fmaxf(a, red[0][w]);
+            b = fmaxf(b, red[1][w]);
+        }
+        atomicMax(&st->sur_num_bits, __float_as_uint(a));
+        atomicMax(&st->sur_den_bits, __float_as_uint(b));
+    }
+}
+
+hipError_t launch_sur_check(const float* b_sur, const float* b_exact, long long ncell, DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_sur_check, dim3((unsigned)((ncell + NT - 1) / NT)), dim3(NT), 0, s, b_sur, b_exact, ncell,
+                       st);
+    return hipGetLastError();
+}
+
+__global__ void k_sur_gate(DevState* st, double tol) {
+    const double num = (double)__uint_as_float(st->sur_num_bits);
+    const double den = (double)__uint_as_float(st->sur_den_bits);
+    st->sur_num_bits = 0u;
+    st->sur_den_bits = 0u;
+    const double err = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+    st->sur_err = err;
+    if (!(err <= tol)) {
+        st->sur_fail = 1;
+        st->sur_fallbacks += 1;
+    }
+}
+
+hipError_t launch_sur_gate(DevState* st, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_sur_gate, dim3(1), dim3(1), 0, s, st, tol);
+    return hipGetLastError();
+}
+
+__global__ void k_sur_clear(DevState* st) { st->sur_fail = 0; }
+
+hipError_t launch_sur_clear(DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_sur_clear, dim3(1), dim3(1), 0, s, st);
     return hipGetLastError();
 }
 

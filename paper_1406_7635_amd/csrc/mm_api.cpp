@@ -10,6 +10,7 @@
 #include "../../include/mm.h"
 #include "mm_internal.h"
 #include "api_common.h"
+#include "sno_internal.h"
 #include "tableau.h"
 
 using namespace mm;
@@ -60,6 +61,13 @@ struct mm_ctx {
     int fsal_precess = -1;
     int fsal_solver = 0;
     TimingClass timing[NTIMING];
+    // surrogate of the magnetostatic field at the inner Dormand-Prince stages
+    const mm_sno* sno = nullptr;
+    double sur_tol = 1e-4;
+    bool sur_active = false;  // this run still uses it (cleared by a fallback)
+    float* bsur = nullptr;    // its prediction [3][ncell]
+    float* bexact = nullptr;  // the exact B_demag of the last stage [3][ncell]
+    long long sur_steps = 0;  // accepted steps taken with surrogate stages
 };
 
 namespace {
@@ -71,8 +79,8 @@ hipError_t dalloc(mm_ctx* c, void** p, size_t bytes) {
 }
 
 void free_all(mm_ctx* c) {
-    void* ptrs[] = {c->region, c->params64, c->lut, c->ptab, c->tw, c->spec,
-                    c->khat,   c->kbuf,     c->ms,  c->ms2,  c->st, c->partials, c->dft_tab};
+    void* ptrs[] = {c->region, c->params64, c->lut, c->ptab, c->tw,       c->spec,    c->khat,
+                    c->kbuf,   c->ms,       c->ms2, c->st,   c->partials, c->dft_tab, c->bsur, c->bexact};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hst) (void)hipHostFree(c->hst);
@@ -285,12 +293,44 @@ FieldArgs stage_args(mm_ctx* c, float* m, const Tableau& tb, int s, int precess,
     return a;
 }
 
+// One Dormand-Prince attempt whose inner stages 2..S-1 take the magnetostatic
+// field from the surrogate (stage combine, surrogate, local terms and torque);
+// the last stage, at the new state, is exact and also writes B_demag, which
+// the surrogate's prediction at the same state is checked against before the
+// controller (a miss rejects the attempt with dt kept).
+int attempt_surrogate(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done) {
+    const int S = tb.stages;
+    hipStream_t s = c->stream;
+    for (int st = 1; st < S - 1; ++st) {
+        FieldArgs a = stage_args(c, m, tb, st, precess, check_done);
+        a.flags |= EPI_HAS_DEMAG;
+        MM_TRY(launch_combine(a, s));
+        MM_TRY(sno_run(c->sno, c->ms, c->bsur, s));
+        MM_TRY(launch_local(a, s, nullptr, c->bsur));
+    }
+    FieldArgs al = stage_args(c, m, tb, S - 1, precess, check_done);
+    al.flags |= EPI_BDEMAG;
+    al.bdemag = c->bexact;
+    MM_CHECK(run_field(c, al, nullptr));
+    MM_TRY(sno_run(c->sno, c->ms, c->bsur, s));
+    MM_TRY(launch_sur_check(c->bsur, c->bexact, c->ncell, c->st, s));
+    MM_TRY(launch_sur_gate(c->st, c->sur_tol, s));
+    MM_TRY(launch_controller(c->st, S - 1, S - 1, check_done ? 1 : 0, s));
+    FieldArgs f = base_args(c, m);
+    MM_TRY(launch_finalize(f, s));
+    return MM_OK;
+}
+
 // One attempt of an embedded pair: stages 2..S, controller, finalisation.
 // With the magnetostatic term (and px >= 8) the x-inverse pass of every inner
 // stage and the x-forward pass of the next one run as one fused pass; the
 // stage state then alternates between two buffers.
 int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done) {
     const int S = tb.stages;
+    if (c->sur_active && c->demag_on && S == 7) {
+        if (!c->khat_ready) return MM_ESTATE;
+        return attempt_surrogate(c, m, tb, precess, check_done);
+    }
     float* fin_ms = c->ms;
     if (c->demag_on && c->px >= 8 && S > 2) {
         if (!c->khat_ready) return MM_ESTATE;
@@ -623,15 +663,28 @@ int mm_run(mm_ctx* c, float* m_dev, int32_t solver, double t_end, int64_t max_at
     long long per = (long long)(3e7 / (double)c->ncell);
     if (per < 4) per = 4;
     if (per > 64) per = 64;
+    // with the surrogate every attempt is checked on the host: after a miss the
+    // rest of the run takes the exact path
+    c->sur_active = c->sno != nullptr && solver == 45 && c->demag_on;
     long long done_attempts = 0;
     while (done_attempts < max_attempts) {
         long long nb = max_attempts - done_attempts;
         if (nb > per) nb = per;
+        if (c->sur_active) nb = 1;
         for (long long i = 0; i < nb; ++i) MM_CHECK(attempt(c, m_dev, tb, op.precess, true));
         done_attempts += nb;
         MM_CHECK(sync_state(c));
+        if (c->sur_active) {
+            if (c->hst->sur_fail) {
+                c->sur_active = false;
+                MM_TRY(launch_sur_clear(c->st, c->stream));
+            } else if (c->hst->accepted) {
+                ++c->sur_steps;
+            }
+        }
         if (c->hst->done) break;
     }
+    c->sur_active = false;
     c->fsal_valid = true;
     c->fsal_m = m_dev;
     c->fsal_precess = op.precess;
@@ -777,6 +830,37 @@ int mm_set_conv_precision(mm_ctx* c, int32_t prec) {
     MM_TRY(hipStreamSynchronize(c->stream));
     c->conv_prec = prec;
     c->fsal_valid = false;
+    return MM_OK;
+}
+
+int mm_set_surrogate(mm_ctx* c, const mm_sno* s, double tol) {
+    if (!c) return MM_EINVAL;
+    if (!s) {
+        c->sno = nullptr;
+        return MM_OK;
+    }
+    if (!(tol > 0.0)) return MM_EINVAL;
+    int nx = 0, ny = 0;
+    sno_grid(s, &nx, &ny);
+    if (c->nz != 1 || nx != c->nx || ny != c->ny) return MM_EUNSUPPORTED;
+    if (!c->bsur) {
+        MM_TRY(dalloc(c, (void**)&c->bsur, (size_t)3 * c->ncell * sizeof(float)));
+        MM_TRY(dalloc(c, (void**)&c->bexact, (size_t)3 * c->ncell * sizeof(float)));
+    }
+    MM_TRY(hipStreamSynchronize(c->stream));
+    c->sno = s;
+    c->sur_tol = tol;
+    c->sur_steps = 0;
+    c->fsal_valid = false;
+    return MM_OK;
+}
+
+int mm_surrogate_stats(mm_ctx* c, int64_t* sur_steps, int64_t* fallbacks, double* last_err) {
+    if (!c) return MM_EINVAL;
+    MM_CHECK(sync_state(c));
+    if (sur_steps) *sur_steps = c->sur_steps;
+    if (fallbacks) *fallbacks = c->hst->sur_fallbacks;
+    if (last_err) *last_err = c->hst->sur_err;
     return MM_OK;
 }
 

@@ -36,6 +36,12 @@ struct DevState {
     long long steps, rejects, evals;
     long long target_steps;     // > 0: the run is done once steps reaches it
     double red[8];              // results of FP64 reductions (energies)
+    // surrogate check of an attempt whose inner stages used the surrogate:
+    // max |B_sur - B_exact| and max |B_exact| over cells at the new state
+    unsigned int sur_num_bits, sur_den_bits;
+    double sur_err;             // their ratio for the last checked attempt
+    int sur_fail;               // the last attempt exceeded the tolerance: rejected, dt kept
+    long long sur_fallbacks;
 };
 
 // One torque evaluation inside a Runge-Kutta step.
@@ -211,7 +217,14 @@ hipError_t launch_prepare_tables(const double* params64, RegionLut* lut, float* 
                                  hipStream_t s);
 hipError_t launch_twiddles(cf* tw, int pt, hipStream_t s);
 hipError_t launch_combine(const FieldArgs& a, hipStream_t s);
-hipError_t launch_local(const FieldArgs& a, hipStream_t s, int* nblocks_out);
+// bd_in (optional): a magnetostatic field [3][ncell] to use instead of none
+hipError_t launch_local(const FieldArgs& a, hipStream_t s, int* nblocks_out, const float* bd_in = nullptr);
+// Surrogate check: accumulate max |b_sur - b_exact| and max |b_exact| (cell
+// vectors) into st, then (gate) their ratio; above tol (or not finite) the
+// attempt is marked failed.  sur_clear resets the failure flag.
+hipError_t launch_sur_check(const float* b_sur, const float* b_exact, long long ncell, DevState* st, hipStream_t s);
+hipError_t launch_sur_gate(DevState* st, double tol, hipStream_t s);
+hipError_t launch_sur_clear(DevState* st, hipStream_t s);
 hipError_t launch_llg(const FieldArgs& a, const float* beff, float* tau, int precess,
                       hipStream_t s);
 hipError_t launch_set_state(DevState* st, double t, double dt, double t_end, double max_err,

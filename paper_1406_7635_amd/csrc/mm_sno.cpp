@@ -58,6 +58,16 @@ int upload(mm_sno* s, const float* weights, int64_t nweights) {
 
 }  // namespace
 
+namespace mm {
+hipError_t sno_run(const mm_sno* s, const float* m, float* out, hipStream_t stream) {
+    return sno_forward(s->args, m, out, stream);
+}
+void sno_grid(const mm_sno* s, int* nx, int* ny) {
+    *nx = s->nx;
+    *ny = s->ny;
+}
+}  // namespace mm
+
 extern "C" {
 
 int mm_sno_create(mm_sno** out, int32_t nx, int32_t ny, const float* weights, int64_t nweights, double out_scale,

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/mm.h"
+
 namespace mm {
 
 constexpr int SNO_C = 32;       // channels
@@ -36,6 +38,9 @@ struct SnoArgs {
 };
 
 hipError_t sno_twiddles(float2* tw, int n, hipStream_t s);
+// the forward pass of a created surrogate on a given stream, and its grid
+hipError_t sno_run(const mm_sno* s, const float* m, float* out, hipStream_t stream);
+void sno_grid(const mm_sno* s, int* nx, int* ny);
 // the whole forward pass: m [3][n] -> out [3][n]
 hipError_t sno_forward(const SnoArgs& a, const float* m, float* out, hipStream_t s);
 size_t sno_dftx_lds(int nx);

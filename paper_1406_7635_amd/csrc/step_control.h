@@ -30,10 +30,15 @@ __device__ inline void set_state(DevState* st, double t, double dt, double t_end
     st->accepted = 0;
     st->done = 0;
     st->target_steps = target_steps;
+    st->sur_num_bits = 0u;
+    st->sur_den_bits = 0u;
+    st->sur_fail = 0;
     if (reset_counters) {
         st->steps = st->rejects = st->evals = 0;
         st->status = 0;
         st->err = 0.0;
+        st->sur_err = 0.0;
+        st->sur_fallbacks = 0;
     }
     if (init_perm)
         for (int i = 0; i < 8; ++i) st->perm[i] = i;
@@ -42,6 +47,14 @@ __device__ inline void set_state(DevState* st, double t, double dt, double t_end
 __device__ inline void controller_update(DevState* st, int last_k, int evals, int check_done) {
     if (check_done && st->done) {
         st->accepted = 0;  // a no-op attempt after the run ended: nothing to finalise
+        return;
+    }
+    if (st->sur_fail) {
+        // the surrogate missed its tolerance: reject, keep dt (the host repeats
+        // the step on the exact path)
+        st->accepted = 0;
+        st->err_bits = 0u;
+        st->evals += evals;
         return;
     }
     const double emax = (double)__uint_as_float(st->err_bits);

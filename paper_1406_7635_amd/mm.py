@@ -96,6 +96,9 @@ EXPORTS = {
     "mm_sno_set_weights": (c_int32, [c_void_p, c_void_p, c_int64]),
     "mm_sno_eval": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "mm_sno_destroy": (None, [c_void_p]),
+    "mm_set_surrogate": (c_int32, [c_void_p, c_void_p, c_double]),
+    "mm_surrogate_stats": (c_int32, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64),
+                                     ctypes.POINTER(c_double)]),
     "mm_destroy": (None, [c_void_p]),
     "mm_strerror": (ctypes.c_char_p, [c_int32]),
 }
@@ -311,6 +314,20 @@ class Context:
         precision on the matrix cores (2D grids with padded y length 2048)."""
         _check(load().mm_set_conv_precision(self._h, PREC[prec] if isinstance(prec, str) else int(prec)),
                "mm_set_conv_precision")
+
+    def set_surrogate(self, surrogate, tol=1e-4):
+        """Inner Dormand-Prince stages of run() take B_demag from `surrogate`
+        (an mm.Surrogate, or None to detach), checked against the exact field
+        at every attempt's last stage; a miss falls back to the exact path."""
+        self._surrogate = surrogate
+        _check(load().mm_set_surrogate(self._h, surrogate._h if surrogate is not None else c_void_p(0),
+                                       float(tol)), "mm_set_surrogate")
+
+    def surrogate_stats(self):
+        n, f, e = c_int64(), c_int64(), c_double()
+        _check(load().mm_surrogate_stats(self._h, ctypes.byref(n), ctypes.byref(f), ctypes.byref(e)),
+               "mm_surrogate_stats")
+        return {"surrogate_steps": n.value, "fallbacks": f.value, "last_err": e.value}
 
     def timing_enable(self, which, enable=True):
         _check(load().mm_timing_enable(self._h, int(which), 1 if enable else 0), "mm_timing_enable")

@@ -232,3 +232,50 @@ def sno_random_weights(seed, scale=1.0):
     out = np.concatenate([np.ravel(a) for a in parts]).astype(np.float32)
     assert out.size == SNO_NWEIGHTS
     return out
+
+
+def film_textures(n, seed=5, grid=(256, 256), cell=4e-9, msat=8e5, aex=1.3e-11):
+    """Seeded magnetisation textures on an nx x ny x 1 film, FP32 [n, 3, 1, ny, nx]:
+    a mixture of (i) domains (2-6 random directions over a smooth partition
+    of the plane, walls of width about pi l_ex, l_ex = sqrt(2 Aex/(mu0 Msat^2))),
+    (ii) vortices with random centre, chirality and polarity, (iii) spirals
+    with wavelength 8-256 nm along a random direction, each with added
+    N(0, s^2) noise, s ~ U(0, 0.1), and renormalised."""
+    rng = _rng(seed)
+    nx, ny = grid
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    x = (x + 0.5) * cell
+    y = (y + 0.5) * cell
+    lex = np.sqrt(2 * aex / (4e-7 * np.pi * msat * msat))
+    width = np.pi * lex
+    out = np.empty((n, 3, 1, ny, nx), dtype=np.float32)
+    for i in range(n):
+        kind = i % 3
+        if kind == 0:
+            k = int(rng.integers(2, 7))
+            cx = rng.uniform(0, nx * cell, k)
+            cy = rng.uniform(0, ny * cell, k)
+            u = _unit(rng.standard_normal((3, k)))
+            d = np.sqrt((x[None] - cx[:, None, None]) ** 2 + (y[None] - cy[:, None, None]) ** 2)
+            w = np.exp(-(d - d.min(axis=0)) / width)
+            m = np.einsum("ck,kyx->cyx", u, w / w.sum(axis=0))
+        elif kind == 1:
+            cx, cy = rng.uniform(0.2, 0.8) * nx * cell, rng.uniform(0.2, 0.8) * ny * cell
+            chir = rng.choice([-1.0, 1.0])
+            pol = rng.choice([-1.0, 1.0])
+            rc = rng.uniform(1.0, 3.0) * lex
+            phi = np.arctan2(y - cy, x - cx)
+            r2 = (x - cx) ** 2 + (y - cy) ** 2
+            mz = pol * np.exp(-r2 / (rc * rc))
+            s = np.sqrt(np.maximum(0.0, 1 - mz * mz))
+            m = np.stack([-chir * np.sin(phi) * s, chir * np.cos(phi) * s, mz])
+        else:
+            lam = np.exp(rng.uniform(np.log(8e-9), np.log(256e-9)))
+            th = rng.uniform(0, 2 * np.pi)
+            ph = 2 * np.pi * (np.cos(th) * x + np.sin(th) * y) / lam + rng.uniform(0, 2 * np.pi)
+            a = _unit(rng.standard_normal(3))
+            b = _unit(np.cross(a, rng.standard_normal(3)))
+            m = a[:, None, None] * np.cos(ph)[None] + b[:, None, None] * np.sin(ph)[None]
+        m = m + rng.uniform(0, 0.1) * rng.standard_normal(m.shape)
+        out[i, :, 0] = _unit(m).astype(np.float32)
+    return out
