@@ -249,6 +249,75 @@ def ensemble_variant(steps, warmup, n=512):
             "dtype": "f32"}
 
 
+def surrogate_variant(steps, warmup):
+    """The surrogate workload: 256 x 256 x 1 film of 4 nm cells (Msat 8e5,
+    Aex 1.3e-11, alpha 0.01), trained weights.  Reports the surrogate's
+    relative B_demag error (max over cells, against the exact FP32 field) on
+    held-out textures, the durations of one surrogate evaluation and of one
+    exact field evaluation, the Dormand-Prince throughput with surrogate
+    stages at the 1e-4 tolerance (falls back to the exact path on the first
+    miss) and with the check disabled (every attempt keeps the surrogate)."""
+    import torch
+
+    from paper_1406_7635_amd import mm, sno_train, synth
+
+    n, cell, msat = 256, 4e-9, 8e5
+    ncell = n * n
+    params = synth.material(msat, 1.3e-11, alpha=0.01)
+    region = np.zeros((1, n, n), dtype=np.uint8)
+    w = sno_train.load_weights()
+    ctx = mm.Context((n, n, 1), (cell, cell, cell), region, params)
+    sur = mm.Surrogate(n, n, w, 4e-7 * np.pi * msat)
+    errs = []
+    for m0 in synth.film_textures(24, seed=6, grid=(n, n), cell=cell):
+        m = torch.from_numpy(m0).cuda()
+        _, bd = ctx.beff(m, want_demag=True)
+        bs = sur(m)
+        errs.append(float((bs - bd).norm(dim=0).max() / bd.norm(dim=0).max()))
+    m = torch.from_numpy(synth.film_textures(2, seed=7, grid=(n, n), cell=cell)[1]).cuda()  # a vortex
+    out = torch.empty_like(m)
+
+    def per_call_us(fn, reps=50):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return 1e3 * e0.elapsed_time(e1) / reps
+
+    sno_us = per_call_us(lambda: sur(m, out))
+    exact_us = per_call_us(lambda: ctx.beff(m))
+
+    def run(tol):
+        ctx.set_surrogate(sur if tol is not None else None, tol if tol is not None else 1.0)
+        mm_ = m.clone()
+        t, dt, _ = ctx.run(mm_, float("inf"), dt=1e-14, max_attempts=warmup, opts=mm.solver_opts(max_err=1e-5))
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        t, dt, st = ctx.run(mm_, float("inf"), t=t, dt=dt, max_attempts=steps, opts=mm.solver_opts(max_err=1e-5))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        return ncell * st["evals"] / wall, ctx.surrogate_stats()
+
+    plain, _ = run(None)
+    at_tol, st_tol = run(1e-4)
+    forced, st_forced = run(1e30)
+    ctx.set_surrogate(None)
+    ctx.close()
+    sur.close()
+    return {"value": forced, "unit": "Beff evals*cells/s", "qualifies": bool(max(errs) <= 1e-4),
+            "surrogate_rel_err_max": max(errs), "surrogate_rel_err_median": float(np.median(errs)),
+            "sno_eval_us": sno_us, "exact_field_eval_us": exact_us,
+            "value_at_tol_1e-4": at_tol, "fallbacks_at_tol_1e-4": st_tol["fallbacks"],
+            "plain_value_same_film": plain, "surrogate_steps_forced": st_forced["surrogate_steps"],
+            "workload": "256x256x1 film, 4 nm cells, Msat 8e5, Aex 1.3e-11, alpha 0.01; vortex texture; "
+                        "DP45 MaxErr 1e-5, surrogate at stages 2-6, exact last stage; errors on 24 held-out "
+                        "textures", "dtype": "bf16 weights, f32 arithmetic"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +326,9 @@ def main():
     ap.add_argument("--n", type=int, default=1024, help="film edge in cells")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble variant")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate variant")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="only the surrogate variant (one JSON line; for profiling)")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the batched-ensemble variant (one JSON line; for profiling)")
     ap.add_argument("--traffic", default=TRAFFIC_FILE,
@@ -285,6 +357,9 @@ def main():
         return
     if args.ensemble_only:
         print(json.dumps(ensemble_variant(max(4, args.steps // 10), max(2, args.warmup // 5))))
+        return
+    if args.surrogate_only:
+        print(json.dumps(surrogate_variant(max(10, args.steps // 4), max(2, args.warmup // 4))))
         return
     case = synth.vortex_film(seed=2, n=args.n)
     ncell = int(np.prod(case["grid"]))
@@ -344,6 +419,8 @@ def main():
     ctx.close()
     if not args.no_ensemble:
         out["variants"]["ensemble"] = ensemble_variant(max(4, args.steps // 10), max(2, args.warmup // 5))
+    if not args.no_surrogate:
+        out["variants"]["surrogate"] = surrogate_variant(max(10, args.steps // 4), max(2, args.warmup // 4))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     else:

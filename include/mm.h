@@ -344,7 +344,7 @@ void mm_batch_destroy(mm_batch *b);
  * weights: host FP32 array of MM_SNO_NWEIGHTS values in the order P[32][3],
  * p[32], then per layer R[16][16][32][32][re,im], W[32][32], b[32], then
  * Q[3][32], q[3]; stored on the device rounded to BF16 (nearest even), all
- * arithmetic FP32.  32 <= nx <= 512, 16 <= ny <= 4096, else MM_EUNSUPPORTED;
+ * arithmetic FP32.  32 <= nx <= 512, 16 <= ny <= 512, else MM_EUNSUPPORTED;
  * a wrong count gives MM_EINVAL.  Work is enqueued on hip_stream. */
 #define MM_SNO_NWEIGHTS 2101603
 typedef struct mm_sno mm_sno;

@@ -77,20 +77,26 @@ __global__ void __launch_bounds__(256) k_sno_dftx(const SnoArgs a, const float* 
 }
 
 // Hhat[c][j][kx] = sum_y H1[c][y][kx] exp(-2 pi i ky y / ny), ky = j - 8:
-// a workgroup per channel, thread (j, kx).
+// a workgroup per channel (its kept columns and the y twiddles staged in
+// LDS), thread (j, kx).
 __global__ void __launch_bounds__(256) k_sno_dfty(const SnoArgs a, const float2* __restrict__ H1,
                                                   float2* __restrict__ Hh) {
+    extern __shared__ float2 sy[];  // ny x 16 columns, then ny twiddles
     const int c = blockIdx.x;
-    const int j = threadIdx.x >> 4, kx = threadIdx.x & 15;
     const int ny = a.ny;
+    float2* tw = sy + ny * SNO_KX;
+    const float2* src = H1 + (long long)c * ny * SNO_KX;
+    for (int i = threadIdx.x; i < ny * SNO_KX; i += 256) sy[i] = src[i];
+    for (int i = threadIdx.x; i < ny; i += 256) tw[i] = a.twy[i];
+    __syncthreads();
+    const int j = threadIdx.x >> 4, kx = threadIdx.x & 15;
     const int ky = j - SNO_KY / 2;
     const int step = ky >= 0 ? ky : ky + ny;  // ky mod ny
     float2 acc = make_float2(0.f, 0.f);
     int idx = 0;
-    const float2* col = H1 + (long long)c * ny * SNO_KX + kx;
     for (int y = 0; y < ny; ++y) {
-        const float2 v = col[(long long)y * SNO_KX];
-        const float2 w = a.twy[idx];
+        const float2 v = sy[y * SNO_KX + kx];
+        const float2 w = tw[idx];
         acc.x += v.x * w.x - v.y * w.y;
         acc.y += v.x * w.y + v.y * w.x;
         idx += step;
@@ -213,6 +219,8 @@ hipError_t sno_twiddles(float2* tw, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
+size_t sno_dfty_lds(int ny);
+
 hipError_t sno_forward(const SnoArgs& a, const float* m, float* out, hipStream_t s) {
     const unsigned pix = (unsigned)((a.n + 255) / 256);
     hipLaunchKernelGGL(k_sno_lift, dim3(pix), dim3(256), 0, s, a, m, a.h0);
@@ -222,7 +230,7 @@ hipError_t sno_forward(const SnoArgs& a, const float* m, float* out, hipStream_t
     const size_t xlds = (size_t)16 * a.nx * sizeof(float) + (size_t)a.nx * sizeof(float2);
     for (int l = 0; l < SNO_LAYERS; ++l) {
         hipLaunchKernelGGL(k_sno_dftx, dim3(SNO_C * rows_per_c), dim3(256), xlds, s, a, h, a.H1);
-        hipLaunchKernelGGL(k_sno_dfty, dim3(SNO_C), dim3(256), 0, s, a, a.H1, a.Hh);
+        hipLaunchKernelGGL(k_sno_dfty, dim3(SNO_C), dim3(256), sno_dfty_lds(a.ny), s, a, a.H1, a.Hh);
         hipLaunchKernelGGL(k_sno_mix, dim3(SNO_KY * SNO_KX), dim3(SNO_C), 0, s, a, a.spec[l], a.Hh, a.Gh);
         const long long ninv = (long long)SNO_C * a.ny * SNO_KX;
         hipLaunchKernelGGL(k_sno_invy, dim3((unsigned)((ninv + 255) / 256)), dim3(256), 0, s, a, a.Gh, a.G1);
@@ -236,5 +244,11 @@ hipError_t sno_forward(const SnoArgs& a, const float* m, float* out, hipStream_t
 }
 
 size_t sno_dftx_lds(int nx) { return (size_t)16 * nx * sizeof(float) + (size_t)nx * sizeof(float2); }
+size_t sno_dfty_lds(int ny) { return (size_t)(SNO_KX + 1) * ny * sizeof(float2); }
+
+hipError_t configure_sno(int ny) {
+    return hipFuncSetAttribute((const void*)k_sno_dfty, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sno_dfty_lds(ny));
+}
 
 }  // namespace mm

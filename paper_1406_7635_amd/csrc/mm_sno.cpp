@@ -75,7 +75,7 @@ int mm_sno_create(mm_sno** out, int32_t nx, int32_t ny, const float* weights, in
     if (!out || !weights) return MM_EINVAL;
     *out = nullptr;
     if (nweights != SNO_NWEIGHTS || !isfinite(out_scale)) return MM_EINVAL;
-    if (nx < 2 * SNO_KX || ny < SNO_KY || nx > 512 || ny > 4096) return MM_EUNSUPPORTED;
+    if (nx < 2 * SNO_KX || ny < SNO_KY || nx > 512 || ny > 512) return MM_EUNSUPPORTED;
     mm_sno* s = new (std::nothrow) mm_sno();
     if (!s) return MM_ENOMEM;
     s->stream = (hipStream_t)hip_stream;
@@ -88,6 +88,7 @@ int mm_sno_create(mm_sno** out, int32_t nx, int32_t ny, const float* weights, in
     if (e == hipSuccess) e = hipMalloc((void**)&s->h, 2 * SNO_C * n * sizeof(float));
     const size_t line = (size_t)SNO_C * ny * SNO_KX, kept = (size_t)SNO_C * SNO_KY * SNO_KX;
     if (e == hipSuccess) e = hipMalloc((void**)&s->modes, (2 * line + 2 * kept) * sizeof(float2));
+    if (e == hipSuccess) e = configure_sno(ny);
     if (e == hipSuccess) e = sno_twiddles(s->tw, nx, s->stream);
     if (e == hipSuccess) e = sno_twiddles(s->tw + nx, ny, s->stream);
     int st = map_err(e);

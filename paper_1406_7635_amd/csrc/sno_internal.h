@@ -44,5 +44,7 @@ void sno_grid(const mm_sno* s, int* nx, int* ny);
 // the whole forward pass: m [3][n] -> out [3][n]
 hipError_t sno_forward(const SnoArgs& a, const float* m, float* out, hipStream_t s);
 size_t sno_dftx_lds(int nx);
+// raise the LDS limit of the y transform (ny <= 512 rows: 69 KB)
+hipError_t configure_sno(int ny);
 
 }  // namespace mm

@@ -3,12 +3,14 @@
 
     python -m paper_1406_7635_amd.sno_train --out weights.npy [--pairs N] [--steps K]
 
+(the committed data/sno_film256_bf16.npy came from --pairs 2048 --steps 4000)
+
 Training pairs: seeded film textures (synth.film_textures) and their B_demag
 from the library's exact FP32 convolution (mm_beff), in units of mu0 Msat.
 The model below is the network of include/mm.h written with torch's real
 FFTs so that autograd can train it; its forward pass is checked against the
 FP64 oracle of the same network by the CPU tests.  The weights are saved as
-the flat FP32 array of include/mm.h's order, rounded to BF16 values.
+the BF16 bit patterns (uint16) of the flat array in include/mm.h's order.
 """
 import argparse
 import math
@@ -20,6 +22,20 @@ import numpy as np
 
 C, KX, KY, NLAYER = 32, 16, 16, 4
 MU0 = 4e-7 * math.pi
+# weights trained by this script for the 256 x 256 x 1 film of 4 nm cells
+# (Msat 8e5 A/m, Aex 1.3e-11 J/m): 2048 pairs, 4000 steps, seed 5
+TRAINED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "sno_film256_bf16.npy")
+
+
+def save_weights(path, w):
+    """The flat weights as their BF16 bit patterns (uint16)."""
+    b = bf16_values(w).view(np.uint32)
+    np.save(path, (b >> 16).astype(np.uint16))
+
+
+def load_weights(path=TRAINED):
+    """Flat FP32 weights from a file written by save_weights."""
+    return (np.load(path).astype(np.uint32) << 16).view(np.float32)
 
 
 def make_model(torch):
@@ -144,7 +160,7 @@ def main():
     a = ap.parse_args()
     w = train(a.pairs, a.steps, seed=a.seed, log=lambda s: print(s, flush=True))
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
-    np.save(a.out, w.astype(np.float32))
+    save_weights(a.out, w)
     print("saved", a.out, w.size, flush=True)
     return 0
 
