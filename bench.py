@@ -191,8 +191,9 @@ def ensemble_attempt_bytes(members):
         if pz == 1:
             col = 2 * spec + 4 * 4 * kx * (py // 2 + 1)
         elif pz in (4, 8) and py * pz <= 4096:
-            # thin grid: one pass per kx column (y FFT, z DFT with K^, inverse y FFT)
-            col = 2 * spec + 4 * 6 * kx * (py // 2 + 1) * (pz // 2 + 1)
+            # thin grid: one pass per kx column (y FFT, z convolution with the kernel
+            # in z space: 4 + 6 (pz/2 - 1) floats per (kx, ky_h), inverse y FFT)
+            col = 2 * spec + 4 * (4 + 6 * (pz // 2 - 1)) * kx * (py // 2 + 1)
         else:
             yf = 3 * 8 * kx * nz * (ny + py)
             zc = 2 * 3 * 8 * kx * py * nz + 4 * 6 * kx * (py // 2 + 1) * (pz // 2 + 1)

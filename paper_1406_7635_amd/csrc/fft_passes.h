@@ -561,18 +561,18 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
 // ---------------------------------------------------------------------------
 // 3D convolution of a thin grid (a few layers) in one pass per kx column:
 // forward FFT along y of the three components of every z plane (the nz
-// planes' sequences side by side in LDS), then for each ky the transform along
-// the short z axis as a direct DFT of its nz non-zero planes, the K^ product
-// at every kz (K^ octant with the mirror signs of both folded axes) and the
-// inverse DFT back to the nz planes, then the inverse FFT along y.  The
-// spectrum keeps ny rows per column (ycount = ny); the padded y and z
-// lengths live only on chip.
+// planes' sequences side by side in LDS), then for each ky the convolution
+// along the short z axis done directly in real space, B(z') = sum_z
+// G(z' - z) M(z), and the inverse FFT along y.  G(d) = sum_kz K^(kz)
+// exp(+2 pi i kz d / PZ) is the kernel spectrum transformed back along z
+// (zkernel_table below): real and even in d for xx, yy, zz, xy; imaginary and
+// odd in d for xz, yz.  The spectrum keeps ny rows per column (ycount = ny);
+// the padded y and z lengths live only on chip.
 //
 // Threads: for each of T kx columns, 3 PZ/2 thread groups (plane z, component
 // c; planes z >= nz idle) of TPF threads.  Serves PZ in {4, 8} (nz from 2 to
 // 4) and PY PZ <= 4096: the workgroup is 768 threads and its exchange LDS
-// 55 KB for every such pair.  (More layers keep the three-pass path: the z
-// step's registers would not fit.)
+// 55 KB for every such pair.  (More layers keep the three-pass path.)
 template <int PY, int PZ>
 struct YzCfg {
     static constexpr int TPF = Cfg<PY>::TPF, PPT = Cfg<PY>::PPT;
@@ -594,13 +594,18 @@ constexpr size_t yz_lds() {
     return (size_t)YzCfg<PY, PZ>::T * YzCfg<PY, PZ>::G * YzCfg<PY, PZ>::SEQ * sizeof(cf);
 }
 
+// floats of the z-space kernel per (kx, ky_h): d = 0: xx, yy, zz, xy; each
+// d = 1 .. PZ/2 - 1: xx, yy, zz, xy, Im xz, Im yz
+constexpr int zkernel_len(int pz) { return 4 + 6 * (pz / 2 - 1); }
+
 // a: spec, col_stride (between kx columns), outer_stride (between z planes),
-// ncol (= kx count), nouter (= nz), n_in (= ny), khat, kyh, kzh, pa (= py).
+// ncol (= kx count), nouter (= nz), n_in (= ny), khat (the z-space kernel
+// [kx][ky_h][zkernel_len(PZ)]), kyh (= PY/2 + 1).
 template <int PY, int PZ>
 __device__ inline void yz_body(const ColArgs& a, int blk, cf* lds, int tid) {
     using C = YzCfg<PY, PZ>;
     constexpr int TPF = C::TPF, PPT = C::PPT, NZM = C::NZM, G = C::G, TK = C::TK, T = C::T, SEQ = C::SEQ;
-    constexpr int MH = PPT / 2;
+    constexpr int MH = PPT / 2, NG = zkernel_len(PZ);
     static_assert(use_yz<PY, PZ>() && C::NTH == 768, "thin-grid convolution shape");
     if (a.check_done && a.st->done) return;
     const int kc = tid / TK, r = tid - kc * TK;
@@ -625,62 +630,49 @@ __device__ inline void yz_body(const ColArgs& a, int blk, cf* lds, int tid) {
     for (int m = 0; m < PPT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
     __syncthreads();
 
-    // along z, one ky at a time: direct DFT of the nz planes, K^ product per
-    // kz, inverse DFT to the nz planes
+    // along z, one ky at a time: B(z') = sum_z G(z' - z) M(z)
     if (kx < a.ncol) {
-        cf wz[PZ];  // exp(-2 pi i j / PZ)
-        const int sh = a.twshift - ilog2(PZ);
-#pragma unroll
-        for (int j = 0; j < PZ; ++j) wz[j] = a.tw[j << sh];
         cf* cb = lds + kc * G * SEQ;
         for (int ky = r; ky < PY; ky += TK) {
             const bool fa = 2 * ky > PY;
-            const int kyh = fa ? PY - ky : ky;
-            const float* K0 = a.khat + ((long long)kx * a.kyh + kyh) * a.kzh * 6;
-            cf X[3][NZM], Y[3][NZM];
+            const float sy = fa ? -1.f : 1.f;  // xy and yz are odd in y
+            const float* Gr = a.khat + ((long long)kx * a.kyh + (fa ? PY - ky : ky)) * NG;
+            float gk[NG];
 #pragma unroll
-            for (int zz = 0; zz < NZM; ++zz)
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    X[cc][zz] = zz < nz ? cb[(3 * zz + cc) * SEQ + lds_pad(ky)] : mkc(0.f, 0.f);
-                    Y[cc][zz] = mkc(0.f, 0.f);
-                }
-#pragma unroll
-            for (int kz = 0; kz < PZ; ++kz) {
-                cf M[3];
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    M[cc] = X[cc][0];
-#pragma unroll
-                    for (int zz = 1; zz < NZM; ++zz) M[cc] = M[cc] + cmul(X[cc][zz], wz[(kz * zz) % PZ]);
-                }
-                const bool fq = 2 * kz > PZ;
-                const float* K = K0 + (fq ? PZ - kz : kz) * 6;
-                float kxy = K[3], kxz = K[4], kyz = K[5];
-                if (fq) {  // xz and yz are odd in z
-                    kxz = -kxz;
-                    kyz = -kyz;
-                }
-                if (fa) {  // xy and yz are odd in y
-                    kxy = -kxy;
-                    kyz = -kyz;
-                }
-                const cf B0 = K[0] * M[0] + kxy * M[1] + kxz * M[2];
-                const cf B1 = kxy * M[0] + K[1] * M[1] + kyz * M[2];
-                const cf B2 = kxz * M[0] + kyz * M[1] + K[2] * M[2];
-#pragma unroll
-                for (int zz = 0; zz < NZM; ++zz) {
-                    const cf w = cconj(wz[(kz * zz) % PZ]);
-                    Y[0][zz] = Y[0][zz] + cmul(B0, w);
-                    Y[1][zz] = Y[1][zz] + cmul(B1, w);
-                    Y[2][zz] = Y[2][zz] + cmul(B2, w);
-                }
-            }
+            for (int i = 0; i < NG; ++i) gk[i] = Gr[i];
+            cf X[3][NZM];
 #pragma unroll
             for (int zz = 0; zz < NZM; ++zz)
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc)
-                    if (zz < nz) cb[(3 * zz + cc) * SEQ + lds_pad(ky)] = Y[cc][zz];
+                    X[cc][zz] = zz < nz ? cb[(3 * zz + cc) * SEQ + lds_pad(ky)] : mkc(0.f, 0.f);
+#pragma unroll
+            for (int zo = 0; zo < NZM; ++zo) {
+                cf B0 = mkc(0.f, 0.f), B1 = mkc(0.f, 0.f), B2 = mkc(0.f, 0.f);
+#pragma unroll
+                for (int zi = 0; zi < NZM; ++zi) {
+                    const int d = zo - zi, ad = d < 0 ? -d : d;
+                    const float* e = gk + (ad == 0 ? 0 : 4 + 6 * (ad - 1));
+                    const float kxx = e[0], kyy = e[1], kzz = e[2], kxy = sy * e[3];
+                    const cf x0 = X[0][zi], x1 = X[1][zi], x2 = X[2][zi];
+                    B0 = B0 + kxx * x0 + kxy * x1;
+                    B1 = B1 + kxy * x0 + kyy * x1;
+                    B2 = B2 + kzz * x2;
+                    if (ad > 0) {
+                        // i g: i (a + i b) = (-b, a)
+                        const float sd = d > 0 ? 1.f : -1.f;
+                        const float gxz = sd * e[4], gyz = sd * sy * e[5];
+                        B0 = B0 + gxz * mkc(-x2.y, x2.x);
+                        B1 = B1 + gyz * mkc(-x2.y, x2.x);
+                        B2 = B2 + gxz * mkc(-x0.y, x0.x) + gyz * mkc(-x1.y, x1.x);
+                    }
+                }
+                if (zo < nz) {
+                    cb[(3 * zo) * SEQ + lds_pad(ky)] = B0;
+                    cb[(3 * zo + 1) * SEQ + lds_pad(ky)] = B1;
+                    cb[(3 * zo + 2) * SEQ + lds_pad(ky)] = B2;
+                }
+            }
         }
     }
     __syncthreads();

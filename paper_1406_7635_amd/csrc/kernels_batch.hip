@@ -125,7 +125,8 @@ __device__ inline ColArgs member_col(const ColArgs& b, const BMember& mb, int i,
     a.pa = mb.py;
     a.pack_col = 0;
     if (kind == BC_YZ) {
-        // thin 3D member: y FFT, z DFT with K^, inverse y FFT per kx column
+        // thin 3D member: y FFT, z convolution with the z-space kernel, inverse y FFT per kx column
+        a.khat = b.zker + mb.zker_off;
         a.pos_stride = 3;
         a.col_stride = mb.colstride;
         a.ncol = mb.kx;

@@ -188,6 +188,39 @@ static hipError_t yz_dispatch(int py, int pz, const F& f) {
     }
 }
 
+__global__ void k_zkernel(const float* __restrict__ khat, float* __restrict__ zk, long long rows, int pz) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    const int kzh = pz / 2 + 1;
+    const float* K = khat + i * kzh * 6;
+    float* G = zk + i * zkernel_len(pz);
+    for (int d = 0; d < pz / 2; ++d) {
+        double e[4] = {0.0, 0.0, 0.0, 0.0}, o[2] = {0.0, 0.0};
+        for (int kz = 0; kz < pz; ++kz) {
+            const bool fq = 2 * kz > pz;
+            const int kh = fq ? pz - kz : kz;
+            double sn, cs;
+            sincospi(2.0 * (double)(kz * d) / (double)pz, &sn, &cs);
+            for (int q = 0; q < 4; ++q) e[q] += (double)K[kh * 6 + q] * cs;
+            // xz and yz are odd in z
+            for (int q = 0; q < 2; ++q) o[q] += (fq ? -1.0 : 1.0) * (double)K[kh * 6 + 4 + q] * sn;
+        }
+        float* out = G + (d == 0 ? 0 : 4 + 6 * (d - 1));
+        for (int q = 0; q < 4; ++q) out[q] = (float)e[q];
+        if (d > 0) {
+            out[4] = (float)o[0];
+            out[5] = (float)o[1];
+        }
+    }
+}
+
+int zkernel_floats(int pz) { return zkernel_len(pz); }
+
+hipError_t launch_zkernel(const float* khat, float* zker, long long rows, int pz, hipStream_t s) {
+    hipLaunchKernelGGL(k_zkernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, khat, zker, rows, pz);
+    return hipGetLastError();
+}
+
 struct YzNop {
     template <int PY, int PZ>
     hipError_t operator()() const {

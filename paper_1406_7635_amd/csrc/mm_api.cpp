@@ -51,6 +51,7 @@ struct mm_ctx {
     float* ms = nullptr;   // stage state
     float* ms2 = nullptr;  // second stage-state buffer of the fused passes
     void* dft_tab = nullptr;  // split DFT matrices of the matrix-core y convolution
+    float* zker = nullptr;    // thin 3D grids: the kernel transformed back along z
     int conv_prec = MM_PREC_FP32;
     DevState* st = nullptr;
     double* partials = nullptr;
@@ -79,8 +80,8 @@ hipError_t dalloc(mm_ctx* c, void** p, size_t bytes) {
 }
 
 void free_all(mm_ctx* c) {
-    void* ptrs[] = {c->region, c->params64, c->lut, c->ptab, c->tw,       c->spec,    c->khat,
-                    c->kbuf,   c->ms,       c->ms2, c->st,   c->partials, c->dft_tab, c->bsur, c->bexact};
+    void* ptrs[] = {c->region, c->params64, c->lut,      c->ptab,    c->tw,   c->spec,   c->khat, c->kbuf,
+                    c->ms,     c->ms2,      c->st,       c->partials, c->dft_tab, c->bsur, c->bexact, c->zker};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hst) (void)hipHostFree(c->hst);
@@ -169,6 +170,7 @@ int run_cols(mm_ctx* c, bool check_done) {
         ca.nouter = c->nz;
         ca.n_in = c->ny;
         ca.n_out = c->ny;
+        ca.khat = c->zker;
         MM_TRY(launch_yz(c->py, c->pz, ca, s, t.e1, t.e2));
     } else if (c->pz > 1) {
         // y transforms of every (z, kx) column, in place (ny rows -> py rows)
@@ -516,6 +518,7 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
     A((void**)&c->ms, (size_t)3 * c->ncell * sizeof(float));
     A((void**)&c->ms2, (size_t)3 * c->ncell * sizeof(float));
     A((void**)&c->dft_tab, (size_t)2 * DFT_TABLE_BYTES);
+    if (c->yz) A((void**)&c->zker, (size_t)c->kx * (c->py / 2 + 1) * zkernel_floats(c->pz) * sizeof(float));
     A((void**)&c->st, sizeof(DevState));
     A((void**)&c->partials, (size_t)maxblk * 4 * sizeof(double));
     if (st == MM_OK && hipHostMalloc((void**)&c->hst, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
@@ -553,6 +556,7 @@ int mm_demag_kernel_init(mm_ctx* c) {
     if (e == hipSuccess)
         e = demag_kernel_spectrum(c->nx, c->ny, c->nz, c->px, c->py, c->pz, oct, work, c->khat, c->ncomp,
                                   c->kx, c->stream);
+    if (e == hipSuccess && c->yz) e = launch_zkernel(c->khat, c->zker, (long long)c->kx * (c->py / 2 + 1), c->pz, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (oct) (void)hipFree(oct);
     if (work) (void)hipFree(work);

@@ -23,7 +23,7 @@ struct mm_batch {
     int n = 0;
     std::vector<BMember> hmem;
     std::vector<mm_grid> hgrid;
-    long long ncell = 0, spec_elems = 0, khat_elems = 0;
+    long long ncell = 0, spec_elems = 0, khat_elems = 0, zker_elems = 0;
     bool has2d = false;
     int pt = 1, twshift = 0;
     // device buffers
@@ -38,6 +38,7 @@ struct mm_batch {
     cf* tw = nullptr;
     cf* spec = nullptr;
     float* khat = nullptr;
+    float* zker = nullptr;  // thin 3D members: kernels transformed back along z
     float* kbuf = nullptr;
     float* ms = nullptr;
     float* ms2 = nullptr;
@@ -64,8 +65,8 @@ struct mm_batch {
 namespace {
 
 void free_batch(mm_batch* b) {
-    void* ptrs[] = {b->mem, b->region, b->params64, b->lut, b->ptab, b->tw, b->spec,
-                    b->khat, b->kbuf, b->ms, b->ms2, b->st, b->active};
+    void* ptrs[] = {b->mem, b->region, b->params64, b->lut, b->ptab, b->tw,     b->spec,
+                    b->khat, b->zker, b->kbuf,  b->ms,       b->ms2, b->st, b->active};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (unsigned int* p : b->items)
@@ -129,6 +130,7 @@ ColArgs base_col(const mm_batch* b, bool check_done) {
     memset(&c, 0, sizeof(c));
     c.spec = b->spec;
     c.khat = b->khat;
+    c.zker = b->zker;
     c.tw = b->tw;
     c.twshift = b->twshift;
     c.st = b->st;
@@ -306,6 +308,7 @@ int mm_batch_create(mm_batch** out, int32_t n, const mm_grid* grids, const mm_pa
         m.cell_off = b->ncell;
         m.spec_off = b->spec_elems;
         m.khat_off = b->khat_elems;
+        m.zker_off = b->zker_elems;
         // rows per spectrum column: py when the y transforms run in place, else ny
         m.colstride = 3LL * (m.pz > 1 && !yz_supported(m.py, m.pz) ? m.py : m.ny);
         m.zstride = (long long)m.kx * m.colstride;
@@ -317,6 +320,7 @@ int mm_batch_create(mm_batch** out, int32_t n, const mm_grid* grids, const mm_pa
         b->ncell += nc;
         b->spec_elems += m.zstride * m.nz;
         b->khat_elems += (long long)m.kx * (m.py / 2 + 1) * (m.pz / 2 + 1) * (m.pz > 1 ? 6 : 4);
+        if (m.pz > 1 && yz_supported(m.py, m.pz)) b->zker_elems += (long long)m.kx * (m.py / 2 + 1) * zkernel_floats(m.pz);
         if (m.pz == 1) b->has2d = true;
         if (m.px > b->pt) b->pt = m.px;
         if (m.py > b->pt) b->pt = m.py;
@@ -356,6 +360,7 @@ int mm_batch_create(mm_batch** out, int32_t n, const mm_grid* grids, const mm_pa
     A((void**)&b->tw, (size_t)b->pt * sizeof(cf));
     A((void**)&b->spec, (size_t)b->spec_elems * sizeof(cf));
     A((void**)&b->khat, (size_t)b->khat_elems * sizeof(float));
+    A((void**)&b->zker, (size_t)b->zker_elems * sizeof(float));
     A((void**)&b->kbuf, (size_t)MAXK * 3 * nc * sizeof(float));
     A((void**)&b->ms, 3 * nc * sizeof(float));
     A((void**)&b->ms2, 3 * nc * sizeof(float));
@@ -419,6 +424,9 @@ int mm_batch_demag_kernel_init(mm_batch* b) {
         if (e == hipSuccess)
             e = demag_kernel_spectrum(m.nx, m.ny, m.nz, m.px, m.py, m.pz, oct, work, b->khat + m.khat_off,
                                       m.pz > 1 ? 6 : 4, m.kx, b->stream);
+        if (e == hipSuccess && m.pz > 1 && yz_supported(m.py, m.pz))
+            e = launch_zkernel(b->khat + m.khat_off, b->zker + m.zker_off, (long long)m.kx * (m.py / 2 + 1), m.pz,
+                               b->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (oct) (void)hipFree(oct);

@@ -108,6 +108,7 @@ struct ColArgs {
     const DevState* st;
     int check_done;
     const void* dft_tab;          // matrix-core variant: split DFT matrices of its precision
+    const float* zker;            // ensembles: base of the members' z-space kernels (thin grids)
 };
 
 // ---- launchers (kernels_fft.hip) -------------------------------------------
@@ -139,6 +140,10 @@ hipError_t launch_xrow(int px, const FieldArgs& ai, const FieldArgs& af, float a
 // (py, pz) with pz in {4, 8}, py >= 16 and py pz <= 4096.
 bool yz_supported(int py, int pz);
 hipError_t launch_yz(int py, int pz, const ColArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// The thin-grid pass's kernel in z space, G(d) = sum_kz K^(kz) exp(+2 pi i kz d/pz),
+// from the K^ octant [kx][ky_h][kz_h][6] (rows = kx (py/2 + 1)); FP64 sums.
+int zkernel_floats(int pz);
+hipError_t launch_zkernel(const float* khat, float* zker, long long rows, int pz, hipStream_t s);
 int xinv_blocks(int px, int nrows);
 // Raise the dynamic-LDS limit of every pass a grid of padded size px x py x pz
 // launches (once per context, on the current device).
@@ -160,6 +165,7 @@ struct BMember {
     long long cell_off;
     long long spec_off;
     long long khat_off;
+    long long zker_off;           // z-space kernel floats before this member's (thin 3D members)
     long long colstride, zstride;
     float idx2, idy2, idz2, cellvol;
 };
