@@ -25,6 +25,8 @@ GRIDS = [
     ((1, 1, 1), (4e-9, 4e-9, 2e-9)),
     ((100, 70, 1), (3e-9, 3e-9, 3e-9)),
     ((40, 24, 3), (2e-9, 2e-9, 2e-9)),
+    ((64, 48, 2), (2.5e-9, 2e-9, 3e-9)),
+    ((200, 33, 2), (2e-9, 3e-9, 2e-9)),
 ]
 
 

@@ -11,6 +11,8 @@ benchmark times (same padded sizes, same kernel instances).
   (exchange over the 256-region pair table, anisotropy, Zeeman) are checked
   over every cell with the magnetostatic term off; and a uniformly magnetised
   box must reproduce the exact box-averaged demagnetising factors.
+* 512 x 256 x 2 film (the one-pass thin-grid convolution): B_demag, B_eff and
+  the torque against the oracle over every cell.
 """
 import numpy as np
 import pytest
@@ -141,4 +143,22 @@ def test_grains_uniform_box_factors(gpu):
     mv = to_np(m)[:, 0, 0, 0]
     ref = -MU0 * 8e5 * np.array([nxx, nyy, nzz]) * mv
     assert np.max(np.abs(mean - ref)) < 1e-5 * MU0 * 8e5
+    ctx.close()
+
+
+def test_thin_film_512x256x2_fields_full(gpu):
+    """Two-layer film at an ensemble member's largest size and beyond: the
+    one-pass y/z convolution (kernel in z space) against the FP64 oracle over
+    every cell."""
+    case = synth.random_problem((512, 256, 2), (3e-9, 3e-9, 2e-9), seed=8, nregions=4, vacuum=True)
+    log("thin film 512x256x2: full-grid B_eff / torque parity")
+    ctx, prob, m = make_pair(case)
+    prob.workers = -1
+    b, bd = ctx.beff(m, want_demag=True)
+    m64 = case["m0"].astype(np.float64)
+    t = prob.terms(m64)
+    assert rel_inf(to_np(bd), t["demag"]) < 1e-5
+    ref_b = sum(t[k] for k in ("demag", "exch", "anis1", "anis2", "zeeman")) * prob.magnetic
+    assert rel_inf(to_np(b), ref_b) < 1e-5
+    assert rel_inf(to_np(ctx.torque(m)), prob.torque(m64)) < 1e-5
     ctx.close()
