@@ -170,6 +170,27 @@ def mfma_variants(ctx, m, opts, ncell, steps):
     return res
 
 
+def copy_bandwidth(reps=20):
+    """Achieved HBM bandwidth of a plain 256 MiB device-to-device copy (read +
+    write bytes / time), the practical ceiling the roofline fraction is also
+    stated against."""
+    import torch
+
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbs
+
+
 def ensemble_attempt_bytes(members):
     """Algorithmic HBM bytes of one Dormand-Prince attempt of every member of
     an ensemble (the pass model above, per member: x-forward, five fused
@@ -395,6 +416,7 @@ def main():
         if n:
             per[name] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms": ms}
     dominant = max(per, key=lambda k: per[k]["total_ms"])
+    copy_gbs = copy_bandwidth()
     bytes_per_launch = {"x_forward": xfwd_pass_bytes(ctx, 1), "column_conv": column_pass_bytes(ctx),
                         "x_inverse": xinv_pass_bytes(ctx, 5), "x_row": xrow_pass_bytes(ctx, DP45_XROW_K)}
     for k in per:
@@ -413,7 +435,8 @@ def main():
                    "evals_per_step": 6, "gpu_event_ms": gpu_ms,
                    "kernel_timing": "second pass of %d attempts, dispatch-recorded HIP events" % args.steps},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant},
+                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
+                     "copy_GBs": copy_gbs, "frac_of_copy": ach / copy_gbs},
         "kernels": per,
     }
     out["variants"] = mfma_variants(ctx, m, opts, ncell, args.steps)
