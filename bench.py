@@ -271,6 +271,36 @@ def ensemble_variant(steps, warmup, n=512):
             "dtype": "f32"}
 
 
+def grains_variant(steps, warmup):
+    """The 3D workload: 256 x 256 x 64 cells of 3 nm, 256 Voronoi grains
+    (random m, the worst-case spectrum), plain FP32 Dormand-Prince: throughput
+    and the three-pass 3D path's algorithmic bytes."""
+    import torch
+
+    from paper_1406_7635_amd import mm, synth
+
+    case = synth.grains(seed=3)
+    ncell = int(np.prod(case["grid"]))
+    ctx = mm.Context(case["grid"], case["cell"], case["region"], case["params"])
+    m = torch.from_numpy(case["m0"]).cuda()
+    opts = mm.solver_opts(max_err=1e-5)
+    t, dt, _ = ctx.run(m, float("inf"), dt=1e-14, max_attempts=warmup, opts=opts)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t, dt, st = ctx.run(m, float("inf"), t=t, dt=dt, max_attempts=steps, opts=opts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ctx.close()
+    b_att = ensemble_attempt_bytes([case])
+    gbs = b_att * steps / wall / 1e9
+    return {"value": ncell * st["evals"] / wall, "unit": "Beff evals*cells/s", "ms_per_attempt": 1e3 * wall / steps,
+            "attempts": steps, "accepted": st["steps"], "alg_bytes_per_attempt": b_att, "alg_GBs": gbs,
+            "alg_frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "workload": "256x256x64 grains, 3 nm cells, 256 Voronoi regions (Msat U(6e5,1e6), Ku1 U(0,5e5), "
+                        "S 0.9), random m; DP45 MaxErr 1e-5; plain FP32 (y-forward, z convolution, y-inverse)",
+            "dtype": "f32"}
+
+
 def surrogate_variant(steps, warmup):
     """The surrogate workload: 256 x 256 x 1 film of 4 nm cells (Msat 8e5,
     Aex 1.3e-11, alpha 0.01), trained weights.  Reports the surrogate's
@@ -349,6 +379,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble variant")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate variant")
+    ap.add_argument("--no-grains", action="store_true", help="skip the 3D grain-workload variant")
+    ap.add_argument("--grains-only", action="store_true",
+                    help="only the 3D grain-workload variant (one JSON line; for profiling)")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the surrogate variant (one JSON line; for profiling)")
     ap.add_argument("--ensemble-only", action="store_true",
@@ -359,8 +392,7 @@ def main():
                     help="only run a plain 256 MiB device copy 10 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the work would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -379,6 +411,9 @@ def main():
         return
     if args.ensemble_only:
         print(json.dumps(ensemble_variant(max(4, args.steps // 10), max(2, args.warmup // 5))))
+        return
+    if args.grains_only:
+        print(json.dumps(grains_variant(max(5, args.steps // 20), max(2, args.warmup // 10))))
         return
     if args.surrogate_only:
         print(json.dumps(surrogate_variant(max(10, args.steps // 4), max(2, args.warmup // 4))))
@@ -445,6 +480,8 @@ def main():
         out["variants"]["ensemble"] = ensemble_variant(max(4, args.steps // 10), max(2, args.warmup // 5))
     if not args.no_surrogate:
         out["variants"]["surrogate"] = surrogate_variant(max(10, args.steps // 4), max(2, args.warmup // 4))
+    if not args.no_grains:
+        out["variants"]["grains"] = grains_variant(max(5, args.steps // 20), max(2, args.warmup // 10))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     else:

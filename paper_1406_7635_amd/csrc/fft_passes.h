@@ -4,9 +4,11 @@
 // convolution theorem on a grid zero-padded to px x py x pz.
 //
 // Spectrum layout (complex64): element (z, kx, y, c) at
-//   z * zstride + kx * colstride + y * 3 + c,  colstride = 3 * ycount,
-// ycount = py in 3D (the y transforms run in place), ny in 2D.  Every column
-// along y is contiguous, so the column passes read and write whole columns.
+//   z * zstride + kx * colstride + y * 3 + c,  zstride = 3 * ycount,
+//   colstride = nz * zstride (kx-major: the planes of one kx are adjacent),
+// ycount = py in 3D grids whose y transforms run in place, else ny.  Every
+// column along y is contiguous, so the column passes read and write whole
+// columns.
 //
 // The three real components of two x-rows a, b travel as three complex
 // "slots": slot 0 = Mx_a + i My_a, slot 1 = Mx_b + i My_b, slot 2 = Mz_a + i Mz_b.
@@ -380,10 +382,19 @@ __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds
 // CFAST the column index varies fastest over the lanes (strided columns, so
 // neighbouring lanes read neighbouring columns), else t does (contiguous
 // columns).
+// LDS elements per sequence of the column pass.  With CFAST the lanes of a
+// wave walk different sequences at the same position, so the sequence stride
+// is made odd: consecutive sequences then start in different LDS banks (an
+// even stride such as 144 would put every other lane on the same banks).
+template <int P, bool CFAST>
+constexpr int col_seq() {
+    return CFAST ? (seq_len(P) | 1) : seq_len(P);
+}
+
 template <int P, int MODE, int NC, bool CFAST>
 __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
     constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, T = ColCfg<P>::T;
-    constexpr int SEQ = seq_len(P);
+    constexpr int SEQ = col_seq<P, CFAST>();
     if (a.check_done && a.st->done) return;
     int ci, s, t;
     if (CFAST) {
@@ -444,6 +455,30 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
             if (i < NIT - 1 || e < TOT) lk[e] = kt[i];
         }
     }
+    // 3D z convolution: the K^ blocks of the tile's (kx, ky) columns (all kz,
+    // 6 components, contiguous per column) go to LDS the same way
+    float* lk6 = reinterpret_cast<float*>(lds + T * 3 * SEQ);
+    if constexpr (MODE == COL_CONV && NC == 6) {
+        constexpr int BL = KHP * 3;  // float2 per column block
+        constexpr int TOT = T * BL, NTH = ColCfg<P>::NTH, NIT = (TOT + NTH - 1) / NTH;
+        const int c0 = (blk - o * ntile) * T;
+        float2 kt[NIT];
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int e = tid + NTH * i;
+            const int ce = e / BL, r = e - ce * BL;
+            const int cy = c0 + ce;
+            const bool in = (i < NIT - 1 || e < TOT) && cy < a.ncol;
+            const int kyh = 2 * cy > a.pa ? a.pa - cy : cy;
+            const float2* src = reinterpret_cast<const float2*>(a.khat + ((long long)o * a.kyh + kyh) * (KHP * 6));
+            kt[i] = in ? src[r] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int e = tid + NTH * i;
+            if (i < NIT - 1 || e < TOT) reinterpret_cast<float2*>(lk6)[e] = kt[i];
+        }
+    }
     RegFft<P, TPF, 1, MODE == COL_INV, HIN>::run(v, buf, a.tw, a.twshift, t);
 
     if (MODE == COL_CONV) {
@@ -486,6 +521,14 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
                     k1 = k4.y;
                     k2 = k4.z;
                     kxy = k4.w;
+                } else if (NC == 6) {
+                    const float* K = lk6 + (ci * KHP + qh) * 6;
+                    k0 = K[0];
+                    k1 = K[1];
+                    k2 = K[2];
+                    kxy = K[3];
+                    kxz = K[4];
+                    kyz = K[5];
                 } else {
                     const float* K = a.khat + (((long long)kxx * a.kyh + kyh) * a.kzh + qh) * NC;
                     k0 = K[0];
@@ -881,9 +924,11 @@ template <int P>
 constexpr size_t x_lds() {
     return (size_t)XCfg<P>::GI * XCfg<P>::GL * sizeof(cf) + NREG * sizeof(RegionLut);
 }
-template <int P, int MODE, int NC>
+template <int P, int MODE, int NC, bool CFAST = false>
 constexpr size_t col_lds() {
-    return (size_t)ColCfg<P>::T * 3 * seq_len(P) * sizeof(cf) + (MODE == COL_CONV && NC == 4 ? khat_lds<P>() : 0);
+    return (size_t)ColCfg<P>::T * 3 * col_seq<P, CFAST>() * sizeof(cf) +
+           (MODE == COL_CONV && NC == 4 ? khat_lds<P>() : 0) +
+           (MODE == COL_CONV && NC == 6 ? (size_t)ColCfg<P>::T * (P / 2 + 1) * 6 * sizeof(float) : 0);
 }
 
 }  // namespace mm

@@ -144,12 +144,13 @@ __device__ inline ColArgs member_col(const ColArgs& b, const BMember& mb, int i,
         a.n_in = mb.nz;
         a.n_out = mb.nz;
     } else if (kind == BC_YFWD || kind == BC_YINV) {
-        // y transforms of every (z, kx) column, in place (ny rows <-> py rows)
+        // y transforms of every (kx, z) column, in place (ny rows <-> py rows);
+        // tiles of adjacent planes of one kx
         a.pos_stride = 3;
-        a.col_stride = mb.colstride;
-        a.ncol = mb.kx;
-        a.outer_stride = mb.zstride;
-        a.nouter = mb.nz;
+        a.col_stride = mb.zstride;
+        a.ncol = mb.nz;
+        a.outer_stride = mb.colstride;
+        a.nouter = mb.kx;
         a.n_in = kind == BC_YFWD ? mb.ny : mb.py;
         a.n_out = kind == BC_YFWD ? mb.py : mb.ny;
     } else {
@@ -447,11 +448,11 @@ PassShape pass_shape(int pass) {
         case BP_Y:
             return {(const void*)k_bcoly<BC_YFWD>, BX_NTH, BY_LDS};
         case BP_Z4:
-            return {(const void*)k_bzconv<4>, BX_NTH, col_lds<4, COL_CONV, 6>()};
+            return {(const void*)k_bzconv<4>, BX_NTH, col_lds<4, COL_CONV, 6, true>()};
         case BP_Z8:
-            return {(const void*)k_bzconv<8>, BX_NTH, col_lds<8, COL_CONV, 6>()};
+            return {(const void*)k_bzconv<8>, BX_NTH, col_lds<8, COL_CONV, 6, true>()};
         case BP_Z16:
-            return {(const void*)k_bzconv<16>, BX_NTH, col_lds<16, COL_CONV, 6>()};
+            return {(const void*)k_bzconv<16>, BX_NTH, col_lds<16, COL_CONV, 6, true>()};
         case BP_YZ4:
             return {(const void*)k_byz<4>, BX_NTH, yz_lds<64, 4>()};
         case BP_YZ8:
@@ -480,7 +481,7 @@ int batch_tiles(int pass, const BMember& m) {
         case BP_C3:
             return m.pz == 1 ? cdiv(m.px / 2, col3_t(m.py)) : 0;
         case BP_Y:
-            return m.pz > 1 && !yz_supported(m.py, m.pz) ? cdiv(m.kx, col_t(m.py)) * m.nz : 0;
+            return m.pz > 1 && !yz_supported(m.py, m.pz) ? cdiv(m.nz, col_t(m.py)) * m.kx : 0;
         case BP_Z4:
         case BP_Z8:
         case BP_Z16: {

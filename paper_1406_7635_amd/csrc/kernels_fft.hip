@@ -120,7 +120,7 @@ static hipError_t xrow_p(const FieldArgs& ai, const FieldArgs& af, float a_last,
 
 template <int P, int MODE, int NC, bool CFAST>
 static hipError_t col_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const size_t lds = col_lds<P, MODE, NC>();
+    const size_t lds = col_lds<P, MODE, NC, CFAST>();
     const long long nb = (long long)((a.ncol + ColCfg<P>::T - 1) / ColCfg<P>::T) * a.nouter;
     hipExtLaunchKernelGGL((k_col<P, MODE, NC, CFAST>), dim3((unsigned)nb), dim3(ColCfg<P>::NTH), (uint32_t)lds, s,
                           e0, e1, 0, a);
@@ -263,7 +263,7 @@ static hipError_t configure_col(bool three_d) {
 
 template <int P>
 static hipError_t configure_zconv(void) {
-    return allow_lds<P>((const void*)k_col<P, COL_CONV, 6, true>, col_lds<P, COL_CONV, 6>());
+    return allow_lds<P>((const void*)k_col<P, COL_CONV, 6, true>, col_lds<P, COL_CONV, 6, true>());
 }
 
 hipError_t configure_field_kernels(int px, int py, int pz) {

@@ -173,12 +173,13 @@ int run_cols(mm_ctx* c, bool check_done) {
         ca.khat = c->zker;
         MM_TRY(launch_yz(c->py, c->pz, ca, s, t.e1, t.e2));
     } else if (c->pz > 1) {
-        // y transforms of every (z, kx) column, in place (ny rows -> py rows)
+        // y transforms of every (kx, z) column, in place (ny rows -> py rows);
+        // tiles of adjacent z planes of one kx
         ca.pos_stride = 3;
-        ca.col_stride = c->colstride;
-        ca.ncol = c->kx;
-        ca.outer_stride = c->zstride;
-        ca.nouter = c->nz;
+        ca.col_stride = c->zstride;
+        ca.ncol = c->nz;
+        ca.outer_stride = c->colstride;
+        ca.nouter = c->kx;
         const bool ypass = c->py > 1;
         if (ypass) {
             ca.n_in = c->ny;
@@ -196,10 +197,10 @@ int run_cols(mm_ctx* c, bool check_done) {
         MM_TRY(launch_col(c->pz, COL_CONV, ca, 6, s, ypass ? nullptr : t.e1, ypass ? nullptr : t.e2));
         if (ypass) {
             ca.pos_stride = 3;
-            ca.col_stride = c->colstride;
-            ca.ncol = c->kx;
-            ca.outer_stride = c->zstride;
-            ca.nouter = c->nz;
+            ca.col_stride = c->zstride;
+            ca.ncol = c->nz;
+            ca.outer_stride = c->colstride;
+            ca.nouter = c->kx;
             ca.n_in = c->py;
             ca.n_out = c->ny;
             MM_TRY(launch_col(c->py, COL_INV, ca, 6, s, nullptr, t.e2));
@@ -489,9 +490,11 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
     c->yz = c->pz > 1 && yz_supported(c->py, c->pz);
     // rows per spectrum column: py when the y transforms run in place, else ny
     const long long ycount = (c->pz > 1 && !c->yz) ? c->py : c->ny;
-    c->colstride = 3LL * ycount;
-    c->zstride = (long long)c->kx * c->colstride;
-    c->spec_elems = c->zstride * c->nz;
+    // kx-major: the nz planes of one kx are adjacent, so the z transforms read
+    // rows a plane apart within one kx block
+    c->zstride = 3LL * ycount;
+    c->colstride = c->zstride * c->nz;
+    c->spec_elems = c->colstride * c->kx;
     c->khat_elems = (long long)c->kx * (c->py / 2 + 1) * (c->pz / 2 + 1) * c->ncomp;
     c->pt = c->px;
     if (c->py > c->pt) c->pt = c->py;

@@ -309,16 +309,17 @@ int mm_batch_create(mm_batch** out, int32_t n, const mm_grid* grids, const mm_pa
         m.spec_off = b->spec_elems;
         m.khat_off = b->khat_elems;
         m.zker_off = b->zker_elems;
-        // rows per spectrum column: py when the y transforms run in place, else ny
-        m.colstride = 3LL * (m.pz > 1 && !yz_supported(m.py, m.pz) ? m.py : m.ny);
-        m.zstride = (long long)m.kx * m.colstride;
+        // rows per spectrum column: py when the y transforms run in place, else ny;
+        // kx-major (the planes of one kx adjacent)
+        m.zstride = 3LL * (m.pz > 1 && !yz_supported(m.py, m.pz) ? m.py : m.ny);
+        m.colstride = m.zstride * m.nz;
         m.idx2 = (float)(1.0 / (g.dx * g.dx));
         m.idy2 = (float)(1.0 / (g.dy * g.dy));
         m.idz2 = (float)(1.0 / (g.dz * g.dz));
         m.cellvol = (float)(g.dx * g.dy * g.dz);
         const long long nc = (long long)g.nx * g.ny * g.nz;
         b->ncell += nc;
-        b->spec_elems += m.zstride * m.nz;
+        b->spec_elems += m.colstride * m.kx;
         b->khat_elems += (long long)m.kx * (m.py / 2 + 1) * (m.pz / 2 + 1) * (m.pz > 1 ? 6 : 4);
         if (m.pz > 1 && yz_supported(m.py, m.pz)) b->zker_elems += (long long)m.kx * (m.py / 2 + 1) * zkernel_floats(m.pz);
         if (m.pz == 1) b->has2d = true;
