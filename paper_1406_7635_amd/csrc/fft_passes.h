@@ -391,10 +391,26 @@ constexpr int col_seq() {
     return CFAST ? (seq_len(P) | 1) : seq_len(P);
 }
 
+// The 3D z convolution pairs the columns ky and py - ky in one tile (the
+// first half of the tile's columns take kyh = ky <= py/2, the second half
+// their mirrors), so each K^ block is loaded once; kyh = 0 and py/2 have no
+// distinct mirror.  Tiles per outer index:
+template <int P, int MODE, int NC>
+constexpr bool col_pairs() {
+    return MODE == COL_CONV && NC == 6 && ColCfg<P>::T >= 2;
+}
+template <int P, int MODE, int NC>
+__host__ __device__ constexpr int col_ntile(int ncol) {
+    constexpr int T = ColCfg<P>::T;
+    return col_pairs<P, MODE, NC>() ? (ncol / 2 + T / 2) / (T / 2) : (ncol + T - 1) / T;
+}
+
 template <int P, int MODE, int NC, bool CFAST>
 __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
     constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, T = ColCfg<P>::T;
     constexpr int SEQ = col_seq<P, CFAST>();
+    constexpr bool PAIR = col_pairs<P, MODE, NC>();
+    constexpr int TH = PAIR ? T / 2 : T;  // K^ blocks per tile
     if (a.check_done && a.st->done) return;
     int ci, s, t;
     if (CFAST) {
@@ -406,10 +422,19 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
         s = (tid / TPF) % 3;
         ci = tid / (3 * TPF);
     }
-    const int ntile = (a.ncol + T - 1) / T;
+    const int ntile = col_ntile<P, MODE, NC>(a.ncol);
     const int o = blk / ntile, tile = blk - o * ntile;
-    const int c = tile * T + ci;
-    const bool valid = c < a.ncol;
+    int c;
+    bool valid;
+    if constexpr (PAIR) {
+        const int kh = tile * TH + (ci % TH);
+        const bool mir = ci >= TH;
+        c = mir ? a.ncol - kh : kh;
+        valid = 2 * kh <= a.ncol && !(mir && (kh == 0 || 2 * kh == a.ncol));
+    } else {
+        c = tile * T + ci;
+        valid = c < a.ncol;
+    }
     // 2D convolution: column 0 carries kx = 0 (real part) and kx = px/2 (imaginary part)
     const bool packed = MODE == COL_CONV && NC == 4 && a.pack_col > 0 && c == 0;
     cf* base = a.spec + (long long)o * a.outer_stride + (long long)(valid ? c : 0) * a.col_stride;
@@ -460,16 +485,22 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
     float* lk6 = reinterpret_cast<float*>(lds + T * 3 * SEQ);
     if constexpr (MODE == COL_CONV && NC == 6) {
         constexpr int BL = KHP * 3;  // float2 per column block
-        constexpr int TOT = T * BL, NTH = ColCfg<P>::NTH, NIT = (TOT + NTH - 1) / NTH;
-        const int c0 = (blk - o * ntile) * T;
+        constexpr int TOT = TH * BL, NTH = ColCfg<P>::NTH, NIT = (TOT + NTH - 1) / NTH;
         float2 kt[NIT];
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
             const int e = tid + NTH * i;
             const int ce = e / BL, r = e - ce * BL;
-            const int cy = c0 + ce;
-            const bool in = (i < NIT - 1 || e < TOT) && cy < a.ncol;
-            const int kyh = 2 * cy > a.pa ? a.pa - cy : cy;
+            int kyh;
+            bool in;
+            if constexpr (PAIR) {
+                kyh = tile * TH + ce;
+                in = (i < NIT - 1 || e < TOT) && 2 * kyh <= a.pa;
+            } else {
+                const int cy = tile * T + ce;
+                in = (i < NIT - 1 || e < TOT) && cy < a.ncol;
+                kyh = 2 * cy > a.pa ? a.pa - cy : cy;
+            }
             const float2* src = reinterpret_cast<const float2*>(a.khat + ((long long)o * a.kyh + kyh) * (KHP * 6));
             kt[i] = in ? src[r] : make_float2(0.f, 0.f);
         }
@@ -522,7 +553,7 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
                     k2 = k4.z;
                     kxy = k4.w;
                 } else if (NC == 6) {
-                    const float* K = lk6 + (ci * KHP + qh) * 6;
+                    const float* K = lk6 + ((ci % TH) * KHP + qh) * 6;
                     k0 = K[0];
                     k1 = K[1];
                     k2 = K[2];
@@ -928,7 +959,9 @@ template <int P, int MODE, int NC, bool CFAST = false>
 constexpr size_t col_lds() {
     return (size_t)ColCfg<P>::T * 3 * col_seq<P, CFAST>() * sizeof(cf) +
            (MODE == COL_CONV && NC == 4 ? khat_lds<P>() : 0) +
-           (MODE == COL_CONV && NC == 6 ? (size_t)ColCfg<P>::T * (P / 2 + 1) * 6 * sizeof(float) : 0);
+           (MODE == COL_CONV && NC == 6
+                ? (size_t)(col_pairs<P, MODE, NC>() ? ColCfg<P>::T / 2 : ColCfg<P>::T) * (P / 2 + 1) * 6 * sizeof(float)
+                : 0);
 }
 
 }  // namespace mm

@@ -483,11 +483,11 @@ int batch_tiles(int pass, const BMember& m) {
         case BP_Y:
             return m.pz > 1 && !yz_supported(m.py, m.pz) ? cdiv(m.nz, col_t(m.py)) * m.kx : 0;
         case BP_Z4:
+            return m.pz == 4 && !yz_supported(m.py, m.pz) ? col_ntile<4, COL_CONV, 6>(m.py) * m.kx : 0;
         case BP_Z8:
-        case BP_Z16: {
-            const int pz = pass == BP_Z4 ? 4 : (pass == BP_Z8 ? 8 : 16);
-            return m.pz == pz && !yz_supported(m.py, m.pz) ? cdiv(m.py, col_t(pz)) * m.kx : 0;
-        }
+            return m.pz == 8 && !yz_supported(m.py, m.pz) ? col_ntile<8, COL_CONV, 6>(m.py) * m.kx : 0;
+        case BP_Z16:
+            return m.pz == 16 && !yz_supported(m.py, m.pz) ? col_ntile<16, COL_CONV, 6>(m.py) * m.kx : 0;
         case BP_YZ4:
         case BP_YZ8: {
             const int pz = pass == BP_YZ4 ? 4 : 8;

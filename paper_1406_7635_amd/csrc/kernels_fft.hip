@@ -121,7 +121,7 @@ static hipError_t xrow_p(const FieldArgs& ai, const FieldArgs& af, float a_last,
 template <int P, int MODE, int NC, bool CFAST>
 static hipError_t col_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const size_t lds = col_lds<P, MODE, NC, CFAST>();
-    const long long nb = (long long)((a.ncol + ColCfg<P>::T - 1) / ColCfg<P>::T) * a.nouter;
+    const long long nb = (long long)col_ntile<P, MODE, NC>(a.ncol) * a.nouter;
     hipExtLaunchKernelGGL((k_col<P, MODE, NC, CFAST>), dim3((unsigned)nb), dim3(ColCfg<P>::NTH), (uint32_t)lds, s,
                           e0, e1, 0, a);
     return hipGetLastError();
