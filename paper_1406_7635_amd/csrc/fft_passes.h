@@ -531,6 +531,29 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
                 fa = true;
             }
         }
+        if constexpr (NC == 6) {
+            // 3D: row s of the symmetric K^ (from the tile's blocks in LDS): s = 0
+            // (xx, xy, xz), 1 (xy, yy, yz), 2 (xz, yz, zz); xy is odd in y, xz
+            // odd in z, yz odd in both
+            const int j0 = s == 0 ? 0 : (s == 1 ? 3 : 4);
+            const int j1 = s == 0 ? 3 : (s == 1 ? 1 : 5);
+            const int j2 = s == 0 ? 4 : (s == 1 ? 5 : 2);
+            auto odd_y = [](int j) { return j == 3 || j == 5; };
+            auto odd_z = [](int j) { return j == 4 || j == 5; };
+            const float* Kb = lk6 + (ci % TH) * KHP * 6;
+#pragma unroll
+            for (int m = 0; m < PPT; ++m) {
+                const int q = t + TPF * m;
+                const bool fq = 2 * q > P;
+                const float* K = Kb + (fq ? P - q : q) * 6;
+                const float s0 = ((fa && odd_y(j0)) != (fq && odd_z(j0))) ? -1.f : 1.f;
+                const float s1 = ((fa && odd_y(j1)) != (fq && odd_z(j1))) ? -1.f : 1.f;
+                const float s2 = ((fa && odd_y(j2)) != (fq && odd_z(j2))) ? -1.f : 1.f;
+                const cf m0 = bufs[lds_pad(q)], m1 = bufs[SEQ + lds_pad(q)], m2 = bufs[2 * SEQ + lds_pad(q)];
+                const cf b = (s0 * K[j0]) * m0 + (s1 * K[j1]) * m1 + (s2 * K[j2]) * m2;
+                v[0][m] = valid ? b : mkc(0.f, 0.f);
+            }
+        } else {
 #pragma unroll
         for (int m = 0; m < PPT; ++m) {
             const int q = t + TPF * m;
@@ -611,6 +634,7 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
                 const cf bn = KN.x * an0 + KN.y * an1 + KN.z * an2;
                 v[0][m] = mkc(b0.x - bn.y, b0.y + bn.x);
             }
+        }
         }
         RegFft<P, TPF, 1, true>::run(v, buf, a.tw, a.twshift, t);
     }
