@@ -271,6 +271,35 @@ def ensemble_variant(steps, warmup, n=512):
             "dtype": "f32"}
 
 
+def size_sweep():
+    """The paper's throughput workload (n x n x 1, 4 nm cells, Msat 8e5, Aex
+    13e-12, alpha 0.01, B_ext 10 mT along y, m along x, RK45) for the powers of
+    two n = 16 ... 1024: cell evaluations per second against n (each point
+    about 0.1 s of attempts)."""
+    import torch
+
+    from paper_1406_7635_amd import mm, synth
+
+    out = {}
+    for n in (16, 32, 64, 128, 256, 512, 1024):
+        case = synth.paper_bench(n)
+        ctx = mm.Context(case["grid"], case["cell"], case["region"], case["params"])
+        m = torch.from_numpy(case["m0"]).cuda()
+        opts = mm.solver_opts(max_err=1e-5)
+        t, dt, _ = ctx.run(m, float("inf"), dt=1e-14, max_attempts=10, opts=opts)
+        k = int(min(3000, max(20, 4e7 / (n * n))))
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        t, dt, st = ctx.run(m, float("inf"), t=t, dt=dt, max_attempts=k, opts=opts)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        out[str(n)] = {"value": n * n * st["evals"] / wall, "ms_per_attempt": 1e3 * wall / k, "attempts": k}
+        ctx.close()
+    return {"unit": "Beff evals*cells/s", "points": out,
+            "workload": "n x n x 1, 4 nm cells, Msat 8e5, Aex 13e-12, alpha 0.01, B_ext (0, 10 mT, 0), "
+                        "m = x; RK45 MaxErr 1e-5; plain FP32", "dtype": "f32"}
+
+
 def grains_variant(steps, warmup):
     """The 3D workload: 256 x 256 x 64 cells of 3 nm, 256 Voronoi grains
     (random m, the worst-case spectrum), plain FP32 Dormand-Prince: throughput
@@ -380,6 +409,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble variant")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate variant")
     ap.add_argument("--no-grains", action="store_true", help="skip the 3D grain-workload variant")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the n x n x 1 size sweep")
     ap.add_argument("--grains-only", action="store_true",
                     help="only the 3D grain-workload variant (one JSON line; for profiling)")
     ap.add_argument("--surrogate-only", action="store_true",
@@ -482,6 +512,8 @@ def main():
         out["variants"]["surrogate"] = surrogate_variant(max(10, args.steps // 4), max(2, args.warmup // 4))
     if not args.no_grains:
         out["variants"]["grains"] = grains_variant(max(5, args.steps // 20), max(2, args.warmup // 10))
+    if not args.no_sweep:
+        out["variants"]["size_sweep"] = size_sweep()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     else:
