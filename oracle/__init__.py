@@ -11,7 +11,7 @@ Modules
 -------
 constants   physical constants used by the oracle (its own copies)
 demag       Newell demagnetising tensor, far-field quadrature, FFT and direct
-            convolution (paper section "Magnetostatic field")
+            convolution, periodic images (paper section "Magnetostatic field")
 fields      exchange, uniaxial anisotropy, Zeeman, effective field, Landau-
             Lifshitz torque and energies (sections "Landau-Lifshitz torque",
             "Heisenberg exchange interaction", "Magneto-crystalline anisotropy")

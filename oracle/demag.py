@@ -250,3 +250,84 @@ def demag_field_direct(M, octant):
                 for i, j, c in _PAIRS:
                     B[i, z, y, x] += np.sum(sub[c] * M[j])
     return -MU0 * B
+
+
+# ---------------------------------------------------------------------------
+# Periodic boundary conditions by macro geometry (paper paragraph "Periodic
+# boundary conditions"): along a periodic axis the magnetisation repeats with
+# the box length L = n d, and a finite number P of repetitions is counted.
+# Reading (pinned by the paper's tables tabPBC1 / tabPBC2, see the tests): a
+# destination cell feels every source -- the box's own cells and their images
+# -- whose displacement along that axis lies within +-(n P - 1) cells, the
+# window of a non-periodic grid 2 n P cells long around the destination.
+
+
+def window_radius(grid, pbc):
+    """Largest |displacement| (cells) per axis: n P - 1 along a periodic axis
+    with P images per side, n - 1 otherwise."""
+    return tuple(int(n) * int(p) - 1 if p > 0 else int(n) - 1 for n, p in zip(grid, pbc))
+
+
+def tensor_window(grid, cell, pbc):
+    """N at every signed displacement of the window: [6, 2Rz+1, 2Ry+1, 2Rx+1],
+    entry [c, k + Rz, j + Ry, i + Rx] = N_c(i dx, j dy, k dz).
+
+    Evaluated at the signed displacement itself (no parity folding)."""
+    rx, ry, rz = window_radius(grid, pbc)
+    dx, dy, dz = cell
+    k, j, i = np.meshgrid(np.arange(-rz, rz + 1), np.arange(-ry, ry + 1), np.arange(-rx, rx + 1), indexing="ij")
+    t = tensor_at(i * dx, j * dy, k * dz, cell)
+    return np.stack([t[c] for c in COMPONENTS])
+
+
+def demag_field_fft_pbc(M, window, pbc, workers=None):
+    """B_demag = -mu0 N * M with periodic axes (tesla), by FFT.
+
+    Along a periodic axis the convolution is cyclic with period n: the kernel
+    of the cyclic transform (length n) at index q is the sum of N over every
+    window displacement congruent to q modulo n.  A non-periodic axis is
+    zero-padded to 2n - 1 as in demag_field_fft.  `window` is tensor_window's
+    array for the same grid and pbc."""
+    _, nz, ny, nx = M.shape
+    shape = tuple(n if p > 0 else 2 * n - 1 for n, p in zip((nz, ny, nx), (pbc[2], pbc[1], pbc[0])))
+    _, wz, wy, wx = window.shape
+    rz, ry, rx = (wz - 1) // 2, (wy - 1) // 2, (wx - 1) // 2
+    dk, dj, di = np.meshgrid(np.arange(-rz, rz + 1), np.arange(-ry, ry + 1), np.arange(-rx, rx + 1), indexing="ij")
+    kern = np.zeros((6,) + shape)
+    for c in range(6):
+        np.add.at(kern[c], (dk % shape[0], dj % shape[1], di % shape[2]), window[c])
+    khat = scipy.fft.rfftn(kern, axes=(1, 2, 3), workers=workers)
+    mhat = scipy.fft.rfftn(M, s=shape, axes=(1, 2, 3), workers=workers)
+    bhat = np.zeros_like(mhat)
+    for i, j, c in _PAIRS:
+        bhat[i] += khat[c] * mhat[j]
+    b = scipy.fft.irfftn(bhat, s=shape, axes=(1, 2, 3), workers=workers)
+    return -MU0 * b[:, :nz, :ny, :nx]
+
+
+def demag_field_direct_pbc(M, window, pbc):
+    """B_demag with periodic axes by the literal sum over source cells and
+    their images: image s of source r' sits at r' + s L; it counts when the
+    displacement r - r' - s L lies inside the window on every axis."""
+    _, nz, ny, nx = M.shape
+    _, wz, wy, wx = window.shape
+    R = ((wx - 1) // 2, (wy - 1) // 2, (wz - 1) // 2)
+    grid = (nx, ny, nz)
+    shifts = [range(-p, p + 1) if p > 0 else range(0, 1) for p in pbc]
+    B = np.zeros_like(M, dtype=np.float64)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                for zs in range(nz):
+                    for ys in range(ny):
+                        for xs in range(nx):
+                            for sz in shifts[2]:
+                                for sy in shifts[1]:
+                                    for sx in shifts[0]:
+                                        d = (x - xs - sx * grid[0], y - ys - sy * grid[1], z - zs - sz * grid[2])
+                                        if any(abs(d[a]) > R[a] for a in range(3)):
+                                            continue
+                                        n = window[:, d[2] + R[2], d[1] + R[1], d[0] + R[0]]
+                                        for i, j, c in _PAIRS:
+                                            B[i, z, y, x] += n[c] * M[j, zs, ys, xs]
+    return -MU0 * B

@@ -47,17 +47,28 @@ def exchange_coefficient(params, ra, rb):
     return 2.0 * exchange_scale(params, ra, rb) * hm
 
 
-def exchange_field(m, region, params, cell):
+def exchange_field(m, region, params, cell, pbc=(0, 0, 0)):
     """6-neighbour exchange field (T), paper Eqs. eqBexch1 / eqBexch.
 
     B(c) = sum over the existing neighbours n of c(r_c, r_n) (m_n - m_c) / D_n^2.
     A neighbour outside the grid is replaced by the cell itself (Neumann
-    boundary), i.e. it contributes nothing."""
+    boundary), i.e. it contributes nothing.  Along a periodic axis (pbc > 0,
+    paragraph "Periodic boundary conditions") the grid wraps around: the last
+    cell and the first are neighbours."""
     m = np.asarray(m, dtype=np.float64)
     B = np.zeros_like(m)
-    for axis, d in zip((3, 2, 1), cell):       # array axis of x, y, z
+    for axis, d, p in zip((3, 2, 1), cell, pbc):   # array axis of x, y, z
         n = m.shape[axis]
         if n < 2:
+            continue
+        if p > 0:
+            # the faces (i, i + 1 mod n), the wrap-around face included
+            nb = np.roll(m, -1, axis=axis)
+            rnb = np.roll(region, -1, axis=axis - 1)
+            coef = exchange_coefficient(params, region, rnb) / (d * d)
+            diff = nb - m
+            B += coef * diff                            # neighbour on the + side
+            B -= np.roll(coef * diff, 1, axis=axis)     # neighbour on the - side
             continue
         lo = [slice(None)] * 4
         hi = [slice(None)] * 4
@@ -105,15 +116,22 @@ class Problem:
     grid = (nx, ny, nz), cell = (dx, dy, dz) in metres; demag=False drops the
     magnetostatic term (the paper's EnableDemag = false)."""
 
-    def __init__(self, grid, cell, region, params, demag=True, workers=None):
+    def __init__(self, grid, cell, region, params, demag=True, workers=None, pbc=(0, 0, 0)):
         self.grid = tuple(int(v) for v in grid)
         self.cell = tuple(float(v) for v in cell)
         self.region = np.asarray(region, dtype=np.uint8).reshape(self.grid[::-1])
         self.params = params
         self.demag = demag
         self.workers = workers
+        self.pbc = tuple(int(v) for v in pbc)
         self.gamma = float(params.get("gamma_ll", 0.0) or GAMMA_LL)
-        self.octant = _demag.tensor_octant(self.grid, self.cell) if demag else None
+        self.periodic = any(p > 0 for p in self.pbc)
+        self.octant = None
+        self.window = None
+        if demag and self.periodic:
+            self.window = _demag.tensor_window(self.grid, self.cell, self.pbc)
+        elif demag:
+            self.octant = _demag.tensor_octant(self.grid, self.cell)
         self.magnetic = _lut(params, "msat", self.region) > 0
 
     # -- field terms ---------------------------------------------------------
@@ -121,6 +139,8 @@ class Problem:
         if not self.demag:
             return np.zeros((3,) + self.region.shape)
         M = magnetisation(m, self.region, self.params)
+        if self.periodic:
+            return _demag.demag_field_fft_pbc(M, self.window, self.pbc, workers=self.workers)
         return _demag.demag_field_fft(M, self.octant, workers=self.workers)
 
     def terms(self, m):
@@ -128,7 +148,7 @@ class Problem:
         b1, b2 = anisotropy_field_parts(m, self.region, self.params)
         return {
             "demag": self.demag_field(m),
-            "exch": exchange_field(m, self.region, self.params, self.cell),
+            "exch": exchange_field(m, self.region, self.params, self.cell, self.pbc),
             "anis1": b1,
             "anis2": b2,
             "zeeman": zeeman_field(self.region, self.params),
