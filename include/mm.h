@@ -65,7 +65,15 @@ typedef struct mm_ctx mm_ctx;
 /* Finite-difference grid (section "Material Regions"): nx*ny*nz orthorhombic
  * cells of dx*dy*dz metres.  Each axis is zero-padded for the aperiodic
  * convolution to the power of two >= 2n-1 (no padding when n = 1); padded
- * lengths above 4096 return MM_EUNSUPPORTED.  pbc must be {0,0,0}. */
+ * lengths above 4096 return MM_EUNSUPPORTED.
+ * pbc[a] >= 0: periodic boundary conditions along axis a (x, y, z) by macro
+ * geometry (section "Magnetostatic field", paragraph "Periodic boundary
+ * conditions"): P = pbc[a] > 0 counts the images of the box along that axis
+ * such that a cell feels every source, image or not, whose displacement lies
+ * within +-(n P - 1) cells (the field of a box 2 n P cells long around it),
+ * and the exchange stencil wraps around.  0: open boundary.  The images enter
+ * the kernel only: the field passes are the same (the periodic axis keeps its
+ * zero padding).  Ensembles take pbc = {0,0,0} only. */
 typedef struct {
     int32_t nx, ny, nz;
     double dx, dy, dz;
@@ -132,9 +140,10 @@ typedef struct {
  * Allocates every buffer; derives the FP32 region tables and the exchange
  * pair table on the device.  Demag is enabled but needs mm_demag_kernel_init
  * before the first field evaluation.  Returns MM_EINVAL for null pointers,
- * non-positive sizes or non-finite cell sizes, MM_EUNSUPPORTED for padded
- * lengths above 4096, more than 2^28 cells or non-zero pbc, MM_ENOMEM if
- * allocation fails. */
+ * non-positive sizes, non-finite cell sizes or negative pbc, MM_EUNSUPPORTED
+ * for padded lengths above 4096, more than 2^28 cells, or an image window
+ * (the product over the axes of n P, or n without images) above 2^26
+ * displacements, MM_ENOMEM if allocation fails. */
 int mm_create(mm_ctx **out, const mm_grid *g, const mm_params *p, const uint8_t *region_dev,
               void *hip_stream);
 
@@ -144,8 +153,12 @@ int mm_create(mm_ctx **out, const mm_grid *g, const mm_params *p, const uint8_t 
  * Gauss-Legendre quadrature of the dipole tensor far away -- mirrored into the
  * padded grid using its symmetries, Fourier transformed in FP64, scaled by
  * -mu0 / (px py pz) and truncated to FP32.  Only the non-redundant octant of
- * the real spectrum is kept (4 components in 2D, 6 in 3D).  Temporary FP64
- * buffers are allocated and freed inside the call.  Synchronous. */
+ * the real spectrum is kept (4 components in 2D, 6 in 3D).  With periodic
+ * axes the tensor is evaluated over the whole image window (0 .. n P - 1 cells
+ * along such an axis) and each box displacement takes the sum over its
+ * images (its negative-displacement images by the tensor's parity) before
+ * the mirror fill.  Temporary FP64 buffers are allocated and freed inside the
+ * call.  Synchronous. */
 int mm_demag_kernel_init(mm_ctx *c);
 
 /* Replace the material tables (same validation as mm_create).  Invalidates
@@ -224,13 +237,15 @@ int mm_get_info(mm_ctx *c, mm_info *info);
 /* Diagnostics.  mm_demag_tensor_dump writes the FP64 real-space tensor N(d)
  * for d = (i dx, j dy, k dz), 0 <= i < nx etc., as [6][nz][ny][nx] doubles
  * (component order xx, yy, zz, xy, xz, yz) into out_dev (recomputed on the
- * device).  mm_demag_kernel_dump copies the FP32 kernel spectrum, layout
+ * device; on a periodic grid, the sum over the images of each displacement,
+ * as the kernel takes it; synchronises then).  mm_demag_kernel_dump copies the FP32 kernel spectrum, layout
  * [kx][ky_h][kz_h][ncomp] (h = folded index 0..p/2; ncomp = 6 in 3D with
  * order xx, yy, zz, xy, xz, yz, or 4 when nz == 1: xx, yy, zz, xy),
  * khat_elems floats.  mm_exchange_dump writes the per-face exchange
  * coefficient c(r, r_n)/D^2 actually gathered by the field kernels, as
  * [6][nz][ny][nx] floats in face order -x, +x, -y, +y, -z, +z (0 where the
- * neighbour is missing). */
+ * neighbour is missing; across a periodic boundary the neighbour is the
+ * cell at the other end of an axis longer than one cell). */
 int mm_demag_tensor_dump(mm_ctx *c, double *out_dev);
 int mm_demag_kernel_dump(mm_ctx *c, float *out_dev);
 int mm_exchange_dump(mm_ctx *c, float *out_dev);
@@ -363,7 +378,8 @@ void mm_sno_destroy(mm_sno *s);
  * and if err > tol (or is not finite) the attempt is rejected with dt kept and
  * the rest of that mm_run call uses the exact path (fallback).  The surrogate
  * must outlive its use; s = NULL detaches it.  Allocates two field buffers
- * the first time.  Synchronises. */
+ * the first time.  A periodic grid returns MM_EUNSUPPORTED (the network
+ * models open boundaries).  Synchronises. */
 int mm_set_surrogate(mm_ctx *c, const mm_sno *s, double tol);
 /* Accepted steps taken with surrogate stages since mm_set_surrogate,
  * fallbacks since the last solver restart, err of the last checked attempt. */

@@ -150,7 +150,8 @@ __device__ inline float3 stage_state(const FieldArgs& a, const Resolved& r, long
 
 // Exchange field at (x, y, z) from the state array mp.  A neighbour outside
 // the grid is replaced by the cell itself (the Neumann rule), which adds
-// c (m - m) = 0; so every neighbour is loaded without a branch.  The six
+// c (m - m) = 0; so every neighbour is loaded without a branch.  Along a
+// periodic axis the grid wraps around instead.  The six
 // neighbour slots have fixed positions (x-, x+, y-, y+, z-, z+) so the arrays
 // stay in registers; the y and z pairs are skipped (uniformly) for a single
 // layer along that axis.
@@ -159,13 +160,17 @@ __device__ inline float3 exchange_at(const FieldArgs& a, const float* __restrict
     const long long n = a.ncell;
     const int sxy = a.nx * a.ny;
     const bool use_y = a.ny > 1, use_z = a.nz > 1;
+    // wrap-around offsets of the low faces (the high faces take their negatives)
+    const int ox = (a.pbc & 1) ? a.nx - 1 : 0;
+    const int oy = (a.pbc & 2) ? sxy - a.nx : 0;
+    const int oz = (a.pbc & 4) ? (int)(n - sxy) : 0;
     int d[6];  // neighbour - cell, in cells
-    d[0] = x > 0 ? -1 : 0;
-    d[1] = x < a.nx - 1 ? 1 : 0;
-    d[2] = y > 0 ? -a.nx : 0;
-    d[3] = y < a.ny - 1 ? a.nx : 0;
-    d[4] = z > 0 ? -sxy : 0;
-    d[5] = z < a.nz - 1 ? sxy : 0;
+    d[0] = x > 0 ? -1 : ox;
+    d[1] = x < a.nx - 1 ? 1 : -ox;
+    d[2] = y > 0 ? -a.nx : oy;
+    d[3] = y < a.ny - 1 ? a.nx : -oy;
+    d[4] = z > 0 ? -sxy : oz;
+    d[5] = z < a.nz - 1 ? sxy : -oz;
     const float id2[3] = {a.idx2, a.idy2, a.idz2};
     const unsigned int c = (unsigned int)cell;
     int rn[6];

@@ -188,6 +188,63 @@ hipError_t demag_tensor_octant(int nx, int ny, int nz, double dx, double dy, dou
 }
 
 // ---------------------------------------------------------------------------
+// Periodic images (paragraph "Periodic boundary conditions"): the kernel entry
+// of box displacement (i, j, k) is the sum of N over the displacements
+// i + s nx (and likewise along y, z) that stay inside the window |d| <= n P - 1
+// of a periodic axis; a non-periodic axis keeps d = i.  The window tensor is
+// stored for d >= 0 (lengths wx, wy, wz); a negative d takes the parity of the
+// component along that axis.  With these sums in place of the octant, the
+// mirror fill below gives the displacement -d the entry of the box
+// displacement n - d (the sums satisfy S(n - d) = parity S(d)), so the padded
+// linear convolution becomes the cyclic one along the periodic axes.
+__global__ void __launch_bounds__(256) k_fold_images(int nx, int ny, int nz, int wx, int wy, int wz, int qx,
+                                                     int qy, int qz, const double* __restrict__ win,
+                                                     double* __restrict__ oct) {
+    const long long n = (long long)nx * ny * nz;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int i = (int)(id % nx);
+    const long long rest = id / nx;
+    const int j = (int)(rest % ny), k = (int)(rest / ny);
+    const long long wn = (long long)wx * wy * wz;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int sz = -qz; sz <= qz; ++sz) {
+        const int dk = k + sz * nz;
+        if (dk <= -wz || dk >= wz) continue;
+        const int ak = dk < 0 ? -dk : dk;
+        const bool nzg = dk < 0;
+        for (int sy = -qy; sy <= qy; ++sy) {
+            const int dj = j + sy * ny;
+            if (dj <= -wy || dj >= wy) continue;
+            const int aj = dj < 0 ? -dj : dj;
+            const bool nyg = dj < 0;
+            for (int sx = -qx; sx <= qx; ++sx) {
+                const int di = i + sx * nx;
+                if (di <= -wx || di >= wx) continue;
+                const int ai = di < 0 ? -di : di;
+                const bool nxg = di < 0;
+                const long long e = ((long long)ak * wy + aj) * wx + ai;
+                acc[0] += win[e];
+                acc[1] += win[wn + e];
+                acc[2] += win[2 * wn + e];
+                acc[3] += (nxg != nyg ? -1.0 : 1.0) * win[3 * wn + e];  // xy: odd in x, y
+                acc[4] += (nxg != nzg ? -1.0 : 1.0) * win[4 * wn + e];  // xz: odd in x, z
+                acc[5] += (nyg != nzg ? -1.0 : 1.0) * win[5 * wn + e];  // yz: odd in y, z
+            }
+        }
+    }
+    for (int c = 0; c < 6; ++c) oct[c * n + id] = acc[c];
+}
+
+hipError_t demag_fold_images(int nx, int ny, int nz, const int* w, const int* pbc, const double* win,
+                             double* oct, hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
+    hipLaunchKernelGGL(k_fold_images, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nx, ny, nz, w[0], w[1],
+                       w[2], pbc[0], pbc[1], pbc[2], win, oct);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Mirror fill of component c into the complex FP64 padded array.
 __global__ void __launch_bounds__(256) k_mirror_fill(int nx, int ny, int nz, int px, int py, int pz,
                                                      int comp, const double* __restrict__ oct, double scale,

@@ -310,8 +310,15 @@ __global__ void __launch_bounds__(NT) k_exchange_dump(const FieldArgs a, float* 
     const int y = (int)(rr % a.ny), z = (int)(rr / a.ny);
     const int r = a.region[i];
     const long long sxy = (long long)a.nx * a.ny;
-    const bool has[6] = {x > 0, x < a.nx - 1, y > 0, y < a.ny - 1, z > 0, z < a.nz - 1};
-    const long long off[6] = {-1, 1, -(long long)a.nx, (long long)a.nx, -sxy, sxy};
+    // a face exists inside the grid, or across a periodic boundary of an axis
+    // longer than one cell
+    const bool wx = (a.pbc & 1) && a.nx > 1, wy = (a.pbc & 2) && a.ny > 1, wz = (a.pbc & 4) && a.nz > 1;
+    const bool has[6] = {x > 0 || wx, x < a.nx - 1 || wx, y > 0 || wy, y < a.ny - 1 || wy,
+                         z > 0 || wz, z < a.nz - 1 || wz};
+    const long long nxl = a.nx;
+    const long long off[6] = {x > 0 ? -1 : nxl - 1, x < a.nx - 1 ? 1 : 1 - nxl,
+                              y > 0 ? -nxl : sxy - nxl, y < a.ny - 1 ? nxl : nxl - sxy,
+                              z > 0 ? -sxy : (a.nz - 1) * sxy, z < a.nz - 1 ? sxy : (1 - a.nz) * sxy};
     const float id2[6] = {a.idx2, a.idx2, a.idy2, a.idy2, a.idz2, a.idz2};
     for (int f = 0; f < 6; ++f) {
         float c = 0.f;

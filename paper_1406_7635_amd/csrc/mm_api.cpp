@@ -40,6 +40,8 @@ struct mm_ctx {
     long long ncell = 0, colstride = 0, zstride = 0, spec_elems = 0, khat_elems = 0;
     int pt = 1, twshift = 0;
     bool demag_on = true, khat_ready = false;
+    int pbc[3] = {0, 0, 0};  // images per side (0: open boundary)
+    int win[3] = {1, 1, 1};  // tensor window per axis: n P, or n
     uint8_t* region = nullptr;
     double* params64 = nullptr;
     RegionLut* lut = nullptr;
@@ -118,6 +120,7 @@ FieldArgs base_args(mm_ctx* c, const float* m0) {
     a.twshift = c->twshift;
     a.partials = c->partials;
     a.cellvol = (float)(c->dx * c->dy * c->dz);
+    a.pbc = (c->pbc[0] > 0 ? 1 : 0) | (c->pbc[1] > 0 ? 2 : 0) | (c->pbc[2] > 0 ? 4 : 0);
     return a;
 }
 
@@ -446,7 +449,7 @@ const char* mm_strerror(int status) {
         case MM_EINVAL: return "invalid argument";
         case MM_ENOMEM: return "device memory allocation failed";
         case MM_EDEVICE: return "HIP runtime error";
-        case MM_EUNSUPPORTED: return "unsupported configuration (padded length > 4096 or PBC)";
+        case MM_EUNSUPPORTED: return "unsupported configuration (size, image window or feature)";
         case MM_ENONFINITE: return "non-finite error estimate";
         case MM_ESTEP: return "time step fell below dt_min";
         case MM_ENOTCONVERGED: return "relax did not reach the MaxErr floor within max_steps";
@@ -461,8 +464,16 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
     *out = nullptr;
     if (g->nx < 1 || g->ny < 1 || g->nz < 1) return MM_EINVAL;
     if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->dz)) return MM_EINVAL;
-    if (g->pbc[0] || g->pbc[1] || g->pbc[2]) return MM_EUNSUPPORTED;
+    if (g->pbc[0] < 0 || g->pbc[1] < 0 || g->pbc[2] < 0) return MM_EINVAL;
     if (g->nx > 2048 || g->ny > 2048 || g->nz > 2048) return MM_EUNSUPPORTED;
+    // image window: n P displacements (0 .. n P - 1) along a periodic axis
+    long long win[3];
+    const int nn[3] = {g->nx, g->ny, g->nz};
+    for (int ax = 0; ax < 3; ++ax) {
+        if (g->pbc[ax] > (1 << 20)) return MM_EUNSUPPORTED;
+        win[ax] = g->pbc[ax] > 0 ? (long long)nn[ax] * g->pbc[ax] : nn[ax];
+    }
+    if (win[0] * win[1] * win[2] > (1LL << 26)) return MM_EUNSUPPORTED;
     // one component array must stay below 2^30 bytes (32-bit offsets in the kernels)
     if ((long long)g->nx * g->ny * g->nz > (1LL << 28)) return MM_EUNSUPPORTED;
     MM_CHECK(validate_params(p));
@@ -478,6 +489,10 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
     c->dz = g->dz;
     c->nrows = g->ny * g->nz;
     c->ncell = (long long)g->nx * g->ny * g->nz;
+    for (int ax = 0; ax < 3; ++ax) {
+        c->pbc[ax] = g->pbc[ax];
+        c->win[ax] = (int)win[ax];
+    }
     c->px = pad_len(g->nx);
     c->py = pad_len(g->ny);
     c->pz = pad_len(g->nz);
@@ -551,17 +566,27 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
 int mm_demag_kernel_init(mm_ctx* c) {
     if (!c) return MM_EINVAL;
     double* oct = nullptr;
+    double* win = nullptr;  // the tensor over the image window (periodic grids)
     double2* work = nullptr;
+    const bool periodic = c->pbc[0] > 0 || c->pbc[1] > 0 || c->pbc[2] > 0;
     hipError_t e = hipMalloc((void**)&oct, (size_t)6 * c->ncell * sizeof(double));
     if (e == hipSuccess)
         e = hipMalloc((void**)&work, (size_t)c->px * c->py * c->pz * sizeof(double2));
-    if (e == hipSuccess) e = demag_tensor_octant(c->nx, c->ny, c->nz, c->dx, c->dy, c->dz, oct, c->stream);
+    if (e == hipSuccess && periodic)
+        e = hipMalloc((void**)&win, (size_t)6 * c->win[0] * c->win[1] * c->win[2] * sizeof(double));
+    if (e == hipSuccess && periodic) {
+        e = demag_tensor_octant(c->win[0], c->win[1], c->win[2], c->dx, c->dy, c->dz, win, c->stream);
+        if (e == hipSuccess) e = demag_fold_images(c->nx, c->ny, c->nz, c->win, c->pbc, win, oct, c->stream);
+    } else if (e == hipSuccess) {
+        e = demag_tensor_octant(c->nx, c->ny, c->nz, c->dx, c->dy, c->dz, oct, c->stream);
+    }
     if (e == hipSuccess)
         e = demag_kernel_spectrum(c->nx, c->ny, c->nz, c->px, c->py, c->pz, oct, work, c->khat, c->ncomp,
                                   c->kx, c->stream);
     if (e == hipSuccess && c->yz) e = launch_zkernel(c->khat, c->zker, (long long)c->kx * (c->py / 2 + 1), c->pz, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (oct) (void)hipFree(oct);
+    if (win) (void)hipFree(win);
     if (work) (void)hipFree(work);
     if (e != hipSuccess) return map_err(e);
     c->khat_ready = true;
@@ -813,7 +838,15 @@ int mm_get_info(mm_ctx* c, mm_info* info) {
 
 int mm_demag_tensor_dump(mm_ctx* c, double* out_dev) {
     if (!c || !out_dev) return MM_EINVAL;
-    return map_err(demag_tensor_octant(c->nx, c->ny, c->nz, c->dx, c->dy, c->dz, out_dev, c->stream));
+    if (c->pbc[0] == 0 && c->pbc[1] == 0 && c->pbc[2] == 0)
+        return map_err(demag_tensor_octant(c->nx, c->ny, c->nz, c->dx, c->dy, c->dz, out_dev, c->stream));
+    double* win = nullptr;
+    hipError_t e = hipMalloc((void**)&win, (size_t)6 * c->win[0] * c->win[1] * c->win[2] * sizeof(double));
+    if (e == hipSuccess) e = demag_tensor_octant(c->win[0], c->win[1], c->win[2], c->dx, c->dy, c->dz, win, c->stream);
+    if (e == hipSuccess) e = demag_fold_images(c->nx, c->ny, c->nz, c->win, c->pbc, win, out_dev, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (win) (void)hipFree(win);
+    return map_err(e);
 }
 
 int mm_demag_kernel_dump(mm_ctx* c, float* out_dev) {
@@ -850,6 +883,7 @@ int mm_set_surrogate(mm_ctx* c, const mm_sno* s, double tol) {
     int nx = 0, ny = 0;
     sno_grid(s, &nx, &ny);
     if (c->nz != 1 || nx != c->nx || ny != c->ny) return MM_EUNSUPPORTED;
+    if (c->pbc[0] > 0 || c->pbc[1] > 0 || c->pbc[2] > 0) return MM_EUNSUPPORTED;
     if (!c->bsur) {
         MM_TRY(dalloc(c, (void**)&c->bsur, (size_t)3 * c->ncell * sizeof(float)));
         MM_TRY(dalloc(c, (void**)&c->bexact, (size_t)3 * c->ncell * sizeof(float)));

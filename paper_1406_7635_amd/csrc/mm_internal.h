@@ -89,6 +89,7 @@ struct FieldArgs {
     double* partials;             // [blocks][4] energy partial sums
     float cellvol;
     int flags;
+    int pbc;                      // periodic axes: bit 0 x, bit 1 y, bit 2 z (exchange wraps around)
 };
 
 struct ColArgs {
@@ -248,6 +249,11 @@ hipError_t launch_exchange_dump(const FieldArgs& a, float* out, hipStream_t s);
 // ---- demag kernel construction (kernels_demag.hip) -------------------------
 hipError_t demag_tensor_octant(int nx, int ny, int nz, double dx, double dy, double dz,
                                double* out, hipStream_t s);
+// periodic images: oct[c][k][j][i] = sum over the images of the box
+// displacement (i, j, k) of the window tensor win[c][|dk|][|dj|][|di|], the
+// negative displacements by parity (win: lengths w[3] = n P or n)
+hipError_t demag_fold_images(int nx, int ny, int nz, const int* w, const int* pbc, const double* win,
+                             double* oct, hipStream_t s);
 hipError_t demag_kernel_spectrum(int nx, int ny, int nz, int px, int py, int pz,
                                  const double* octant, double2* work, float* khat, int ncomp,
                                  int kx, hipStream_t s);

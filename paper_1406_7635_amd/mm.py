@@ -157,9 +157,10 @@ class Context:
     """One simulation grid on the current CUDA (HIP) device.
 
     grid (nx, ny, nz), cell (dx, dy, dz) in m, region uint8 [nz, ny, nx]
-    (numpy or tensor), params dict of region tables."""
+    (numpy or tensor), params dict of region tables; pbc (Px, Py, Pz): images
+    per side along each axis (0: open boundary)."""
 
-    def __init__(self, grid, cell, region, params, demag=True, stream=None):
+    def __init__(self, grid, cell, region, params, demag=True, stream=None, pbc=(0, 0, 0)):
         import torch
 
         self._torch = torch
@@ -175,7 +176,8 @@ class Context:
             raise ValueError("region must have shape (nz, ny, nx) = %s" % ((nz, ny, nx),))
         self._region = reg.to(self.device, torch.uint8).contiguous()
         self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        g = Grid(nx, ny, nz, *self.cell, (c_int32 * 3)(0, 0, 0))
+        self.pbc = tuple(int(v) for v in pbc)
+        g = Grid(nx, ny, nz, *self.cell, (c_int32 * 3)(*self.pbc))
         self._params = params_struct(params)
         handle = c_void_p()
         _check(lib.mm_create(ctypes.byref(handle), ctypes.byref(g), ctypes.byref(self._params),
