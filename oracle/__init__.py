@@ -15,9 +15,11 @@ demag       Newell demagnetising tensor, far-field quadrature, FFT and direct
 fields      exchange, uniaxial anisotropy, Zeeman, effective field, Landau-
             Lifshitz torque and energies (sections "Landau-Lifshitz torque",
             "Heisenberg exchange interaction", "Magneto-crystalline anisotropy")
-integrate   classical RK4, Bogacki-Shampine 3(2), Dormand-Prince 5(4), the
+integrate   classical RK4, Heun 2(1), Bogacki-Shampine 3(2), Dormand-Prince 5(4), the
             adaptive step controller and relax() (sections "Dynamics",
             "Adaptive time step", "Energy minimization")
+thermal     Brown's thermal field with a counter-based Philox4x32-10 generator,
+            Heun steps at finite temperature (section "Thermal fluctuations")
 
 Parity status: every function is pinned by the `-m "not gpu"` tests in
 tests/test_oracle_*.py against closed forms, brute force or invariants, except

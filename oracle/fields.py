@@ -154,18 +154,21 @@ class Problem:
             "zeeman": zeeman_field(self.region, self.params),
         }
 
-    def beff(self, m):
-        """Effective field (T); zero in cells with Msat = 0."""
+    def beff(self, m, extra=None):
+        """Effective field (T); zero in cells with Msat = 0.  `extra` (e.g. the
+        thermal field, section "Thermal fluctuations") is added as is."""
         t = self.terms(m)
         b = t["demag"] + t["exch"] + t["anis1"] + t["anis2"] + t["zeeman"]
+        if extra is not None:
+            b = b + extra
         return b * self.magnetic
 
-    def torque(self, m, precess=True):
+    def torque(self, m, precess=True, extra=None):
         """Landau-Lifshitz torque (1/s), paper Eq. eqLLG with the sign that damps.
 
         tau = -gamma/(1+alpha^2) [m x B + alpha m x (m x B)]; with precess=False
         (relax, section "Energy minimization") the m x B term is dropped."""
-        return llg_torque(m, self.beff(m), _lut(self.params, "alpha", self.region),
+        return llg_torque(m, self.beff(m, extra), _lut(self.params, "alpha", self.region),
                           self.gamma, precess) * self.magnetic
 
     def energy(self, m):

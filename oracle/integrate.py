@@ -1,7 +1,8 @@
 """Time integration of the Landau-Lifshitz equation (oracle, FP64, CPU).
 
 Paper section "Dynamics": RK45 (Dormand-Prince, 5th order with a 4th-order
-error estimate, the default), RK32 (Bogacki-Shampine, used by relax) and the
+error estimate, the default), RK32 (Bogacki-Shampine, used by relax), RK12
+(Heun, second order with the Euler step as error estimate) and the
 adaptive step of section "Adaptive time step": the error of a step is
 eps = max over cells |tau_high - tau_low| dt, compared with MaxErr and used to
 rescale dt with a headroom of 0.8.  Classical fixed-step RK4 is not among the
@@ -47,7 +48,15 @@ DP45 = {  # Dormand-Prince 5(4), FSAL
     "order_low": 4,
 }
 
-SOLVERS = {"rk23": BS23, "rk45": DP45}
+RK12 = {  # Heun with the Euler step as error estimate; not first-same-as-last
+    "a": [[F(1)]],
+    "b": [F(1, 2), F(1, 2)],
+    "bstar": [F(1), F(0)],
+    "order_low": 1,
+    "fsal": False,
+}
+
+SOLVERS = {"rk12": RK12, "rk23": BS23, "rk45": DP45}
 
 
 def normalize(m):
@@ -113,12 +122,25 @@ class Integrator:
         dt = self.dt
         if t_end is not None and self.t + dt > t_end:
             dt = t_end - self.t
-        m_new, k_last, eps = embedded_step(self.f, self.m, self.k1, dt, self.tab)
+        if self.tab.get("fsal", True):
+            m_new, k_last, eps = embedded_step(self.f, self.m, self.k1, dt, self.tab)
+        else:
+            k = [self.k1]
+            for row in self.tab["a"]:
+                k.append(self.f(self.m + dt * sum(float(a) * kj for a, kj in zip(row, k) if a != 0)))
+            m_new = self.m + dt * sum(float(b) * kj for b, kj in zip(self.tab["b"], k))
+            e = [float(b - bs) for b, bs in zip(self.tab["b"], self.tab["bstar"])]
+            diff = sum(ej * kj for ej, kj in zip(e, k) if ej != 0)
+            eps = dt * float(np.max(np.sqrt(np.sum(diff * diff, axis=0))))
+            k_last = None
         self.nevals += len(self.tab["a"])
         fac = step_factor(eps, self.max_err, self.tab["order_low"], self.headroom)
         accepted = eps <= self.max_err
         if accepted:
             self.m = normalize(m_new)
+            if k_last is None:  # no first-same-as-last: the next first stage is evaluated afresh
+                k_last = self.f(self.m)
+                self.nevals += 1
             self.k1 = k_last
             self.t += dt
             self.nsteps += 1
