@@ -200,15 +200,23 @@ int mm_rk4_step(mm_ctx *c, float *m_dev, double dt, int32_t precess);
 int mm_rk45_step(mm_ctx *c, float *m_dev, double *t, double *dt, const mm_solver_opts *o,
                  int32_t *accepted, double *err);
 
-/* Same for the Bogacki-Shampine 3(2) pair (RK32 of the paper; exponent 1/3). */
+/* Same for the Bogacki-Shampine 3(2) pair (RK32 of the paper; exponent 1/3).
+ * Both return MM_EUNSUPPORTED while a temperature is set. */
 int mm_rk23_step(mm_ctx *c, float *m_dev, double *t, double *dt, const mm_solver_opts *o,
                  int32_t *accepted, double *err);
 
-/* Advance with solver 45 (Dormand-Prince) or 23 (Bogacki-Shampine) until
- * t_end (the last step is clipped to land on it) or until max_attempts
- * attempts, with the step controller running on the device (no host
- * round trip per step).  *t and *dt are read and updated.  stats may be NULL.
- * Returns MM_ESTEP / MM_ENONFINITE if the run stopped on those conditions. */
+/* Advance with solver 45 (Dormand-Prince), 23 (Bogacki-Shampine) or 12 (Heun,
+ * RK12 of section "Dynamics": k1 at m, k2 at m + dt k1, new state
+ * m + dt (k1 + k2)/2, Euler error estimate, exponent 1/2; two torque
+ * evaluations per attempt, no first-same-as-last) until t_end (the last step
+ * is clipped to land on it) or until max_attempts attempts, with the step
+ * controller running on the device (no host round trip per step).  While a
+ * temperature is set (mm_set_temperature) only solver 12 runs, at the fixed
+ * step *dt (section "Thermal fluctuations": every step accepted; max_err and
+ * the step limits are ignored) with the thermal field of each step added to
+ * B_eff in both stages; the other solvers return MM_EUNSUPPORTED.  *t and *dt
+ * are read and updated.  stats may be NULL.  Returns MM_ESTEP / MM_ENONFINITE
+ * if the run stopped on those conditions. */
 int mm_run(mm_ctx *c, float *m_dev, int32_t solver, double t_end, int64_t max_attempts,
            double *t, double *dt, const mm_solver_opts *o, mm_run_stats *stats);
 
@@ -233,6 +241,28 @@ int mm_max_torque(mm_ctx *c, const float *m_dev, int32_t precess, double *out);
 int mm_solver_reset(mm_ctx *c);
 
 int mm_get_info(mm_ctx *c, mm_info *info);
+
+/* Temperature (section "Thermal fluctuations"): temp_k[256] in kelvin per
+ * region (host array; NULL = 0 K everywhere), and the seed of the generator.
+ * Each cell then carries the thermal field
+ *   B_therm = eta sqrt(2 alpha kB T / (Msat gamma_LL dV dt))
+ * (the paper's form with B_sat = mu0 Msat), eta three standard normal numbers
+ * per cell and step, held over the stages of a step and drawn anew for each
+ * accepted step, from Philox4x32-10 (Salmon et al., SC 2011): counter (cell
+ * index, step mod 2^32, step div 2^32, 0), key (seed mod 2^32, seed div 2^32),
+ * 32-bit outputs x -> u = (floor(x / 2^8) + 1/2) / 2^24, Box-Muller
+ * eta_x, eta_y = sqrt(-2 ln u0) (cos, sin)(2 pi u1),
+ * eta_z = sqrt(-2 ln u2) cos(2 pi u3).  step counts the steps accepted since
+ * this call (which resets it).  The field enters mm_run with solver 12 only
+ * (relax and the single-step calls run at 0 K or refuse).  Allocates the
+ * field buffer the first time.  Synchronises.  MM_EINVAL for a negative or
+ * non-finite temperature. */
+int mm_set_temperature(mm_ctx *c, const double *temp_k, uint64_t seed);
+
+/* The thermal field of generator step `step` with time step dt into out_dev
+ * ([3][nz][ny][nx] floats, T), as the Heun steps take it.  MM_ESTATE before
+ * mm_set_temperature. */
+int mm_thermal_field(mm_ctx *c, double dt, uint64_t step, float *out_dev);
 
 /* Diagnostics.  mm_demag_tensor_dump writes the FP64 real-space tensor N(d)
  * for d = (i dx, j dy, k dz), 0 <= i < nx etc., as [6][nz][ny][nx] doubles

@@ -22,7 +22,7 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 SOURCES = ["kernels_fft.hip", "kernels_mfma.hip", "kernels_batch.hip", "kernels_local.hip", "kernels_demag.hip",
-           "kernels_sno.hip", "mm_api.cpp", "mm_batch.cpp", "mm_sno.cpp"]
+           "kernels_sno.hip", "kernels_thermal.hip", "mm_api.cpp", "mm_batch.cpp", "mm_sno.cpp"]
 
 
 def _compile(src):

@@ -231,7 +231,8 @@ __device__ inline float3 epilogue(const FieldArgs& a, const Resolved& rs, const 
     const float3 ban1 = f3scale(L.a.y * um, u);
     const float3 ban2 = f3scale(L.a.z * um * um * um, u);
     const float3 bz = make_float3(L.c.x, L.c.y, L.c.z);
-    const float3 B = f3add(f3add(bd, bex), f3add(f3add(ban1, ban2), bz));
+    float3 B = f3add(f3add(bd, bex), f3add(f3add(ban1, ban2), bz));
+    if (flags & EPI_THERM) B = f3add(B, ld3o(a.bth, n, c4));
     if (flags & EPI_BEFF) st3o(a.beff, n, c4, B);
     if (flags & (EPI_TORQUE | EPI_MAXTQ | EPI_ERR)) {
         const float3 mxb = f3cross(m, B);

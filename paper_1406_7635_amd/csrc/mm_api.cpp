@@ -71,6 +71,13 @@ struct mm_ctx {
     float* bsur = nullptr;    // its prediction [3][ncell]
     float* bexact = nullptr;  // the exact B_demag of the last stage [3][ncell]
     long long sur_steps = 0;  // accepted steps taken with surrogate stages
+    // thermal field (section "Thermal fluctuations")
+    double temp[NREG] = {};   // temperature per region (K)
+    bool therm_on = false;    // some magnetic region has T > 0
+    unsigned long long seed = 0;
+    float* sigma = nullptr;   // [256] sqrt(2 alpha kB T / (Msat gamma dV)), FP32
+    float* bth = nullptr;     // thermal field of the current step [3][ncell]
+    mm_params* hparams = nullptr;  // host copy of the parameters
 };
 
 namespace {
@@ -83,9 +90,11 @@ hipError_t dalloc(mm_ctx* c, void** p, size_t bytes) {
 
 void free_all(mm_ctx* c) {
     void* ptrs[] = {c->region, c->params64, c->lut,      c->ptab,    c->tw,   c->spec,   c->khat, c->kbuf,
-                    c->ms,     c->ms2,      c->st,       c->partials, c->dft_tab, c->bsur, c->bexact, c->zker};
+                    c->ms,     c->ms2,      c->st,       c->partials, c->dft_tab, c->bsur, c->bexact, c->zker,
+                    c->sigma,  c->bth};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    delete c->hparams;
     if (c->hst) (void)hipHostFree(c->hst);
     for (auto& t : c->timing)
         for (auto& pr : t.ev) {
@@ -242,6 +251,26 @@ int run_xinv(mm_ctx* c, const FieldArgs& a, int* nblocks_out) {
 }
 
 // One field evaluation (section "Landau-Lifshitz torque": B_eff and torque).
+// Per-region prefactor of the thermal field, sqrt(2 alpha kB T / (Msat gamma dV))
+// (section "Thermal fluctuations", with B_sat = mu0 Msat), in FP64, stored FP32.
+int upload_sigma(mm_ctx* c) {
+    const double kb = 1.380649e-23;
+    const double gamma = c->hparams->gamma_ll != 0.0 ? c->hparams->gamma_ll : GAMMA_DEFAULT;
+    const double vol = c->dx * c->dy * c->dz;
+    float sig[NREG];
+    bool on = false;
+    for (int r = 0; r < NREG; ++r) {
+        const double ms = c->hparams->msat[r], al = c->hparams->alpha[r], t = c->temp[r];
+        const double v = (ms > 0.0 && t > 0.0) ? sqrt(2.0 * al * kb * t / (ms * gamma * vol)) : 0.0;
+        sig[r] = (float)v;
+        on = on || sig[r] != 0.f;
+    }
+    c->therm_on = on;
+    MM_TRY(hipMemcpyAsync(c->sigma, sig, sizeof(sig), hipMemcpyHostToDevice, c->stream));
+    MM_TRY(hipStreamSynchronize(c->stream));
+    return MM_OK;
+}
+
 int run_field(mm_ctx* c, FieldArgs& a, int* nblocks_out) {
     hipStream_t s = c->stream;
     if (c->demag_on) {
@@ -385,6 +414,43 @@ int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done
     return MM_OK;
 }
 
+// One Heun (RK12) attempt (section "Dynamics"; with the thermal field,
+// section "Thermal fluctuations"): the thermal field of the step, k1 at m0, k2
+// at m0 + dt k1 with the Euler error estimate, the new state
+// m0 + dt (k1 + k2)/2 into the stage buffer (before the controller changes
+// dt), the controller, and the commit of an accepted state.  The thermal
+// field is held over both stages; its generator step advances per accepted
+// step.
+int heun_attempt(mm_ctx* c, float* m, int precess, bool check_done) {
+    hipStream_t s = c->stream;
+    const bool th = c->therm_on;
+    if (th)
+        MM_TRY(launch_thermal(c->ncell, c->region, c->sigma, c->seed, c->st, 1, 0, 0.0, check_done ? 1 : 0, c->bth,
+                              s));
+    FieldArgs a0 = base_args(c, m);
+    a0.sd.nk = 0;
+    a0.sd.out_k = 0;
+    a0.flags = EPI_TORQUE | (precess ? EPI_PRECESS : 0) | (check_done ? EPI_CHECK_DONE : 0) | (th ? EPI_THERM : 0);
+    a0.bth = c->bth;
+    MM_CHECK(run_field(c, a0, nullptr));
+    FieldArgs a1 = stage_args(c, m, RK12, 1, precess, check_done);
+    a1.flags |= th ? EPI_THERM : 0;
+    a1.bth = c->bth;
+    MM_CHECK(run_field(c, a1, nullptr));
+    FieldArgs f = base_args(c, m);
+    f.sd.nk = 2;
+    f.sd.kidx[0] = 0;
+    f.sd.kidx[1] = 1;
+    f.sd.a[0] = 0.5f;
+    f.sd.a[1] = 0.5f;
+    f.flags = check_done ? EPI_CHECK_DONE : 0;
+    MM_TRY(launch_combine(f, s));
+    MM_TRY(launch_controller(c->st, 0, 2, check_done ? 1 : 0, s));
+    FieldArgs fin = base_args(c, m);
+    MM_TRY(launch_finalize(fin, s));
+    return MM_OK;
+}
+
 bool need_first(mm_ctx* c, const float* m, int precess, int solver) {
     return !(c->fsal_valid && c->fsal_m == m && c->fsal_precess == precess && c->fsal_solver == solver);
 }
@@ -393,6 +459,7 @@ int embedded_step(mm_ctx* c, float* m, const Tableau& tb, int solver, double* t,
                   const mm_solver_opts* o, int32_t* accepted, double* err) {
     if (!c || !m || !t || !dt) return MM_EINVAL;
     if (!(isfinite(*t) && finite_pos(*dt))) return MM_EINVAL;
+    if (c->therm_on) return MM_EUNSUPPORTED;  // the thermal field needs Heun's fixed step
     const Opts op = get_opts(o);
     const bool first = need_first(c, m, op.precess, solver);
     MM_TRY(launch_set_state(c->st, *t, *dt, INFINITY, op.max_err, op.headroom, op.dt_min, op.dt_max,
@@ -551,8 +618,13 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
         if (e == hipSuccess) e = configure_colm();
         if (e == hipSuccess)
             e = launch_set_state(c->st, 0.0, 1e-14, INFINITY, 1e-5, 0.8, 0.0, 0.0, 4, 1, 1, 0, c->stream);
+        if (e == hipSuccess) e = launch_set_therm_step(c->st, 0, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         st = map_err(e);
+    }
+    if (st == MM_OK) {
+        c->hparams = new (std::nothrow) mm_params(*p);
+        if (!c->hparams) st = MM_ENOMEM;
     }
     if (st != MM_OK) {
         free_all(c);
@@ -600,8 +672,34 @@ int mm_set_params(mm_ctx* c, const mm_params* p) {
     MM_TRY(hipMemcpyAsync(c->params64, p, sizeof(mm_params), hipMemcpyHostToDevice, c->stream));
     MM_TRY(launch_prepare_tables(c->params64, c->lut, c->ptab, c->stream));
     MM_TRY(hipStreamSynchronize(c->stream));
+    *c->hparams = *p;
+    if (c->sigma) MM_CHECK(upload_sigma(c));
     c->fsal_valid = false;
     return MM_OK;
+}
+
+int mm_set_temperature(mm_ctx* c, const double* temp_k, uint64_t seed) {
+    if (!c) return MM_EINVAL;
+    if (temp_k)
+        for (int r = 0; r < NREG; ++r)
+            if (!(temp_k[r] >= 0.0) || !isfinite(temp_k[r])) return MM_EINVAL;
+    for (int r = 0; r < NREG; ++r) c->temp[r] = temp_k ? temp_k[r] : 0.0;
+    c->seed = seed;
+    if (!c->sigma) {
+        MM_TRY(dalloc(c, (void**)&c->sigma, NREG * sizeof(float)));
+        MM_TRY(dalloc(c, (void**)&c->bth, (size_t)3 * c->ncell * sizeof(float)));
+    }
+    MM_CHECK(upload_sigma(c));
+    MM_TRY(launch_set_therm_step(c->st, 0, c->stream));
+    MM_TRY(hipStreamSynchronize(c->stream));
+    return MM_OK;
+}
+
+int mm_thermal_field(mm_ctx* c, double dt, uint64_t step, float* out_dev) {
+    if (!c || !out_dev || !finite_pos(dt)) return MM_EINVAL;
+    if (!c->sigma) return MM_ESTATE;
+    return map_err(launch_thermal(c->ncell, c->region, c->sigma, c->seed, c->st, 0, step, dt, 0, out_dev,
+                                  c->stream));
 }
 
 int mm_set_demag(mm_ctx* c, int32_t enable) {
@@ -673,17 +771,25 @@ int mm_rk23_step(mm_ctx* c, float* m_dev, double* t, double* dt, const mm_solver
 int mm_run(mm_ctx* c, float* m_dev, int32_t solver, double t_end, int64_t max_attempts, double* t, double* dt,
            const mm_solver_opts* o, mm_run_stats* stats) {
     if (!c || !m_dev || !t || !dt || max_attempts < 0) return MM_EINVAL;
-    if (solver != 45 && solver != 23) return MM_EINVAL;
+    if (solver != 45 && solver != 23 && solver != 12) return MM_EINVAL;
     if (!(isfinite(*t) && finite_pos(*dt)) || isnan(t_end)) return MM_EINVAL;
-    const Tableau& tb = solver == 45 ? DP45 : BS23;
-    const Opts op = get_opts(o);
+    // with the thermal field only Heun runs, at a fixed step
+    if (c->therm_on && solver != 12) return MM_EUNSUPPORTED;
+    const bool heun = solver == 12;
+    const Tableau& tb = solver == 45 ? DP45 : (solver == 23 ? BS23 : RK12);
+    Opts op = get_opts(o);
     double dt0 = *dt;
     if (isfinite(t_end) && *t + dt0 > t_end) dt0 = t_end - *t;
     if (!(dt0 > 0.0)) {  // nothing to do
         if (stats) memset(stats, 0, sizeof(*stats));
         return MM_OK;
     }
-    const bool first = need_first(c, m_dev, op.precess, solver);
+    if (heun && c->therm_on) {  // every step accepted, dt kept
+        op.max_err = INFINITY;
+        op.dt_min = 0.0;
+        op.dt_max = dt0;
+    }
+    const bool first = !heun && need_first(c, m_dev, op.precess, solver);
     MM_TRY(launch_set_state(c->st, *t, dt0, t_end, op.max_err, op.headroom, op.dt_min, op.dt_max, tb.order_low,
                             1, first ? 1 : 0, 0, c->stream));
     long long extra = 0;
@@ -703,7 +809,12 @@ int mm_run(mm_ctx* c, float* m_dev, int32_t solver, double t_end, int64_t max_at
         long long nb = max_attempts - done_attempts;
         if (nb > per) nb = per;
         if (c->sur_active) nb = 1;
-        for (long long i = 0; i < nb; ++i) MM_CHECK(attempt(c, m_dev, tb, op.precess, true));
+        for (long long i = 0; i < nb; ++i) {
+            if (heun)
+                MM_CHECK(heun_attempt(c, m_dev, op.precess, true));
+            else
+                MM_CHECK(attempt(c, m_dev, tb, op.precess, true));
+        }
         done_attempts += nb;
         MM_CHECK(sync_state(c));
         if (c->sur_active) {
@@ -717,7 +828,7 @@ int mm_run(mm_ctx* c, float* m_dev, int32_t solver, double t_end, int64_t max_at
         if (c->hst->done) break;
     }
     c->sur_active = false;
-    c->fsal_valid = true;
+    c->fsal_valid = !heun;  // Heun leaves no first-stage torque of the new state
     c->fsal_m = m_dev;
     c->fsal_precess = op.precess;
     c->fsal_solver = solver;

@@ -42,6 +42,9 @@ struct DevState {
     double sur_err;             // their ratio for the last checked attempt
     int sur_fail;               // the last attempt exceeded the tolerance: rejected, dt kept
     long long sur_fallbacks;
+    // steps accepted since the thermal generator was seeded: the step index of
+    // its counter (not reset by set_state)
+    unsigned long long therm_step;
 };
 
 // One torque evaluation inside a Runge-Kutta step.
@@ -64,7 +67,8 @@ enum EpiFlags {
     EPI_ENERGY = 32,     // per-workgroup FP64 energy partial sums
     EPI_PRECESS = 64,    // keep the m x B term of the torque
     EPI_HAS_DEMAG = 128, // the pass carries a demag field (else B_demag = 0)
-    EPI_CHECK_DONE = 256 // device-controlled run: skip the work once the run is done
+    EPI_CHECK_DONE = 256, // device-controlled run: skip the work once the run is done
+    EPI_THERM = 512       // add the thermal field of the step (bth) to B_eff
 };
 
 struct FieldArgs {
@@ -90,6 +94,7 @@ struct FieldArgs {
     float cellvol;
     int flags;
     int pbc;                      // periodic axes: bit 0 x, bit 1 y, bit 2 z (exchange wraps around)
+    const float* bth;             // thermal field of the current step [3][ncell] (EPI_THERM)
 };
 
 struct ColArgs {
@@ -242,6 +247,13 @@ hipError_t launch_reset_accum(DevState* st, hipStream_t s);
 hipError_t launch_controller(DevState* st, int last_k, int evals, int check_done, hipStream_t s);
 hipError_t launch_finalize(const FieldArgs& a, hipStream_t s);
 hipError_t launch_final_combine(const FieldArgs& a, hipStream_t s);
+// thermal field (kernels_thermal.hip): bth = eta sigma[r] / sqrt(dt) for the
+// generator step `step` and time step dt, or (from_state) for the state's
+// therm_step and dt; sigma[256] = sqrt(2 alpha kB T / (Msat gamma dV)) (FP32)
+hipError_t launch_thermal(long long ncell, const uint8_t* region, const float* sigma, unsigned long long seed,
+                          const DevState* st, int from_state, unsigned long long step, double dt, int check_done,
+                          float* bth, hipStream_t s);
+hipError_t launch_set_therm_step(DevState* st, unsigned long long step, hipStream_t s);
 hipError_t launch_reduce_energy(const double* partials, int nblocks, DevState* st, double cellvol,
                                 hipStream_t s);
 hipError_t launch_exchange_dump(const FieldArgs& a, float* out, hipStream_t s);

@@ -80,6 +80,7 @@ __device__ inline void controller_update(DevState* st, int last_k, int evals, in
     if (acc) {
         st->t = clipped ? st->t_end : st->t + dt;
         st->steps += 1;
+        st->therm_step += 1;
         if (last_k > 0) {
             const int tmp = st->perm[0];
             st->perm[0] = st->perm[last_k];

@@ -36,6 +36,18 @@ inline const Tableau BS23 = {
      {0, 0, 0, 0, 0, 0}},
     {2.0 / 9 - 7.0 / 24, 1.0 / 3 - 1.0 / 4, 4.0 / 9 - 1.0 / 3, -1.0 / 8, 0, 0, 0}};
 
+// Heun's method with the Euler step as error estimate (RK12); not first same
+// as last: the new state m0 + dt (k1 + k2)/2 is formed after the stages.
+inline const Tableau RK12 = {
+    2, 1,
+    {{0, 0, 0, 0, 0, 0},
+     {1.0, 0, 0, 0, 0, 0},
+     {0, 0, 0, 0, 0, 0},
+     {0, 0, 0, 0, 0, 0},
+     {0, 0, 0, 0, 0, 0},
+     {0, 0, 0, 0, 0, 0},
+     {0, 0, 0, 0, 0, 0}},
+    {1.0 / 2 - 1.0, 1.0 / 2, 0, 0, 0, 0, 0}};
 
 // Stage s of tableau tb: combine over the non-zero a_sj, derivative into
 // logical buffer s; the last stage also lists the error weights.  Returns

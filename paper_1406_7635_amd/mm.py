@@ -55,6 +55,8 @@ EXPORTS = {
     "mm_demag_kernel_init": (c_int32, [c_void_p]),
     "mm_set_params": (c_int32, [c_void_p, ctypes.POINTER(Params)]),
     "mm_set_demag": (c_int32, [c_void_p, c_int32]),
+    "mm_set_temperature": (c_int32, [c_void_p, c_void_p, ctypes.c_uint64]),
+    "mm_thermal_field": (c_int32, [c_void_p, c_double, ctypes.c_uint64, c_void_p]),
     "mm_beff": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mm_llg_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32]),
     "mm_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
@@ -264,6 +266,20 @@ class Context:
         _check(load().mm_run(self._h, _ptr(self._vec(m)), int(solver), float(t_end), int(max_attempts),
                              ctypes.byref(t_), ctypes.byref(dt_), ctypes.byref(o), ctypes.byref(st)), "mm_run")
         return t_.value, dt_.value, {k: getattr(st, k) for k, _ in RunStats._fields_}
+
+    def set_temperature(self, temp, seed=0):
+        """Temperature in K: a scalar (every region) or 256 values per region;
+        seed of the thermal generator (resets its step counter)."""
+        t = np.broadcast_to(np.asarray(temp, dtype=np.float64), (256,)).copy()
+        self._temp = t
+        _check(load().mm_set_temperature(self._h, t.ctypes.data_as(c_void_p), int(seed) & ((1 << 64) - 1)),
+               "mm_set_temperature")
+
+    def thermal_field(self, dt, step):
+        """The thermal field [3, nz, ny, nx] (T) of generator step `step` at time step dt."""
+        out = self.new_field()
+        _check(load().mm_thermal_field(self._h, float(dt), int(step), _ptr(out)), "mm_thermal_field")
+        return out
 
     def relax(self, m, max_err=1e-5, min_max_err=1e-9, max_steps=100000):
         e, tq, n = c_double(), c_double(), c_int64()

@@ -1,0 +1,170 @@
+"""Thermal field and Heun's method on the GPU (section "Thermal fluctuations",
+section "Dynamics" RK12), against the FP64 oracle and closed forms.
+
+The generator is counter-based, so the GPU's field of a step equals the
+oracle's element by element (FP32 transcendental functions against FP64),
+and a finite-temperature Heun trajectory can be compared with the oracle's
+deterministically.  The statistics are checked against the Boltzmann
+equilibrium (Langevin function) and the paper's own verification, the
+Arrhenius switching rate of uniaxial macrospins (Eq. eqSwitch, figure
+figSwitch) on the paper's 512 x 512 ensemble of 10 nm particles.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import integrate as ointegrate
+from oracle import thermal as othermal
+from oracle.constants import GAMMA_LL, KB
+from paper_1406_7635_amd import mm, synth
+from tests.gpu_helpers import log, make_pair, rel_inf, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _temps(pairs):
+    t = np.zeros(256)
+    for r, v in pairs:
+        t[r] = v
+    return t
+
+
+def test_thermal_field_matches_oracle(gpu):
+    case = synth.random_problem((37, 21, 3), (2e-9, 3e-9, 2.5e-9), seed=5, nregions=4, vacuum=True)
+    ctx, prob, _ = make_pair(case, demag=False)
+    temp = _temps([(0, 300.0), (1, 0.0), (2, 77.0), (3, 1000.0)])
+    seed = 0x123456789ABCDEF
+    ctx.set_temperature(temp, seed)
+    for step, dt in ((0, 1e-13), (1, 1e-13), (12345, 3e-14), ((1 << 32) + 7, 1e-12)):
+        got = to_np(ctx.thermal_field(dt, step))
+        ref = othermal.thermal_field(case["region"], case["params"], temp, case["cell"], dt, step, seed)
+        err = rel_inf(got, ref)
+        log("thermal field step", step, "rel", err)
+        assert err < 1e-5
+        assert np.all(got[:, case["region"] == 1] == 0)
+    ctx.close()
+
+
+def test_heun_adaptive_matches_oracle(gpu):
+    case = synth.vortex_film(seed=2, n=32)
+    case["params"]["alpha"][0] = 0.1
+    ctx, prob, m = make_pair(case)
+    t_end = 5e-12
+    t, dt, st = ctx.run(m, t_end, dt=1e-14, solver=12, opts=mm.solver_opts(max_err=1e-5))
+    assert t == pytest.approx(t_end, rel=1e-12)
+    assert st["evals"] == 2 * (st["steps"] + st["rejects"])
+    it = ointegrate.Integrator(prob.torque, case["m0"], "rk12", dt=1e-14, max_err=1e-5)
+    it.run(t_end)
+    err = np.max(np.abs(to_np(m) - it.m))
+    log("heun steps", st["steps"], "rejects", st["rejects"], "oracle", it.nsteps, it.nrejects, "max |dm|", err)
+    assert err < 1e-3
+    ctx.close()
+
+
+def test_heun_thermal_trajectory_matches_oracle(gpu):
+    """A finite-temperature film (demag, exchange, anisotropy) for 30 fixed
+    steps: the same random field on both sides, so the trajectories agree;
+    and 15 + 15 steps in two calls equal 30 in one (the generator's step
+    counter carries over)."""
+    import torch
+
+    case = synth.random_problem((24, 20, 1), (3e-9, 3e-9, 3e-9), seed=8, nregions=2)
+    ctx, prob, m = make_pair(case)
+    temp = _temps([(0, 300.0), (1, 150.0)])
+    dt = 5e-14
+    ctx.set_temperature(temp, 42)
+    m2 = m.clone()
+    t, _, st = ctx.run(m, 30 * dt * (1 + 1e-9), dt=dt, solver=12, max_attempts=30)
+    assert st["steps"] == 30 and st["rejects"] == 0
+    ref = othermal.run_thermal(prob, case["m0"], dt, 30, temp, seed=42)
+    err = np.max(np.abs(to_np(m) - ref))
+    log("thermal heun 30 steps: max |dm|", err)
+    assert err < 1e-4
+    ctx.set_temperature(temp, 42)
+    ctx.run(m2, 1.0, dt=dt, solver=12, max_attempts=15)
+    ctx.run(m2, 1.0, dt=dt, solver=12, max_attempts=15)
+    assert torch.equal(m, m2)
+    ctx.close()
+
+
+def test_thermal_refusals(gpu):
+    case = synth.random_problem((16, 16, 1), (2e-9, 2e-9, 2e-9), seed=1)
+    ctx, _, m = make_pair(case)
+    with pytest.raises(mm.MMError):
+        ctx.thermal_field(1e-13, 0)          # no temperature yet
+    with pytest.raises(mm.MMError):
+        ctx.set_temperature(-1.0, 0)
+    ctx.set_temperature(300.0, 1)
+    for solver in (45, 23):
+        with pytest.raises(mm.MMError):
+            ctx.run(m, 1e-12, solver=solver)
+    with pytest.raises(mm.MMError):
+        ctx.rk45_step(m, 0.0, 1e-14)
+    ctx.set_temperature(0.0, 1)                # back to 0 K: every solver again
+    ctx.run(m, 1e-13, solver=45)
+    ctx.close()
+
+
+def _free_spins(n, msat, alpha, cell, bext=(0.0, 0.0, 0.0), ku1=0.0):
+    params = synth.material(msat, 0.0, alpha=alpha, ku1=ku1, anis_u=(0.0, 0.0, 1.0), bext=bext)
+    return mm.Context((n, n, 1), (cell,) * 3, np.zeros((1, n, n), np.uint8), params, demag=False)
+
+
+def test_boltzmann_equilibrium_langevin(gpu):
+    """65536 free macrospins in 0.05 T stay in the Boltzmann distribution:
+    <m_z> = coth x - 1/x (x = Msat V B / kB T = 3)."""
+    import torch
+
+    n, msat, b, alpha, cell, x = 256, 8e5, 0.05, 0.5, 5e-9, 3.0
+    ctx = _free_spins(n, msat, alpha, cell, bext=(0.0, 0.0, b))
+    ctx.set_temperature(msat * cell ** 3 * b / (x * KB), 7)
+    rng = np.random.Generator(np.random.PCG64(3))
+    u = rng.random((n, n))
+    ct = 1.0 + np.log1p(-u * (1.0 - math.exp(-2.0 * x))) / x
+    ph = 2 * math.pi * rng.random((n, n))
+    st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
+    m = torch.from_numpy(np.stack([st * np.cos(ph), st * np.sin(ph), ct])[:, None].astype(np.float32)).cuda()
+    dt = 2e-13
+    tau = (1 + alpha ** 2) / (alpha * GAMMA_LL * b)
+    t, _, _ = ctx.run(m, tau, dt=dt, solver=12)
+    vals = []
+    for k in range(20):
+        t, _, _ = ctx.run(m, t + tau / 10, t=t, dt=dt, solver=12)
+        vals.append(float(m[2].double().mean()))
+    mz = float(np.mean(vals))
+    lang = 1.0 / math.tanh(x) - 1.0 / x
+    log("langevin: <m_z> %.4f expected %.4f" % (mz, lang))
+    assert mz == pytest.approx(lang, abs=0.01)
+    ctx.close()
+
+
+def test_arrhenius_switching_rate(gpu):
+    """The paper's verification (Eq. eqSwitch, figure figSwitch): 512 x 512
+    uncoupled 10 nm cubes, Msat 1 MA/m, alpha 0.1, Ku1 1e4 J/m^3 along z,
+    dt 1e-12 s, Heun; at KV/kT = 8 the population difference decays as
+    exp(-2 f t) with f = gamma alpha/(1+alpha^2) sqrt(8 Ku1^3 V/(2 pi Msat^2 kT))
+    exp(-KV/kT).  The formula is the high-barrier limit; the measured rate
+    must lie within 35 % of it (statistical error about 5 %)."""
+    import torch
+
+    n, msat, alpha, cell, ku = 512, 1e6, 0.1, 10e-9, 1e4
+    vol = cell ** 3
+    kt = ku * vol / 8.0
+    ctx = _free_spins(n, msat, alpha, cell, ku1=ku)
+    ctx.set_temperature(kt / KB, 2024)
+    m = torch.zeros((3, 1, n, n), dtype=torch.float32, device="cuda:0")
+    m[2] = 1.0
+    dt = 1e-12
+    t, _, _ = ctx.run(m, 10e-9, dt=dt, solver=12)              # equilibrium inside the well
+    mz1 = float(m[2].double().mean())
+    span = 0.2e-6
+    t, _, st = ctx.run(m, t + span, t=t, dt=dt, solver=12)
+    mz2 = float(m[2].double().mean())
+    f_meas = -math.log(mz2 / mz1) / (2 * span)
+    f_th = GAMMA_LL * alpha / (1 + alpha ** 2) * math.sqrt(8 * ku ** 3 * vol / (2 * math.pi * msat ** 2 * kt)) \
+        * math.exp(-ku * vol / kt)
+    log("arrhenius: <m_z> %.4f -> %.4f, f %.3e /s, Eq. eqSwitch %.3e /s (%d steps)" % (mz1, mz2, f_meas, f_th,
+                                                                                   st["steps"]))
+    assert abs(math.log(f_meas / f_th)) < math.log(1.35)
+    ctx.close()
