@@ -330,6 +330,49 @@ def grains_variant(steps, warmup):
             "dtype": "f32"}
 
 
+# algorithmic bytes per cell of one finite-temperature Heun step on a grid
+# without the magnetostatic term (float32 fields of 12 B, region 1 B):
+# thermal field (region, write 12), stage 1 (m, region, field, write k1),
+# stage 2 combine (m, k1, write m_s) and field (m_s, region, field, k1 for the
+# error estimate, write k2), new state (m, k1, k2, write m_s), commit (m_s,
+# write m)
+HEUN_THERMAL_BYTES_PER_CELL = 13 + 37 + 36 + 49 + 48 + 24
+
+
+def thermal_variant(steps, warmup):
+    """The paper's thermal-switching workload (figure figSwitch): 512 x 512
+    uncoupled 10 nm cubes, Msat 1 MA/m, alpha 0.1, Ku1 1e4 J/m^3 along z, no
+    demag, Heun at the fixed step 1e-12 s with Brown's thermal field at 90.5 K
+    (KV/kT = 8).  Throughput in field evaluations x cells per second (two per
+    step) and the local passes' algorithmic bytes."""
+    import torch
+
+    from paper_1406_7635_amd import mm, synth
+
+    n, cell, ku = 512, 10e-9, 1e4
+    params = synth.material(1e6, 0.0, alpha=0.1, ku1=ku, anis_u=(0.0, 0.0, 1.0))
+    ctx = mm.Context((n, n, 1), (cell,) * 3, np.zeros((1, n, n), np.uint8), params, demag=False)
+    ctx.set_temperature(ku * cell ** 3 / 8.0 / 1.380649e-23, 1)
+    m = torch.zeros((3, 1, n, n), dtype=torch.float32, device="cuda:0")
+    m[2] = 1.0
+    dt = 1e-12
+    t, _, _ = ctx.run(m, float("inf"), dt=dt, solver=12, max_attempts=warmup)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t, _, st = ctx.run(m, float("inf"), t=t, dt=dt, solver=12, max_attempts=steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ctx.close()
+    ncell = n * n
+    gbs = HEUN_THERMAL_BYTES_PER_CELL * ncell * steps / wall / 1e9
+    return {"value": ncell * st["evals"] / wall, "unit": "Beff evals*cells/s", "us_per_step": 1e6 * wall / steps,
+            "steps": st["steps"], "alg_bytes_per_step": HEUN_THERMAL_BYTES_PER_CELL * ncell, "alg_GBs": gbs,
+            "alg_frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "workload": "512x512 uncoupled 10 nm cubes, Msat 1e6, alpha 0.1, Ku1 1e4 (z), no demag; Heun, fixed "
+                        "dt 1e-12 s, thermal field at KV/kT = 8 (90.5 K)",
+            "dtype": "f32"}
+
+
 def surrogate_variant(steps, warmup):
     """The surrogate workload: 256 x 256 x 1 film of 4 nm cells (Msat 8e5,
     Aex 1.3e-11, alpha 0.01), trained weights.  Reports the surrogate's
@@ -410,6 +453,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate variant")
     ap.add_argument("--no-grains", action="store_true", help="skip the 3D grain-workload variant")
     ap.add_argument("--no-sweep", action="store_true", help="skip the n x n x 1 size sweep")
+    ap.add_argument("--no-thermal", action="store_true", help="skip the thermal-switching (Heun) variant")
     ap.add_argument("--grains-only", action="store_true",
                     help="only the 3D grain-workload variant (one JSON line; for profiling)")
     ap.add_argument("--surrogate-only", action="store_true",
@@ -514,6 +558,8 @@ def main():
         out["variants"]["grains"] = grains_variant(max(5, args.steps // 20), max(2, args.warmup // 10))
     if not args.no_sweep:
         out["variants"]["size_sweep"] = size_sweep()
+    if not args.no_thermal:
+        out["variants"]["thermal"] = thermal_variant(max(200, args.steps * 10), max(20, args.warmup))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     else:
