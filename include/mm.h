@@ -259,6 +259,17 @@ int mm_get_info(mm_ctx *c, mm_info *info);
  * non-finite temperature. */
 int mm_set_temperature(mm_ctx *c, const double *temp_k, uint64_t seed);
 
+/* Cubic magneto-crystalline anisotropy (section "Magneto-crystalline
+ * anisotropy"), per region: kc[256][3] = (Kc1, Kc2, Kc3) in J/m^3 and the axes
+ * c1[256][3], c2[256][3] (host arrays, normalised here; c3 = c1 x c2, so c1
+ * and c2 should be perpendicular).  Adds to B_eff, with a_i = c_i . m,
+ *   -2 Kc1/Msat sum_i a_i (a_j^2 + a_k^2) c_i - 2 Kc2/Msat sum_i a_i a_j^2 a_k^2 c_i
+ *   -4 Kc3/Msat sum_i a_i^3 (a_j^4 + a_k^4) c_i
+ * and to the anisotropy energy -1/4 M.B(Kc1) - 1/6 M.B(Kc2) - 1/8 M.B(Kc3).
+ * kc = NULL removes it.  Tables are rebuilt by mm_set_params (Msat).  Ensembles
+ * have no cubic term.  Synchronises. */
+int mm_set_cubic_anisotropy(mm_ctx *c, const double *kc, const double *c1, const double *c2);
+
 /* The thermal field of generator step `step` with time step dt into out_dev
  * ([3][nz][ny][nx] floats, T), as the Heun steps take it.  MM_ESTATE before
  * mm_set_temperature. */

@@ -99,6 +99,50 @@ def anisotropy_field_parts(m, region, params):
     return b1, b2
 
 
+def cubic_axes(params, region):
+    """(c1, c2, c3) per cell [3, ...]: the given axes normalised, c3 = c1 x c2
+    (section "Magneto-crystalline anisotropy", paragraph "Cubic")."""
+    c1 = np.asarray(params["anis_c1"], dtype=np.float64)
+    c2 = np.asarray(params["anis_c2"], dtype=np.float64)
+    n1 = np.linalg.norm(c1, axis=-1, keepdims=True)
+    n2 = np.linalg.norm(c2, axis=-1, keepdims=True)
+    c1 = np.where(n1 > 0, c1 / np.where(n1 > 0, n1, 1.0), 0.0)
+    c2 = np.where(n2 > 0, c2 / np.where(n2 > 0, n2, 1.0), 0.0)
+    c3 = np.cross(c1, c2)
+    return tuple(np.moveaxis(c[region], -1, 0) for c in (c1, c2, c3))
+
+
+def cubic_anisotropy_field_parts(m, region, params):
+    """Cubic anisotropy field split by constant (Kc1, Kc2, Kc3 parts), tesla,
+    as the paper's equation for B_anis writes it term by term:
+
+      -2 Kc1/Msat [((c2.m)^2 + (c3.m)^2)(c1.m) c1 + ((c1.m)^2 + (c3.m)^2)(c2.m) c2
+                   + ((c1.m)^2 + (c2.m)^2)(c3.m) c3]
+      -2 Kc2/Msat [(c2.m)^2 (c3.m)^2 (c1.m) c1 + (c1.m)^2 (c3.m)^2 (c2.m) c2
+                   + (c1.m)^2 (c2.m)^2 (c3.m) c3]
+      -4 Kc3/Msat [((c2.m)^4 + (c3.m)^4)(c1.m)^3 c1 + ((c1.m)^4 + (c3.m)^4)(c2.m)^3 c2
+                   + ((c1.m)^4 + (c2.m)^4)(c3.m)^3 c3]
+
+    params may lack the cubic keys ("kc" [256, 3], "anis_c1", "anis_c2"):
+    then all three parts are zero."""
+    m = np.asarray(m, dtype=np.float64)
+    if "kc" not in params:
+        z = np.zeros_like(m)
+        return z, z, z
+    c1, c2, c3 = cubic_axes(params, region)
+    msat = _lut(params, "msat", region)
+    inv = np.where(msat > 0, 1.0 / np.where(msat > 0, msat, 1.0), 0.0)
+    kc = np.moveaxis(np.asarray(params["kc"], dtype=np.float64)[region], -1, 0)
+    d1, d2, d3 = (np.sum(c * m, axis=0) for c in (c1, c2, c3))
+    b1 = -2.0 * kc[0] * inv * ((d2 ** 2 + d3 ** 2) * d1 * c1 + (d1 ** 2 + d3 ** 2) * d2 * c2
+                                + (d1 ** 2 + d2 ** 2) * d3 * c3)
+    b2 = -2.0 * kc[1] * inv * (d2 ** 2 * d3 ** 2 * d1 * c1 + d1 ** 2 * d3 ** 2 * d2 * c2
+                                + d1 ** 2 * d2 ** 2 * d3 * c3)
+    b3 = -4.0 * kc[2] * inv * ((d2 ** 4 + d3 ** 4) * d1 ** 3 * c1 + (d1 ** 4 + d3 ** 4) * d2 ** 3 * c2
+                                + (d1 ** 4 + d2 ** 4) * d3 ** 3 * c3)
+    return b1, b2, b3
+
+
 def zeeman_field(region, params):
     """Applied field B_ext of each cell's region (T), paper section "Landau-Lifshitz torque"."""
     b = np.moveaxis(np.asarray(params["bext"], dtype=np.float64)[region], -1, 0)
@@ -146,11 +190,15 @@ class Problem:
     def terms(self, m):
         """Dict of the field terms at m: demag, exch, anis1, anis2, zeeman (T)."""
         b1, b2 = anisotropy_field_parts(m, self.region, self.params)
+        c1, c2, c3 = cubic_anisotropy_field_parts(m, self.region, self.params)
         return {
             "demag": self.demag_field(m),
             "exch": exchange_field(m, self.region, self.params, self.cell, self.pbc),
             "anis1": b1,
             "anis2": b2,
+            "cubic1": c1,
+            "cubic2": c2,
+            "cubic3": c3,
             "zeeman": zeeman_field(self.region, self.params),
         }
 
@@ -158,7 +206,7 @@ class Problem:
         """Effective field (T); zero in cells with Msat = 0.  `extra` (e.g. the
         thermal field, section "Thermal fluctuations") is added as is."""
         t = self.terms(m)
-        b = t["demag"] + t["exch"] + t["anis1"] + t["anis2"] + t["zeeman"]
+        b = t["demag"] + t["exch"] + t["anis1"] + t["anis2"] + t["zeeman"] + t["cubic1"] + t["cubic2"] + t["cubic3"]
         if extra is not None:
             b = b + extra
         return b * self.magnetic
@@ -175,14 +223,18 @@ class Problem:
         """Energies (J) from the fields, paper Eqs. for E_demag, E_exch, E_anis.
 
         E = V sum[-1/2 M.B_demag - 1/2 M.B_exch - 1/2 M.B_anis(Ku1)
-                  - 1/4 M.B_anis(Ku2) - M.B_ext], summed with math.fsum."""
+                  - 1/4 M.B_anis(Ku2) - 1/4 M.B_anis(Kc1) - 1/6 M.B_anis(Kc2)
+                  - 1/8 M.B_anis(Kc3) - M.B_ext], summed with math.fsum (the
+        cubic weights: Eq. EanisCM)."""
         t = self.terms(m)
         M = magnetisation(m, self.region, self.params)
         vol = self.cell[0] * self.cell[1] * self.cell[2]
         dens = {
             "demag": -0.5 * np.sum(M * t["demag"], axis=0),
             "exch": -0.5 * np.sum(M * t["exch"], axis=0),
-            "anis": -0.5 * np.sum(M * t["anis1"], axis=0) - 0.25 * np.sum(M * t["anis2"], axis=0),
+            "anis": -0.5 * np.sum(M * t["anis1"], axis=0) - 0.25 * np.sum(M * t["anis2"], axis=0)
+            - 0.25 * np.sum(M * t["cubic1"], axis=0) - np.sum(M * t["cubic2"], axis=0) / 6.0
+            - 0.125 * np.sum(M * t["cubic3"], axis=0),
             "zeeman": -np.sum(M * t["zeeman"], axis=0),
         }
         e = {k: vol * math.fsum(v[self.magnetic].ravel()) for k, v in dens.items()}

@@ -233,6 +233,28 @@ __device__ inline float3 epilogue(const FieldArgs& a, const Resolved& rs, const 
     const float3 bz = make_float3(L.c.x, L.c.y, L.c.z);
     float3 B = f3add(f3add(bd, bex), f3add(f3add(ban1, ban2), bz));
     if (flags & EPI_THERM) B = f3add(B, ld3o(a.bth, n, c4));
+    float ecub = 0.f;  // cubic anisotropy energy density / Msat
+    if (a.cub) {
+        // cubic anisotropy (section "Magneto-crystalline anisotropy"): with
+        // a_i = c_i . m and s_i = a_i^2, B = sum_i g_i c_i where
+        // g_i = a_i [k1 (s_j + s_k) + k2 s_j s_k + k3 s_i (s_j^2 + s_k^2)]
+        // ({i, j, k} the three axes; k1 = -2 Kc1/Msat, k2 = -2 Kc2/Msat,
+        // k3 = -4 Kc3/Msat).  The energy -1/4 M.B(Kc1) - 1/6 M.B(Kc2)
+        // - 1/8 M.B(Kc3) uses m.B(Kc1) = 2 k1 (s1 s2 + s1 s3 + s2 s3),
+        // m.B(Kc2) = 3 k2 s1 s2 s3, m.B(Kc3) = 2 k3 (s1^2 s2^2 + s1^2 s3^2 + s2^2 s3^2).
+        const float4 p = a.cub[3 * r], q = a.cub[3 * r + 1], w = a.cub[3 * r + 2];
+        const float3 c1 = make_float3(p.x, p.y, p.z), c2 = make_float3(q.x, q.y, q.z),
+                     c3 = make_float3(w.x, w.y, w.z);
+        const float a1 = f3dot(c1, m), a2 = f3dot(c2, m), a3 = f3dot(c3, m);
+        const float s1 = a1 * a1, s2 = a2 * a2, s3 = a3 * a3;
+        const float g1 = a1 * (p.w * (s2 + s3) + q.w * s2 * s3 + w.w * s1 * (s2 * s2 + s3 * s3));
+        const float g2 = a2 * (p.w * (s1 + s3) + q.w * s1 * s3 + w.w * s2 * (s1 * s1 + s3 * s3));
+        const float g3 = a3 * (p.w * (s1 + s2) + q.w * s1 * s2 + w.w * s3 * (s1 * s1 + s2 * s2));
+        B = f3add(B, f3add(f3add(f3scale(g1, c1), f3scale(g2, c2)), f3scale(g3, c3)));
+        if (flags & EPI_ENERGY)
+            ecub = -(0.5f * p.w * (s1 * s2 + s1 * s3 + s2 * s3) + 0.5f * q.w * s1 * s2 * s3 +
+                     0.25f * w.w * (s1 * s1 * s2 * s2 + s1 * s1 * s3 * s3 + s2 * s2 * s3 * s3));
+    }
     if (flags & EPI_BEFF) st3o(a.beff, n, c4, B);
     if (flags & (EPI_TORQUE | EPI_MAXTQ | EPI_ERR)) {
         const float3 mxb = f3cross(m, B);
@@ -261,6 +283,7 @@ __device__ inline float3 epilogue(const FieldArgs& a, const Resolved& rs, const 
         acc.e[0] += -0.5 * dot(bd);
         acc.e[1] += -0.5 * dot(bex);
         acc.e[2] += -0.5 * dot(ban1) - 0.25 * dot(ban2);
+        acc.e[2] += ms * (double)ecub;
         acc.e[3] += -dot(bz);
     }
     return tq;

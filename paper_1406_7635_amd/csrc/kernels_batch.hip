@@ -94,6 +94,7 @@ __device__ inline FieldArgs member_field(const FieldArgs& b, const BMember& mb, 
     a.ncell = (long long)mb.nx * mb.ny * mb.nz;
     a.pbc = 0;                // ensemble members have open boundaries
     a.flags &= ~EPI_THERM;    // and no thermal field
+    a.cub = nullptr;          // nor cubic anisotropy
     const long long c = mb.cell_off, c3 = 3 * c;
     a.m0 = b.m0 + c3;
     a.ms = b.ms + c3;

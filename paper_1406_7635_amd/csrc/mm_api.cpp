@@ -78,6 +78,10 @@ struct mm_ctx {
     float* sigma = nullptr;   // [256] sqrt(2 alpha kB T / (Msat gamma dV)), FP32
     float* bth = nullptr;     // thermal field of the current step [3][ncell]
     mm_params* hparams = nullptr;  // host copy of the parameters
+    // cubic anisotropy (section "Magneto-crystalline anisotropy")
+    bool cub_on = false;
+    float4* cub = nullptr;    // [256][3] device table
+    double hkc[NREG][3] = {}, hc1[NREG][3] = {}, hc2[NREG][3] = {};
 };
 
 namespace {
@@ -91,7 +95,7 @@ hipError_t dalloc(mm_ctx* c, void** p, size_t bytes) {
 void free_all(mm_ctx* c) {
     void* ptrs[] = {c->region, c->params64, c->lut,      c->ptab,    c->tw,   c->spec,   c->khat, c->kbuf,
                     c->ms,     c->ms2,      c->st,       c->partials, c->dft_tab, c->bsur, c->bexact, c->zker,
-                    c->sigma,  c->bth};
+                    c->sigma,  c->bth,      c->cub};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete c->hparams;
@@ -130,6 +134,7 @@ FieldArgs base_args(mm_ctx* c, const float* m0) {
     a.partials = c->partials;
     a.cellvol = (float)(c->dx * c->dy * c->dz);
     a.pbc = (c->pbc[0] > 0 ? 1 : 0) | (c->pbc[1] > 0 ? 2 : 0) | (c->pbc[2] > 0 ? 4 : 0);
+    a.cub = c->cub_on ? c->cub : nullptr;
     return a;
 }
 
@@ -267,6 +272,37 @@ int upload_sigma(mm_ctx* c) {
     }
     c->therm_on = on;
     MM_TRY(hipMemcpyAsync(c->sigma, sig, sizeof(sig), hipMemcpyHostToDevice, c->stream));
+    MM_TRY(hipStreamSynchronize(c->stream));
+    return MM_OK;
+}
+
+// Cubic anisotropy table: c1, c2 normalised, c3 = c1 x c2, coefficients
+// -2 Kc1/Msat, -2 Kc2/Msat, -4 Kc3/Msat (FP64, stored FP32); zero for
+// non-magnetic regions.
+int upload_cubic(mm_ctx* c) {
+    float4 tab[NREG * 3];
+    bool on = false;
+    for (int r = 0; r < NREG; ++r) {
+        const double ms = c->hparams->msat[r];
+        double u[3], v[3], w[3];
+        const double nu = sqrt(c->hc1[r][0] * c->hc1[r][0] + c->hc1[r][1] * c->hc1[r][1] + c->hc1[r][2] * c->hc1[r][2]);
+        const double nv = sqrt(c->hc2[r][0] * c->hc2[r][0] + c->hc2[r][1] * c->hc2[r][1] + c->hc2[r][2] * c->hc2[r][2]);
+        for (int i = 0; i < 3; ++i) {
+            u[i] = nu > 0.0 ? c->hc1[r][i] / nu : 0.0;
+            v[i] = nv > 0.0 ? c->hc2[r][i] / nv : 0.0;
+        }
+        w[0] = u[1] * v[2] - u[2] * v[1];
+        w[1] = u[2] * v[0] - u[0] * v[2];
+        w[2] = u[0] * v[1] - u[1] * v[0];
+        const double inv = ms > 0.0 ? 1.0 / ms : 0.0;
+        const double k1 = -2.0 * c->hkc[r][0] * inv, k2 = -2.0 * c->hkc[r][1] * inv, k3 = -4.0 * c->hkc[r][2] * inv;
+        tab[3 * r] = make_float4((float)u[0], (float)u[1], (float)u[2], (float)k1);
+        tab[3 * r + 1] = make_float4((float)v[0], (float)v[1], (float)v[2], (float)k2);
+        tab[3 * r + 2] = make_float4((float)w[0], (float)w[1], (float)w[2], (float)k3);
+        on = on || k1 != 0.0 || k2 != 0.0 || k3 != 0.0;
+    }
+    c->cub_on = on;
+    MM_TRY(hipMemcpyAsync(c->cub, tab, sizeof(tab), hipMemcpyHostToDevice, c->stream));
     MM_TRY(hipStreamSynchronize(c->stream));
     return MM_OK;
 }
@@ -674,6 +710,7 @@ int mm_set_params(mm_ctx* c, const mm_params* p) {
     MM_TRY(hipStreamSynchronize(c->stream));
     *c->hparams = *p;
     if (c->sigma) MM_CHECK(upload_sigma(c));
+    if (c->cub) MM_CHECK(upload_cubic(c));
     c->fsal_valid = false;
     return MM_OK;
 }
@@ -692,6 +729,22 @@ int mm_set_temperature(mm_ctx* c, const double* temp_k, uint64_t seed) {
     MM_CHECK(upload_sigma(c));
     MM_TRY(launch_set_therm_step(c->st, 0, c->stream));
     MM_TRY(hipStreamSynchronize(c->stream));
+    return MM_OK;
+}
+
+int mm_set_cubic_anisotropy(mm_ctx* c, const double* kc, const double* c1, const double* c2) {
+    if (!c) return MM_EINVAL;
+    if (kc && (!c1 || !c2)) return MM_EINVAL;
+    for (int r = 0; r < NREG; ++r)
+        for (int i = 0; i < 3; ++i) {
+            c->hkc[r][i] = kc ? kc[3 * r + i] : 0.0;
+            c->hc1[r][i] = kc ? c1[3 * r + i] : 0.0;
+            c->hc2[r][i] = kc ? c2[3 * r + i] : 0.0;
+            if (!isfinite(c->hkc[r][i]) || !isfinite(c->hc1[r][i]) || !isfinite(c->hc2[r][i])) return MM_EINVAL;
+        }
+    if (!c->cub) MM_TRY(dalloc(c, (void**)&c->cub, (size_t)NREG * 3 * sizeof(float4)));
+    MM_CHECK(upload_cubic(c));
+    c->fsal_valid = false;
     return MM_OK;
 }
 

@@ -95,6 +95,9 @@ struct FieldArgs {
     int flags;
     int pbc;                      // periodic axes: bit 0 x, bit 1 y, bit 2 z (exchange wraps around)
     const float* bth;             // thermal field of the current step [3][ncell] (EPI_THERM)
+    // cubic anisotropy per region (null: none): 3 float4 per region,
+    // (c1, -2 Kc1/Msat), (c2, -2 Kc2/Msat), (c3, -4 Kc3/Msat)
+    const float4* cub;
 };
 
 struct ColArgs {

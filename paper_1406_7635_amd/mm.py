@@ -57,6 +57,7 @@ EXPORTS = {
     "mm_set_demag": (c_int32, [c_void_p, c_int32]),
     "mm_set_temperature": (c_int32, [c_void_p, c_void_p, ctypes.c_uint64]),
     "mm_thermal_field": (c_int32, [c_void_p, c_double, ctypes.c_uint64, c_void_p]),
+    "mm_set_cubic_anisotropy": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mm_beff": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mm_llg_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32]),
     "mm_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
@@ -185,6 +186,8 @@ class Context:
         _check(lib.mm_create(ctypes.byref(handle), ctypes.byref(g), ctypes.byref(self._params),
                              _ptr(self._region), c_void_p(self._stream.cuda_stream)), "mm_create")
         self._h = handle
+        if "kc" in params:
+            self.set_cubic_anisotropy(params["kc"], params["anis_c1"], params["anis_c2"])
         self.demag = bool(demag)
         if self.demag:
             _check(lib.mm_demag_kernel_init(self._h), "mm_demag_kernel_init")
@@ -215,8 +218,12 @@ class Context:
 
     # -- API -----------------------------------------------------------------
     def set_params(self, params):
+        """New region tables; a params dict with cubic keys ("kc", "anis_c1",
+        "anis_c2") also sets the cubic anisotropy."""
         self._params = params_struct(params)
         _check(load().mm_set_params(self._h, ctypes.byref(self._params)), "mm_set_params")
+        if "kc" in params:
+            self.set_cubic_anisotropy(params["kc"], params["anis_c1"], params["anis_c2"])
 
     def set_demag(self, enable):
         if enable and not self.demag:
@@ -274,6 +281,17 @@ class Context:
         self._temp = t
         _check(load().mm_set_temperature(self._h, t.ctypes.data_as(c_void_p), int(seed) & ((1 << 64) - 1)),
                "mm_set_temperature")
+
+    def set_cubic_anisotropy(self, kc, c1, c2):
+        """Cubic anisotropy per region: kc [256, 3] (Kc1, Kc2, Kc3) in J/m^3, axes
+        c1, c2 [256, 3]; kc None removes it."""
+        if kc is None:
+            _check(load().mm_set_cubic_anisotropy(self._h, None, None, None), "mm_set_cubic_anisotropy")
+            return
+        arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64), (256, 3))) for v in (kc, c1, c2)]
+        self._cub = arrs
+        _check(load().mm_set_cubic_anisotropy(self._h, *(x.ctypes.data_as(c_void_p) for x in arrs)),
+               "mm_set_cubic_anisotropy")
 
     def thermal_field(self, dt, step):
         """The thermal field [3, nz, ny, nx] (T) of generator step `step` at time step dt."""
