@@ -83,6 +83,78 @@ def exchange_field(m, region, params, cell, pbc=(0, 0, 0)):
     return B * (_lut(params, "msat", region) > 0)
 
 
+def _dmi_neighbours(m, region, params, cell, pbc):
+    """For the in-plane directions (-x, +x, -y, +y): each cell's neighbour
+    magnetisation with the boundary rule of the induced DMI (section
+    "Dzyaloshinskii-Moriya interaction", Eqs. eqDMIBC1 - eqDMIBC2), and
+    whether the neighbour is real.
+
+    A neighbour is real when it lies inside the grid (or across a periodic
+    boundary) and is coupled to the cell by exchange (pair coefficient > 0);
+    otherwise it is replaced by the ghost m + n Delta dm/di|_boundary with n = -1
+    on the low side and +1 on the high side, where, with xi = D/(2A) of the
+    cell's region, dm/dx|_b = (-xi m_z, 0, xi m_x) and dm/dy|_b = (0, -xi m_z, xi m_y).
+    Returns a list of (value [3, ...], real mask, sign n, axis letter)."""
+    m = np.asarray(m, dtype=np.float64)
+    aex = _lut(params, "aex", region)
+    dind = _lut(params, "dind", region)
+    xi = np.where(aex > 0, dind / (2.0 * np.where(aex > 0, aex, 1.0)), 0.0)
+    out = []
+    for axis, d, p, name in ((3, cell[0], pbc[0], "x"), (2, cell[1], pbc[1], "y")):
+        n = m.shape[axis]
+        for sgn in (-1, 1):
+            nb = np.roll(m, -sgn, axis=axis)              # value at index i + sgn
+            rnb = np.roll(region, -sgn, axis=axis - 1)
+            idx = np.arange(n)
+            inside = (idx + sgn >= 0) & (idx + sgn < n) if p == 0 else np.ones(n, bool)
+            shape = [1, 1, 1]
+            shape[axis - 1] = n
+            inside = np.broadcast_to(inside.reshape(shape), region.shape)
+            real = inside & (exchange_coefficient(params, region, rnb) > 0)
+            if name == "x":
+                dm = np.stack([-xi * m[2], 0.0 * m[0], xi * m[0]])
+            else:
+                dm = np.stack([0.0 * m[0], -xi * m[2], xi * m[1]])
+            ghost = m + sgn * d * dm
+            out.append((np.where(real, nb, ghost), real, sgn, name))
+    return out
+
+
+def dmi_field(m, region, params, cell, pbc=(0, 0, 0)):
+    """Induced (interfacial) DMI field (T), Eq. eqBDMI with central differences:
+    B = 2D/Msat (dm_z/dx, dm_z/dy, -dm_x/dx - dm_y/dy), dm/di = (m_{i+1} - m_{i-1})/(2 Delta_i),
+    a missing neighbour replaced by its boundary ghost (_dmi_neighbours).
+    Zero without the "dind" table or where Msat = 0."""
+    m = np.asarray(m, dtype=np.float64)
+    if "dind" not in params:
+        return np.zeros_like(m)
+    msat = _lut(params, "msat", region)
+    pre = np.where(msat > 0, 2.0 * _lut(params, "dind", region) / np.where(msat > 0, msat, 1.0), 0.0)
+    (xm, _, _, _), (xp, _, _, _), (ym, _, _, _), (yp, _, _, _) = _dmi_neighbours(m, region, params, cell, pbc)
+    dx, dy = cell[0], cell[1]
+    dmz_dx = (xp[2] - xm[2]) / (2 * dx)
+    dmz_dy = (yp[2] - ym[2]) / (2 * dy)
+    dmx_dx = (xp[0] - xm[0]) / (2 * dx)
+    dmy_dy = (yp[1] - ym[1]) / (2 * dy)
+    return pre * np.stack([dmz_dx, dmz_dy, -dmx_dx - dmy_dy])
+
+
+def dmi_boundary_exchange(m, region, params, cell, pbc=(0, 0, 0)):
+    """The exchange field's share of the DMI boundary rule ("applied to the
+    Heisenberg exchange field" as well): each missing in-plane neighbour
+    contributes 2A/Msat (ghost - m)/Delta^2 of the cell's own region, where
+    without DMI it contributes nothing."""
+    m = np.asarray(m, dtype=np.float64)
+    if "dind" not in params:
+        return np.zeros_like(m)
+    c_self = exchange_coefficient(params, region, region)
+    B = np.zeros_like(m)
+    for val, real, sgn, name in _dmi_neighbours(m, region, params, cell, pbc):
+        d = cell[0] if name == "x" else cell[1]
+        B += np.where(real, 0.0, c_self * (val - m) / (d * d))
+    return B
+
+
 def anisotropy_field_parts(m, region, params):
     """Uniaxial anisotropy field split as (Ku1 part, Ku2 part), in tesla.
 
@@ -188,12 +260,17 @@ class Problem:
         return _demag.demag_field_fft(M, self.octant, workers=self.workers)
 
     def terms(self, m):
-        """Dict of the field terms at m: demag, exch, anis1, anis2, zeeman (T)."""
+        """Dict of the field terms at m: demag, exch (Heisenberg exchange plus the
+        induced DMI, with the DMI boundary rule, section "Dzyaloshinskii-Moriya
+        interaction": its energy is -1/2 M.B like the exchange's), anis1, anis2,
+        cubic1..3, zeeman (T)."""
         b1, b2 = anisotropy_field_parts(m, self.region, self.params)
         c1, c2, c3 = cubic_anisotropy_field_parts(m, self.region, self.params)
         return {
             "demag": self.demag_field(m),
-            "exch": exchange_field(m, self.region, self.params, self.cell, self.pbc),
+            "exch": exchange_field(m, self.region, self.params, self.cell, self.pbc)
+            + dmi_boundary_exchange(m, self.region, self.params, self.cell, self.pbc)
+            + dmi_field(m, self.region, self.params, self.cell, self.pbc),
             "anis1": b1,
             "anis2": b2,
             "cubic1": c1,
