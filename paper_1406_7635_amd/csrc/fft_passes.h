@@ -284,7 +284,7 @@ __device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds
 // extension, inverse FFT, crop, per-cell epilogue (FUSED: the torque also to
 // LDS for the next stage's combine), reductions.  The region table goes to
 // LDS at lut_l.
-template <int P, bool FUSED>
+template <int P, bool FUSED, bool DMI = false>
 __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
                                  RegionLut* lut_l, double* red, int blk, int tid) {
     constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI, NTH = XCfg<P>::NTH;
@@ -363,7 +363,7 @@ __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds
         const cf v01 = b3[(rr & 1) * SEQ + lds_pad(x)];
         const cf v2 = b3[2 * SEQ + lds_pad(x)];
         const int z = row / a.ny, y = row - z * a.ny;
-        const float3 tq = epilogue(a, rs, lut_l, mp, (long long)row * a.nx + x, x, y, z,
+        const float3 tq = epilogue<DMI>(a, rs, lut_l, mp, (long long)row * a.nx + x, x, y, z,
                                    make_float3(v01.x, v01.y, (rr & 1) ? v2.y : v2.x), acc);
         if constexpr (FUSED) {
             const int o = (rr & 1) * a.nx + x;

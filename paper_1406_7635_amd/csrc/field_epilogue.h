@@ -155,6 +155,8 @@ __device__ inline float3 stage_state(const FieldArgs& a, const Resolved& r, long
 // neighbour slots have fixed positions (x-, x+, y-, y+, z-, z+) so the arrays
 // stay in registers; the y and z pairs are skipped (uniformly) for a single
 // layer along that axis.
+// DMI = false compiles the DMI branch out (the hot x passes of grids without it).
+template <bool DMI = true>
 __device__ inline float3 exchange_at(const FieldArgs& a, const float* __restrict__ mp, long long cell,
                                      int x, int y, int z, int r, float3 mc) {
     const long long n = a.ncell;
@@ -190,6 +192,38 @@ __device__ inline float3 exchange_at(const FieldArgs& a, const float* __restrict
         const bool use = i < 2 || (i < 4 ? use_y : use_z);
         if (use) b = f3add(b, f3scale(a.ptab[pair_index(r, rn[i])] * id2[i / 2], f3sub(mn[i], mc)));
     }
+    if (DMI && a.dmi) {
+        // induced DMI (section "Dzyaloshinskii-Moriya interaction"):
+        // B = 2D/Msat (dm_z/dx, dm_z/dy, -dm_x/dx - dm_y/dy), central
+        // differences; an in-plane neighbour that is missing (outside an open
+        // boundary) or not exchange-coupled is replaced by the ghost
+        // m + n Delta dm/di|_b (n = -1 low side, +1 high side) with
+        // dm/dx|_b = xi (-m_z, 0, m_x), dm/dy|_b = xi (0, -m_z, m_y), xi = D/(2A);
+        // the exchange field then takes 2A/Msat (ghost - m)/Delta^2 from it too.
+        const float2 dm = a.dmi[r];
+        const float hx = rsqrtf(a.idx2), hy = rsqrtf(a.idy2);
+        const float3 gx = make_float3(-dm.y * mc.z, 0.f, dm.y * mc.x);
+        const float3 gy = make_float3(0.f, -dm.y * mc.z, dm.y * mc.y);
+        const bool wx = a.pbc & 1, wy = a.pbc & 2;
+        const bool geo[4] = {x > 0 || wx, x < a.nx - 1 || wx, y > 0 || wy, y < a.ny - 1 || wy};
+        const float cs = a.ptab[pair_index(r, r)];
+        float3 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const bool loaded = i < 2 || use_y;
+            const int rr = loaded ? rn[i] : r;
+            const float3 val = loaded ? mn[i] : mc;
+            const bool real = geo[i] && a.ptab[pair_index(r, rr)] > 0.f;
+            const float3 g = i < 2 ? gx : gy;
+            const float h = i < 2 ? hx : hy;
+            const float3 ghost = f3add(mc, f3scale((i & 1) ? h : -h, g));
+            v[i] = real ? val : ghost;
+            if (!real) b = f3add(b, f3scale(cs * id2[i / 2], f3sub(ghost, mc)));
+        }
+        const float ix = 0.5f / hx, iy = 0.5f / hy;
+        b = f3add(b, f3scale(dm.x, make_float3((v[1].z - v[0].z) * ix, (v[3].z - v[2].z) * iy,
+                                               -(v[1].x - v[0].x) * ix - (v[3].y - v[2].y) * iy)));
+    }
     return b;
 }
 
@@ -209,6 +243,7 @@ __device__ inline void epi_init(EpiAcc& acc) {
 // Everything after the magnetostatic field for one cell.
 // lut: the region table (global memory, or a copy in LDS).  Returns the
 // torque (zero in non-magnetic cells; only meaningful with EPI_TORQUE).
+template <bool DMI = true>
 __device__ inline float3 epilogue(const FieldArgs& a, const Resolved& rs, const RegionLut* lut,
                                 const float* __restrict__ mp, long long cell, int x, int y, int z, float3 bd,
                                 EpiAcc& acc) {
@@ -225,7 +260,7 @@ __device__ inline float3 epilogue(const FieldArgs& a, const Resolved& rs, const 
         return tq;
     }
     const float3 m = ld3o(mp, n, c4);
-    const float3 bex = exchange_at(a, mp, cell, x, y, z, r, m);
+    const float3 bex = exchange_at<DMI>(a, mp, cell, x, y, z, r, m);
     const float3 u = make_float3(L.b.x, L.b.y, L.b.z);
     const float um = f3dot(u, m);
     const float3 ban1 = f3scale(L.a.y * um, u);

@@ -95,6 +95,7 @@ __device__ inline FieldArgs member_field(const FieldArgs& b, const BMember& mb, 
     a.pbc = 0;                // ensemble members have open boundaries
     a.flags &= ~EPI_THERM;    // and no thermal field
     a.cub = nullptr;          // nor cubic anisotropy
+    a.dmi = nullptr;          // nor DMI
     const long long c = mb.cell_off, c3 = 3 * c;
     a.m0 = b.m0 + c3;
     a.ms = b.ms + c3;

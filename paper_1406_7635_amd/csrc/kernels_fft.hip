@@ -22,8 +22,9 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
     xfwd_part<P, false>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), &lut, 0.f, blk, threadIdx.x);
 }
 
-template <int P>
-__global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
+template <int P, bool DMI>
+__global__ void __launch_bounds__(XCfg<P>::NTH) __attribute__((amdgpu_waves_per_eu(P >= 4096 ? 4 : 6)))
+k_xinv(const FieldArgs a) {
     constexpr int GI = XCfg<P>::GI, GL = XCfg<P>::GL, NTH = XCfg<P>::NTH;
     extern __shared__ cf lds[];
     __shared__ double red[(NTH / 64 > 0 ? NTH / 64 : 1) * 6];
@@ -33,14 +34,14 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xinv(const FieldArgs a) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     row_bases<GI>(a, blk * GI, rbs, threadIdx.x);
     __syncthreads();
-    xinv_part<P, false>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), red, blk, threadIdx.x);
+    xinv_part<P, false, DMI>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), red, blk, threadIdx.x);
 }
 
 // Fused pass: the x-inverse of stage s (torque k_s, read m_s from ai.ms)
 // followed, row pair by row pair, by the x-forward of stage s + 1 (combine
 // with k_s from LDS as the last term, m_{s+1} to af.ms, a second buffer since
 // other workgroups still read m_s for the exchange field).
-template <int P>
+template <int P, bool DMI>
 __global__ void __launch_bounds__(XCfg<P>::NTH) __attribute__((amdgpu_waves_per_eu(6)))
 k_xrow(const FieldArgs ai, const FieldArgs af, float a_last) {
     constexpr int GI = XCfg<P>::GI, GL = XCfg<P>::GL, NTH = XCfg<P>::NTH;
@@ -53,7 +54,7 @@ k_xrow(const FieldArgs ai, const FieldArgs af, float a_last) {
     row_bases<GI>(ai, blk * GI, rbs, threadIdx.x);
     __syncthreads();
     RegionLut* lut_l = reinterpret_cast<RegionLut*>(lds + GI * GL);
-    xinv_part<P, true>(ai, rsi, lds, rbs, lut_l, red, blk, threadIdx.x);
+    xinv_part<P, true, DMI>(ai, rsi, lds, rbs, lut_l, red, blk, threadIdx.x);
     __syncthreads();
     // the next stage's pointers only now (short live ranges across the first part)
     const Resolved rsf = resolve(af);
@@ -105,7 +106,10 @@ static hipError_t xinv_p(const FieldArgs& a, hipStream_t s, int* nb_out, hipEven
     const size_t lds = x_lds<P>();
     const int nb = x_blocks<P>(a.nrows);
     if (nb_out) *nb_out = nb;
-    hipExtLaunchKernelGGL((k_xinv<P>), dim3(nb), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0, a);
+    if (a.dmi)
+        hipExtLaunchKernelGGL((k_xinv<P, true>), dim3(nb), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0, a);
+    else
+        hipExtLaunchKernelGGL((k_xinv<P, false>), dim3(nb), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0, a);
     return hipGetLastError();
 }
 
@@ -113,8 +117,12 @@ template <int P>
 static hipError_t xrow_p(const FieldArgs& ai, const FieldArgs& af, float a_last, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
     const size_t lds = x_lds<P>();
-    hipExtLaunchKernelGGL((k_xrow<P>), dim3(x_blocks<P>(ai.nrows)), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0,
-                          ai, af, a_last);
+    if (ai.dmi)
+        hipExtLaunchKernelGGL((k_xrow<P, true>), dim3(x_blocks<P>(ai.nrows)), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0,
+                              e1, 0, ai, af, a_last);
+    else
+        hipExtLaunchKernelGGL((k_xrow<P, false>), dim3(x_blocks<P>(ai.nrows)), dim3(XCfg<P>::NTH), (uint32_t)lds, s,
+                              e0, e1, 0, ai, af, a_last);
     return hipGetLastError();
 }
 
@@ -153,9 +161,12 @@ static hipError_t allow_lds(const void* f, size_t bytes) {
 template <int P>
 static hipError_t configure_x(void) {
     hipError_t e = allow_lds<P>((const void*)k_xfwd<P>, x_lds<P>());
-    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P>, x_lds<P>());
-    if constexpr (P >= 8)
-        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P>, x_lds<P>());
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, false>, x_lds<P>());
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, true>, x_lds<P>());
+    if constexpr (P >= 8) {
+        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, false>, x_lds<P>());
+        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, true>, x_lds<P>());
+    }
     return e;
 }
 

@@ -82,6 +82,10 @@ struct mm_ctx {
     bool cub_on = false;
     float4* cub = nullptr;    // [256][3] device table
     double hkc[NREG][3] = {}, hc1[NREG][3] = {}, hc2[NREG][3] = {};
+    // induced DMI (section "Dzyaloshinskii-Moriya interaction")
+    bool dmi_on = false;
+    float2* dmi = nullptr;    // [256] (2 D/Msat, D/(2 A))
+    double hdind[NREG] = {};
 };
 
 namespace {
@@ -95,7 +99,7 @@ hipError_t dalloc(mm_ctx* c, void** p, size_t bytes) {
 void free_all(mm_ctx* c) {
     void* ptrs[] = {c->region, c->params64, c->lut,      c->ptab,    c->tw,   c->spec,   c->khat, c->kbuf,
                     c->ms,     c->ms2,      c->st,       c->partials, c->dft_tab, c->bsur, c->bexact, c->zker,
-                    c->sigma,  c->bth,      c->cub};
+                    c->sigma,  c->bth,      c->cub,      c->dmi};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete c->hparams;
@@ -135,6 +139,7 @@ FieldArgs base_args(mm_ctx* c, const float* m0) {
     a.cellvol = (float)(c->dx * c->dy * c->dz);
     a.pbc = (c->pbc[0] > 0 ? 1 : 0) | (c->pbc[1] > 0 ? 2 : 0) | (c->pbc[2] > 0 ? 4 : 0);
     a.cub = c->cub_on ? c->cub : nullptr;
+    a.dmi = c->dmi_on ? c->dmi : nullptr;
     return a;
 }
 
@@ -303,6 +308,24 @@ int upload_cubic(mm_ctx* c) {
     }
     c->cub_on = on;
     MM_TRY(hipMemcpyAsync(c->cub, tab, sizeof(tab), hipMemcpyHostToDevice, c->stream));
+    MM_TRY(hipStreamSynchronize(c->stream));
+    return MM_OK;
+}
+
+// DMI table: 2 D/Msat and D/(2 A) per region in FP64, stored FP32 (0 for
+// non-magnetic regions; D/(2A) = 0 where A = 0).
+int upload_dmi(mm_ctx* c) {
+    float2 tab[NREG];
+    bool on = false;
+    for (int r = 0; r < NREG; ++r) {
+        const double ms = c->hparams->msat[r], aex = c->hparams->aex[r], d = c->hdind[r];
+        const double pre = ms > 0.0 ? 2.0 * d / ms : 0.0;
+        const double xi = (ms > 0.0 && aex > 0.0) ? d / (2.0 * aex) : 0.0;
+        tab[r] = make_float2((float)pre, (float)xi);
+        on = on || pre != 0.0;
+    }
+    c->dmi_on = on;
+    MM_TRY(hipMemcpyAsync(c->dmi, tab, sizeof(tab), hipMemcpyHostToDevice, c->stream));
     MM_TRY(hipStreamSynchronize(c->stream));
     return MM_OK;
 }
@@ -711,6 +734,7 @@ int mm_set_params(mm_ctx* c, const mm_params* p) {
     *c->hparams = *p;
     if (c->sigma) MM_CHECK(upload_sigma(c));
     if (c->cub) MM_CHECK(upload_cubic(c));
+    if (c->dmi) MM_CHECK(upload_dmi(c));
     c->fsal_valid = false;
     return MM_OK;
 }
@@ -744,6 +768,18 @@ int mm_set_cubic_anisotropy(mm_ctx* c, const double* kc, const double* c1, const
         }
     if (!c->cub) MM_TRY(dalloc(c, (void**)&c->cub, (size_t)NREG * 3 * sizeof(float4)));
     MM_CHECK(upload_cubic(c));
+    c->fsal_valid = false;
+    return MM_OK;
+}
+
+int mm_set_dmi(mm_ctx* c, const double* dind) {
+    if (!c) return MM_EINVAL;
+    for (int r = 0; r < NREG; ++r) {
+        c->hdind[r] = dind ? dind[r] : 0.0;
+        if (!isfinite(c->hdind[r])) return MM_EINVAL;
+    }
+    if (!c->dmi) MM_TRY(dalloc(c, (void**)&c->dmi, (size_t)NREG * sizeof(float2)));
+    MM_CHECK(upload_dmi(c));
     c->fsal_valid = false;
     return MM_OK;
 }

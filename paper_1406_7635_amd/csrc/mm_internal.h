@@ -98,6 +98,8 @@ struct FieldArgs {
     // cubic anisotropy per region (null: none): 3 float4 per region,
     // (c1, -2 Kc1/Msat), (c2, -2 Kc2/Msat), (c3, -4 Kc3/Msat)
     const float4* cub;
+    // induced DMI per region (null: none): (2 D/Msat, D/(2 A))
+    const float2* dmi;
 };
 
 struct ColArgs {

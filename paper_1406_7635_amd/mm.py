@@ -58,6 +58,7 @@ EXPORTS = {
     "mm_set_temperature": (c_int32, [c_void_p, c_void_p, ctypes.c_uint64]),
     "mm_thermal_field": (c_int32, [c_void_p, c_double, ctypes.c_uint64, c_void_p]),
     "mm_set_cubic_anisotropy": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mm_set_dmi": (c_int32, [c_void_p, c_void_p]),
     "mm_beff": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mm_llg_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32]),
     "mm_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
@@ -188,6 +189,8 @@ class Context:
         self._h = handle
         if "kc" in params:
             self.set_cubic_anisotropy(params["kc"], params["anis_c1"], params["anis_c2"])
+        if "dind" in params:
+            self.set_dmi(params["dind"])
         self.demag = bool(demag)
         if self.demag:
             _check(lib.mm_demag_kernel_init(self._h), "mm_demag_kernel_init")
@@ -219,11 +222,13 @@ class Context:
     # -- API -----------------------------------------------------------------
     def set_params(self, params):
         """New region tables; a params dict with cubic keys ("kc", "anis_c1",
-        "anis_c2") also sets the cubic anisotropy."""
+        "anis_c2") or the DMI key "dind" also sets those terms."""
         self._params = params_struct(params)
         _check(load().mm_set_params(self._h, ctypes.byref(self._params)), "mm_set_params")
         if "kc" in params:
             self.set_cubic_anisotropy(params["kc"], params["anis_c1"], params["anis_c2"])
+        if "dind" in params:
+            self.set_dmi(params["dind"])
 
     def set_demag(self, enable):
         if enable and not self.demag:
@@ -292,6 +297,15 @@ class Context:
         self._cub = arrs
         _check(load().mm_set_cubic_anisotropy(self._h, *(x.ctypes.data_as(c_void_p) for x in arrs)),
                "mm_set_cubic_anisotropy")
+
+    def set_dmi(self, dind):
+        """Induced DMI constant D per region (J/m^2, scalar or 256 values);
+        None removes it."""
+        if dind is None:
+            _check(load().mm_set_dmi(self._h, None), "mm_set_dmi")
+            return
+        self._dind = np.ascontiguousarray(np.broadcast_to(np.asarray(dind, dtype=np.float64), (256,)))
+        _check(load().mm_set_dmi(self._h, self._dind.ctypes.data_as(c_void_p)), "mm_set_dmi")
 
     def thermal_field(self, dt, step):
         """The thermal field [3, nz, ny, nx] (T) of generator step `step` at time step dt."""
