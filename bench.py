@@ -331,12 +331,11 @@ def grains_variant(steps, warmup):
 
 
 # algorithmic bytes per cell of one finite-temperature Heun step on a grid
-# without the magnetostatic term (float32 fields of 12 B, region 1 B):
-# thermal field (region, write 12), stage 1 (m, region, field, write k1),
-# stage 2 combine (m, k1, write m_s) and field (m_s, region, field, k1 for the
-# error estimate, write k2), new state (m, k1, k2, write m_s), commit (m_s,
-# write m)
-HEUN_THERMAL_BYTES_PER_CELL = 13 + 37 + 36 + 49 + 48 + 24
+# without the magnetostatic term (float32 fields of 12 B, region 1 B; the
+# thermal field is generated in the stage passes): stage 1 (m, region, write
+# k1), stage combine (m, k1, write m_s), stage 2 (m_s, region, m, k1, write k2
+# and the new state), commit (new state, write m)
+HEUN_THERMAL_BYTES_PER_CELL = 25 + 36 + 61 + 24
 
 
 def thermal_variant(steps, warmup):

@@ -4,6 +4,7 @@
 
 #include "../../include/mm.h"
 #include "field_epilogue.h"
+#include "thermal_noise.h"
 #include "step_control.h"
 
 namespace mm {
@@ -103,6 +104,43 @@ __global__ void __launch_bounds__(NT) k_local(const FieldArgs a, const float* __
         epilogue(a, rs, a.lut, mp, i, x, y, z, bd, acc);
     }
     if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NT>(a, acc, red, blockIdx.x);
+}
+
+// One stage of Heun's method without the magnetostatic term, fused: the
+// thermal field of the cell is generated in place (no field buffer) and, on
+// the second stage (mnew set), the new state m0 + dt (k1 + k2)/2 is formed
+// from the first-stage derivative and the torque just computed.
+__global__ void __launch_bounds__(NT) k_local_heun(const FieldArgs a, HeunLocal h) {
+    __shared__ double red[(NT / 64) * 6];
+    const Resolved rs = resolve(a);
+    if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    EpiAcc acc;
+    epi_init(acc);
+    if (i < a.ncell) {
+        const int x = (int)(i % a.nx);
+        const long long r = i / a.nx;
+        const int y = (int)(r % a.ny), z = (int)(r / a.ny);
+        const float* mp = a.sd.nk > 0 ? a.ms : a.m0;
+        float3 bth = make_float3(0.f, 0.f, 0.f);
+        if (h.sigma) {
+            const float sc = h.sigma[a.region[i]] * (float)(1.0 / sqrt(a.st->dt));
+            if (sc != 0.f) bth = thermal_eta(i, a.st->therm_step, h.seed, sc);
+        }
+        const float3 tq = epilogue(a, rs, a.lut, mp, i, x, y, z, bth, acc);
+        if (h.mnew) {
+            const float3 m0 = ld3(a.m0, a.ncell, i), k1 = ld3(rs.kin[0], a.ncell, i);
+            const float hd = 0.5f * rs.dt;
+            st3(h.mnew, a.ncell, i, make_float3(m0.x + hd * (k1.x + tq.x), m0.y + hd * (k1.y + tq.y),
+                                                m0.z + hd * (k1.z + tq.z)));
+        }
+    }
+    if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NT>(a, acc, red, blockIdx.x);
+}
+
+hipError_t launch_local_heun(const FieldArgs& a, const HeunLocal& h, hipStream_t s) {
+    hipLaunchKernelGGL(k_local_heun, dim3((unsigned)((a.ncell + NT - 1) / NT)), dim3(NT), 0, s, a, h);
+    return hipGetLastError();
 }
 
 hipError_t launch_local(const FieldArgs& a, hipStream_t s, int* nblocks_out, const float* bd_in) {

@@ -12,33 +12,13 @@
 #include <hip/hip_runtime.h>
 
 #include "mm_internal.h"
+#include "thermal_noise.h"
 
 namespace mm {
 
 namespace {
 
 constexpr int NTT = 256;
-
-struct U4 {
-    unsigned int x, y, z, w;
-};
-
-// Philox4x32 round constants: multipliers and the key increments (Weyl sequence)
-__device__ inline U4 philox10(U4 c, unsigned int k0, unsigned int k1) {
-    constexpr unsigned int MA = 0xD2511F53u, MB = 0xCD9E8D57u;
-    constexpr unsigned int WA = 0x9E3779B9u, WB = 0xBB67AE85u;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const unsigned int hi0 = __umulhi(MA, c.x), lo0 = MA * c.x;
-        const unsigned int hi1 = __umulhi(MB, c.z), lo1 = MB * c.z;
-        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
-        k0 += WA;
-        k1 += WB;
-    }
-    return c;
-}
-
-__device__ inline float unit24(unsigned int x) { return ((float)(x >> 8) + 0.5f) * 0x1p-24f; }
 
 __global__ void __launch_bounds__(NTT) k_thermal(long long ncell, const uint8_t* __restrict__ region,
                                                  const float* __restrict__ sigma, unsigned long long seed,
@@ -52,19 +32,9 @@ __global__ void __launch_bounds__(NTT) k_thermal(long long ncell, const uint8_t*
         dt = st->dt;
     }
     const float sc = sigma[region[i]] * (float)(1.0 / sqrt(dt));
-    float ex = 0.f, ey = 0.f, ez = 0.f;
-    if (sc != 0.f) {
-        const U4 o = philox10(U4{(unsigned int)i, (unsigned int)step, (unsigned int)(step >> 32), 0u},
-                              (unsigned int)seed, (unsigned int)(seed >> 32));
-        const float r0 = sqrtf(-2.f * logf(unit24(o.x)));
-        const float r2 = sqrtf(-2.f * logf(unit24(o.z)));
-        float s1, c1, s3, c3;
-        sincospif(2.f * unit24(o.y), &s1, &c1);
-        sincospif(2.f * unit24(o.w), &s3, &c3);
-        ex = sc * r0 * c1;
-        ey = sc * r0 * s1;
-        ez = sc * r2 * c3;
-    }
+    float3 e = make_float3(0.f, 0.f, 0.f);
+    if (sc != 0.f) e = thermal_eta(i, step, seed, sc);
+    const float ex = e.x, ey = e.y, ez = e.z;
     bth[i] = ex;
     bth[ncell + i] = ey;
     bth[2 * ncell + i] = ez;

@@ -86,6 +86,11 @@ struct mm_ctx {
     bool dmi_on = false;
     float2* dmi = nullptr;    // [256] (2 D/Msat, D/(2 A))
     double hdind[NREG] = {};
+    // mm_run replays one captured attempt as a HIP graph on a stream of its own
+    // (opt-in: measured slower than direct launches on this stack)
+    bool run_graphs = false;
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_user = nullptr, ev_graph = nullptr;
 };
 
 namespace {
@@ -103,6 +108,9 @@ void free_all(mm_ctx* c) {
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete c->hparams;
+    if (c->ev_user) (void)hipEventDestroy(c->ev_user);
+    if (c->ev_graph) (void)hipEventDestroy(c->ev_graph);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
     if (c->hst) (void)hipHostFree(c->hst);
     for (auto& t : c->timing)
         for (auto& pr : t.ev) {
@@ -483,6 +491,25 @@ int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done
 int heun_attempt(mm_ctx* c, float* m, int precess, bool check_done) {
     hipStream_t s = c->stream;
     const bool th = c->therm_on;
+    if (!c->demag_on) {
+        // no convolution: two fused local passes (noise generated in place,
+        // the new state formed by the second), the stage combine between them
+        HeunLocal h{th ? c->sigma : nullptr, c->seed, nullptr};
+        FieldArgs a0 = base_args(c, m);
+        a0.sd.nk = 0;
+        a0.sd.out_k = 0;
+        a0.flags = EPI_TORQUE | (precess ? EPI_PRECESS : 0) | (check_done ? EPI_CHECK_DONE : 0);
+        MM_TRY(launch_local_heun(a0, h, s));
+        FieldArgs a1 = stage_args(c, m, RK12, 1, precess, check_done);
+        MM_TRY(launch_combine(a1, s));
+        h.mnew = c->ms2;
+        MM_TRY(launch_local_heun(a1, h, s));
+        MM_TRY(launch_controller(c->st, 0, 2, check_done ? 1 : 0, s));
+        FieldArgs fin = base_args(c, m);
+        fin.ms = c->ms2;
+        MM_TRY(launch_finalize(fin, s));
+        return MM_OK;
+    }
     if (th)
         MM_TRY(launch_thermal(c->ncell, c->region, c->sigma, c->seed, c->st, 1, 0, 0.0, check_done ? 1 : 0, c->bth,
                               s));
@@ -508,6 +535,46 @@ int heun_attempt(mm_ctx* c, float* m, int precess, bool check_done) {
     FieldArgs fin = base_args(c, m);
     MM_TRY(launch_finalize(fin, s));
     return MM_OK;
+}
+
+bool timing_any(const mm_ctx* c) {
+    for (const auto& t : c->timing)
+        if (t.enabled) return true;
+    return false;
+}
+
+// One mm_run attempt captured as a graph.  Every kernel argument is fixed for
+// the run (buffers, solver, flags); what changes per attempt -- t, dt, the
+// stage map, the generator step -- lives in the device-side solver state, so
+// replays are the same launches.  The capture runs on the context's own
+// stream (default priority); on failure the caller launches directly.
+int capture_attempt(mm_ctx* c, float* m, const Tableau& tb, bool heun, int precess, hipGraphExec_t* out) {
+    *out = nullptr;
+    if (!c->gstream) {
+        MM_TRY(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+        MM_TRY(hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming));
+        MM_TRY(hipEventCreateWithFlags(&c->ev_graph, hipEventDisableTiming));
+    }
+    hipStream_t user = c->stream;
+    c->stream = c->gstream;
+    hipError_t e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        c->stream = user;
+        return map_err(e);
+    }
+    const int st = heun ? heun_attempt(c, m, precess, true) : attempt(c, m, tb, precess, true);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->gstream, &g);
+    c->stream = user;
+    if (st != MM_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return st != MM_OK ? st : map_err(e);
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) *out = nullptr;
+    return map_err(e);
 }
 
 bool need_first(mm_ctx* c, const float* m, int precess, int solver) {
@@ -784,6 +851,12 @@ int mm_set_dmi(mm_ctx* c, const double* dind) {
     return MM_OK;
 }
 
+int mm_set_run_graphs(mm_ctx* c, int32_t enable) {
+    if (!c) return MM_EINVAL;
+    c->run_graphs = enable != 0;
+    return MM_OK;
+}
+
 int mm_thermal_field(mm_ctx* c, double dt, uint64_t step, float* out_dev) {
     if (!c || !out_dev || !finite_pos(dt)) return MM_EINVAL;
     if (!c->sigma) return MM_ESTATE;
@@ -893,19 +966,35 @@ int mm_run(mm_ctx* c, float* m_dev, int32_t solver, double t_end, int64_t max_at
     // with the surrogate every attempt is checked on the host: after a miss the
     // rest of the run takes the exact path
     c->sur_active = c->sno != nullptr && solver == 45 && c->demag_on;
+    // many attempts: replay one captured attempt (fewer host launches)
+    hipGraphExec_t ge = nullptr;
+    if (c->run_graphs && !c->sur_active && !timing_any(c) && max_attempts >= 16) {
+        if (capture_attempt(c, m_dev, tb, heun, op.precess, &ge) != MM_OK) ge = nullptr;
+    }
     long long done_attempts = 0;
+    int rst = MM_OK;
     while (done_attempts < max_attempts) {
         long long nb = max_attempts - done_attempts;
         if (nb > per) nb = per;
         if (c->sur_active) nb = 1;
-        for (long long i = 0; i < nb; ++i) {
-            if (heun)
-                MM_CHECK(heun_attempt(c, m_dev, op.precess, true));
-            else
-                MM_CHECK(attempt(c, m_dev, tb, op.precess, true));
+        if (ge) {
+            hipError_t e = hipEventRecord(c->ev_user, c->stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(c->gstream, c->ev_user, 0);
+            for (long long i = 0; i < nb && e == hipSuccess; ++i) e = hipGraphLaunch(ge, c->gstream);
+            if (e == hipSuccess) e = hipEventRecord(c->ev_graph, c->gstream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->ev_graph, 0);
+            if (e != hipSuccess) {
+                rst = map_err(e);
+                break;
+            }
+        } else {
+            for (long long i = 0; i < nb && rst == MM_OK; ++i)
+                rst = heun ? heun_attempt(c, m_dev, op.precess, true) : attempt(c, m_dev, tb, op.precess, true);
+            if (rst != MM_OK) break;
         }
         done_attempts += nb;
-        MM_CHECK(sync_state(c));
+        rst = sync_state(c);
+        if (rst != MM_OK) break;
         if (c->sur_active) {
             if (c->hst->sur_fail) {
                 c->sur_active = false;
@@ -916,6 +1005,8 @@ int mm_run(mm_ctx* c, float* m_dev, int32_t solver, double t_end, int64_t max_at
         }
         if (c->hst->done) break;
     }
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (rst != MM_OK) return rst;
     c->sur_active = false;
     c->fsal_valid = !heun;  // Heun leaves no first-stage torque of the new state
     c->fsal_m = m_dev;

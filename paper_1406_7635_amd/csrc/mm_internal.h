@@ -259,6 +259,13 @@ hipError_t launch_thermal(long long ncell, const uint8_t* region, const float* s
                           const DevState* st, int from_state, unsigned long long step, double dt, int check_done,
                           float* bth, hipStream_t s);
 hipError_t launch_set_therm_step(DevState* st, unsigned long long step, hipStream_t s);
+// fused Heun stage without the magnetostatic term (kernels_local.hip)
+struct HeunLocal {
+    const float* sigma;       // thermal prefactors per region, null at 0 K
+    unsigned long long seed;
+    float* mnew;              // second stage: new state m0 + dt (k1 + k2)/2 written here
+};
+hipError_t launch_local_heun(const FieldArgs& a, const HeunLocal& h, hipStream_t s);
 hipError_t launch_reduce_energy(const double* partials, int nblocks, DevState* st, double cellvol,
                                 hipStream_t s);
 hipError_t launch_exchange_dump(const FieldArgs& a, float* out, hipStream_t s);

@@ -59,6 +59,7 @@ EXPORTS = {
     "mm_thermal_field": (c_int32, [c_void_p, c_double, ctypes.c_uint64, c_void_p]),
     "mm_set_cubic_anisotropy": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mm_set_dmi": (c_int32, [c_void_p, c_void_p]),
+    "mm_set_run_graphs": (c_int32, [c_void_p, c_int32]),
     "mm_beff": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mm_llg_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32]),
     "mm_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
@@ -297,6 +298,10 @@ class Context:
         self._cub = arrs
         _check(load().mm_set_cubic_anisotropy(self._h, *(x.ctypes.data_as(c_void_p) for x in arrs)),
                "mm_set_cubic_anisotropy")
+
+    def set_run_graphs(self, enable):
+        """Replay a captured attempt in run() (on by default)."""
+        _check(load().mm_set_run_graphs(self._h, 1 if enable else 0), "mm_set_run_graphs")
 
     def set_dmi(self, dind):
         """Induced DMI constant D per region (J/m^2, scalar or 256 values);

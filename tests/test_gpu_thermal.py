@@ -62,15 +62,17 @@ def test_heun_adaptive_matches_oracle(gpu):
     ctx.close()
 
 
-def test_heun_thermal_trajectory_matches_oracle(gpu):
-    """A finite-temperature film (demag, exchange, anisotropy) for 30 fixed
-    steps: the same random field on both sides, so the trajectories agree;
-    and 15 + 15 steps in two calls equal 30 in one (the generator's step
-    counter carries over)."""
+@pytest.mark.parametrize("demag", [True, False])
+def test_heun_thermal_trajectory_matches_oracle(gpu, demag):
+    """A finite-temperature film (exchange, anisotropy, with or without demag:
+    the field-buffer path and the fused local passes) for 30 fixed steps: the
+    same random field on both sides, so the trajectories agree; and 15 + 15
+    steps in two calls equal 30 in one (the generator's step counter carries
+    over)."""
     import torch
 
     case = synth.random_problem((24, 20, 1), (3e-9, 3e-9, 3e-9), seed=8, nregions=2)
-    ctx, prob, m = make_pair(case)
+    ctx, prob, m = make_pair(case, demag=demag)
     temp = _temps([(0, 300.0), (1, 150.0)])
     dt = 5e-14
     ctx.set_temperature(temp, 42)
