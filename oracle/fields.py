@@ -279,22 +279,41 @@ class Problem:
             "zeeman": zeeman_field(self.region, self.params),
         }
 
-    def beff(self, m, extra=None):
+    excitations = ()
+
+    def excitation_field(self, t):
+        """Sum of the excitation terms f_k(t) g_k(r) at time t (section "Material
+        Regions", paragraph "Time-dependent parameters"): each term is
+        (g [3, nz, ny, nx] in T, a, b, omega, phi) with f(t) = a + b sin(omega t + phi)."""
+        out = np.zeros((3,) + self.region.shape)
+        for g, a, b, w, phi in self.excitations:
+            out += (a + b * np.sin(w * t + phi)) * np.asarray(g, dtype=np.float64)
+        return out
+
+    def beff(self, m, extra=None, t=None):
         """Effective field (T); zero in cells with Msat = 0.  `extra` (e.g. the
-        thermal field, section "Thermal fluctuations") is added as is."""
-        t = self.terms(m)
-        b = t["demag"] + t["exch"] + t["anis1"] + t["anis2"] + t["zeeman"] + t["cubic1"] + t["cubic2"] + t["cubic3"]
+        thermal field, section "Thermal fluctuations") is added as is; with a
+        time t the excitation terms at t are added too."""
+        terms = self.terms(m)
+        b = terms["demag"] + terms["exch"] + terms["anis1"] + terms["anis2"] + terms["zeeman"] \
+            + terms["cubic1"] + terms["cubic2"] + terms["cubic3"]
         if extra is not None:
             b = b + extra
+        if t is not None and self.excitations:
+            b = b + self.excitation_field(t)
         return b * self.magnetic
 
-    def torque(self, m, precess=True, extra=None):
+    def torque(self, m, precess=True, extra=None, t=None):
         """Landau-Lifshitz torque (1/s), paper Eq. eqLLG with the sign that damps.
 
         tau = -gamma/(1+alpha^2) [m x B + alpha m x (m x B)]; with precess=False
         (relax, section "Energy minimization") the m x B term is dropped."""
-        return llg_torque(m, self.beff(m, extra), _lut(self.params, "alpha", self.region),
+        return llg_torque(m, self.beff(m, extra, t), _lut(self.params, "alpha", self.region),
                           self.gamma, precess) * self.magnetic
+
+    def torque_at(self, m, t):
+        """The torque at time t (excitations evaluated at t)."""
+        return self.torque(m, True, None, t)
 
     def energy(self, m):
         """Energies (J) from the fields, paper Eqs. for E_demag, E_exch, E_anis.

@@ -74,17 +74,18 @@ def rk4_step(f, m, dt):
     return normalize(m1)
 
 
-def embedded_step(f, m, k1, dt, tab):
+def embedded_step(f, m, k1, dt, tab, t=None):
     """One attempt of an FSAL embedded pair.
 
     Returns (m_new_raw, k_last, eps) where m_new_raw is the higher-order
     solution (= the last stage state), k_last = f(m_new_raw) and
-    eps = dt * max_cells |sum_j (b_j - b*_j) k_j|."""
+    eps = dt * max_cells |sum_j (b_j - b*_j) k_j|.  With a time t, f takes
+    (m, t_s) with the stage time t_s = t + c_s dt, c_s the row sum of a."""
     k = [k1]
     ms = m
     for row in tab["a"]:
         ms = m + dt * sum(float(a) * kj for a, kj in zip(row, k) if a != 0)
-        k.append(f(ms))
+        k.append(f(ms) if t is None else f(ms, t + dt * float(sum(row))))
     e = [float(b - bs) for b, bs in zip(tab["b"], tab["bstar"])]
     diff = sum(ej * kj for ej, kj in zip(e, k) if ej != 0)
     eps = dt * float(np.max(np.sqrt(np.sum(diff * diff, axis=0)))) if diff.size else 0.0
@@ -102,7 +103,9 @@ class Integrator:
     """Adaptive integrator state: m, t, dt, the FSAL torque and counters."""
 
     def __init__(self, f, m, solver="rk45", dt=1e-14, max_err=1e-5, headroom=0.8,
-                 dt_min=0.0, dt_max=np.inf):
+                 dt_min=0.0, dt_max=np.inf, timed=False):
+        """timed: f takes (m, t), evaluated at each stage's time."""
+        self.timed = timed
         self.f = f
         self.tab = SOLVERS[solver]
         self.m = np.asarray(m, dtype=np.float64).copy()
@@ -112,7 +115,7 @@ class Integrator:
         self.headroom = headroom
         self.dt_min = dt_min
         self.dt_max = dt_max
-        self.k1 = f(self.m)
+        self.k1 = f(self.m, 0.0) if timed else f(self.m)
         self.nsteps = 0
         self.nrejects = 0
         self.nevals = 1
@@ -123,11 +126,13 @@ class Integrator:
         if t_end is not None and self.t + dt > t_end:
             dt = t_end - self.t
         if self.tab.get("fsal", True):
-            m_new, k_last, eps = embedded_step(self.f, self.m, self.k1, dt, self.tab)
+            m_new, k_last, eps = embedded_step(self.f, self.m, self.k1, dt, self.tab,
+                                               self.t if self.timed else None)
         else:
             k = [self.k1]
             for row in self.tab["a"]:
-                k.append(self.f(self.m + dt * sum(float(a) * kj for a, kj in zip(row, k) if a != 0)))
+                ms = self.m + dt * sum(float(a) * kj for a, kj in zip(row, k) if a != 0)
+                k.append(self.f(ms, self.t + dt * float(sum(row))) if self.timed else self.f(ms))
             m_new = self.m + dt * sum(float(b) * kj for b, kj in zip(self.tab["b"], k))
             e = [float(b - bs) for b, bs in zip(self.tab["b"], self.tab["bstar"])]
             diff = sum(ej * kj for ej, kj in zip(e, k) if ej != 0)
@@ -139,7 +144,7 @@ class Integrator:
         if accepted:
             self.m = normalize(m_new)
             if k_last is None:  # no first-same-as-last: the next first stage is evaluated afresh
-                k_last = self.f(self.m)
+                k_last = self.f(self.m, self.t + dt) if self.timed else self.f(self.m)
                 self.nevals += 1
             self.k1 = k_last
             self.t += dt
