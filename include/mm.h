@@ -242,6 +242,21 @@ int mm_solver_reset(mm_ctx *c);
 
 int mm_get_info(mm_ctx *c, mm_info *info);
 
+/* Time-dependent excitation (section "Material Regions", paragraph
+ * "Time-dependent parameters"): term `slot` (0..3) adds f(t) g(r) to B_eff,
+ * f(t) = a + b sin(omega t + phi), g_dev a caller-owned device profile
+ * [3][nz][ny][nx] (FP32, tesla) that must outlive its use; g_dev = NULL clears
+ * the slot.  Every field evaluation inside mm_run and the single-step calls
+ * takes f at its stage time t + c_s dt (c_s the stage's node of the
+ * tableau); mm_beff, mm_torque, mm_energy and mm_max_torque take it at the
+ * context's current time (the end of the last run, 0 before); the field is
+ * part of B_eff but not of the energies; relax ignores it and mm_rk4_step
+ * (which has no time argument) returns MM_EUNSUPPORTED while a term is set.
+ * The surrogate stages are not used while a term is set.  Allocates the
+ * field buffer the first time. */
+int mm_set_excitation(mm_ctx *c, int32_t slot, const float *g_dev, double a, double b, double omega,
+                      double phi);
+
 /* enable = 1: mm_run with at least 16 attempts captures one attempt as a HIP
  * graph on a stream of the context's own (default priority, ordered after the
  * work on the context stream by events) and replays it, one host launch per

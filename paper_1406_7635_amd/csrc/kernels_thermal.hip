@@ -11,6 +11,7 @@
 //   eta_x, eta_y = sqrt(-2 ln u0) (cos, sin)(2 pi u1), eta_z = sqrt(-2 ln u2) cos(2 pi u3).
 #include <hip/hip_runtime.h>
 
+#include "extra_field.h"
 #include "mm_internal.h"
 #include "thermal_noise.h"
 
@@ -42,6 +43,32 @@ __global__ void __launch_bounds__(NTT) k_thermal(long long ncell, const uint8_t*
 
 __global__ void k_set_therm_step(DevState* st, unsigned long long step) { st->therm_step = step; }
 
+__global__ void __launch_bounds__(NTT) k_extra_field(const ExtraArgs e, const DevState* st, double cs,
+                                                     int check_done, float* __restrict__ bth) {
+    if (check_done && st->done) return;
+    const long long i = (long long)blockIdx.x * NTT + threadIdx.x;
+    if (i >= e.ncell) return;
+    const double dt = st->dt, ts = st->t + cs * dt;
+    float3 v = make_float3(0.f, 0.f, 0.f);
+    if (e.sigma) {
+        const float sc = e.sigma[e.region[i]] * (float)(1.0 / sqrt(dt));
+        if (sc != 0.f) v = thermal_eta(i, st->therm_step, e.seed, sc);
+    }
+#pragma unroll
+    for (int k = 0; k < MAX_EXC; ++k) {
+        if (k < e.nexc) {
+            const float f = (float)(e.exc[k].a + e.exc[k].b * sin(e.exc[k].omega * ts + e.exc[k].phi));
+            const float* g = e.exc[k].g;
+            v.x += f * g[i];
+            v.y += f * g[e.ncell + i];
+            v.z += f * g[2 * e.ncell + i];
+        }
+    }
+    bth[i] = v.x;
+    bth[e.ncell + i] = v.y;
+    bth[2 * e.ncell + i] = v.z;
+}
+
 }  // namespace
 
 hipError_t launch_thermal(long long ncell, const uint8_t* region, const float* sigma, unsigned long long seed,
@@ -49,6 +76,13 @@ hipError_t launch_thermal(long long ncell, const uint8_t* region, const float* s
                           float* bth, hipStream_t s) {
     hipLaunchKernelGGL(k_thermal, dim3((unsigned)((ncell + NTT - 1) / NTT)), dim3(NTT), 0, s, ncell, region, sigma,
                        seed, st, from_state, step, dt, check_done, bth);
+    return hipGetLastError();
+}
+
+hipError_t launch_extra_field(const ExtraArgs& e, const DevState* st, double cs, int check_done, float* bth,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_extra_field, dim3((unsigned)((e.ncell + NTT - 1) / NTT)), dim3(NTT), 0, s, e, st, cs,
+                       check_done, bth);
     return hipGetLastError();
 }
 

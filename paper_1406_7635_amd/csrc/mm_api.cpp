@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/mm.h"
+#include "extra_field.h"
 #include "mm_internal.h"
 #include "api_common.h"
 #include "sno_internal.h"
@@ -91,6 +92,9 @@ struct mm_ctx {
     bool run_graphs = false;
     hipStream_t gstream = nullptr;
     hipEvent_t ev_user = nullptr, ev_graph = nullptr;
+    // time-dependent excitation terms f_k(t) g_k(r) (caller-owned profiles)
+    ExcTerm exc[MAX_EXC] = {};
+    bool relaxing = false;    // relax runs without excitations
 };
 
 namespace {
@@ -376,12 +380,48 @@ Opts get_opts(const mm_solver_opts* o) {
     return r;
 }
 
+int n_exc(const mm_ctx* c) {
+    int n = 0;
+    for (const auto& e : c->exc) n += e.g != nullptr;
+    return n;
+}
+
+// Stage time fraction c_s of tableau tb: the row sum of a.
+double stage_c(const Tableau& tb, int s) {
+    double v = 0.0;
+    for (int j = 0; j < s; ++j) v += tb.a[s][j];
+    return v;
+}
+
+// The additive field of a field evaluation at t + cs dt (t, dt on the device):
+// the thermal field of the step when `thermal` (Heun stages) and the
+// excitation terms (not during relax), into the field buffer the pass adds.
+int prep_extra(mm_ctx* c, FieldArgs& a, double cs, bool thermal, bool check_done) {
+    const bool th = thermal && c->therm_on;
+    const int nx = c->relaxing ? 0 : n_exc(c);
+    if (!th && nx == 0) return MM_OK;
+    ExtraArgs e{};
+    e.ncell = c->ncell;
+    e.region = c->region;
+    e.sigma = th ? c->sigma : nullptr;
+    e.seed = c->seed;
+    e.nexc = 0;
+    if (nx > 0)
+        for (const auto& t : c->exc)
+            if (t.g) e.exc[e.nexc++] = t;
+    MM_TRY(launch_extra_field(e, c->st, cs, check_done ? 1 : 0, c->bth, c->stream));
+    a.flags |= EPI_THERM;
+    a.bth = c->bth;
+    return MM_OK;
+}
+
 // Torque of the committed state into logical derivative 0 (first stage).
 int eval_first(mm_ctx* c, const float* m, int precess) {
     FieldArgs a = base_args(c, m);
     a.sd.nk = 0;
     a.sd.out_k = 0;
     a.flags = EPI_TORQUE | (precess ? EPI_PRECESS : 0);
+    MM_CHECK(prep_extra(c, a, 0.0, false, false));
     return run_field(c, a, nullptr);
 }
 
@@ -429,7 +469,7 @@ int attempt_surrogate(mm_ctx* c, float* m, const Tableau& tb, int precess, bool 
 // stage state then alternates between two buffers.
 int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done) {
     const int S = tb.stages;
-    if (c->sur_active && c->demag_on && S == 7) {
+    if (c->sur_active && c->demag_on && S == 7 && n_exc(c) == 0) {
         if (!c->khat_ready) return MM_ESTATE;
         return attempt_surrogate(c, m, tb, precess, check_done);
     }
@@ -456,6 +496,7 @@ int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done
                 a_last = af.sd.a[af.sd.nk - 1];
                 --af.sd.nk;
             }
+            MM_CHECK(prep_extra(c, ai, stage_c(tb, s), false, check_done));
             {
                 Timed t(c, 3);
                 MM_TRY(launch_xrow(c->px, ai, af, a_last, c->stream, t.e1, t.e2));
@@ -466,11 +507,13 @@ int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done
         FieldArgs al = stage_args(c, m, tb, S - 1, precess, check_done);
         al.flags |= EPI_HAS_DEMAG;
         al.ms = buf[cur];
+        MM_CHECK(prep_extra(c, al, stage_c(tb, S - 1), false, check_done));
         MM_CHECK(run_xinv(c, al, nullptr));
         fin_ms = buf[cur];
     } else {
         for (int s = 1; s < S; ++s) {
             FieldArgs a = stage_args(c, m, tb, s, precess, check_done);
+            MM_CHECK(prep_extra(c, a, stage_c(tb, s), false, check_done));
             MM_CHECK(run_field(c, a, nullptr));
         }
     }
@@ -491,7 +534,7 @@ int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done
 int heun_attempt(mm_ctx* c, float* m, int precess, bool check_done) {
     hipStream_t s = c->stream;
     const bool th = c->therm_on;
-    if (!c->demag_on) {
+    if (!c->demag_on && n_exc(c) == 0) {
         // no convolution: two fused local passes (noise generated in place,
         // the new state formed by the second), the stage combine between them
         HeunLocal h{th ? c->sigma : nullptr, c->seed, nullptr};
@@ -510,18 +553,14 @@ int heun_attempt(mm_ctx* c, float* m, int precess, bool check_done) {
         MM_TRY(launch_finalize(fin, s));
         return MM_OK;
     }
-    if (th)
-        MM_TRY(launch_thermal(c->ncell, c->region, c->sigma, c->seed, c->st, 1, 0, 0.0, check_done ? 1 : 0, c->bth,
-                              s));
     FieldArgs a0 = base_args(c, m);
     a0.sd.nk = 0;
     a0.sd.out_k = 0;
-    a0.flags = EPI_TORQUE | (precess ? EPI_PRECESS : 0) | (check_done ? EPI_CHECK_DONE : 0) | (th ? EPI_THERM : 0);
-    a0.bth = c->bth;
+    a0.flags = EPI_TORQUE | (precess ? EPI_PRECESS : 0) | (check_done ? EPI_CHECK_DONE : 0);
+    MM_CHECK(prep_extra(c, a0, 0.0, true, check_done));
     MM_CHECK(run_field(c, a0, nullptr));
     FieldArgs a1 = stage_args(c, m, RK12, 1, precess, check_done);
-    a1.flags |= th ? EPI_THERM : 0;
-    a1.bth = c->bth;
+    MM_CHECK(prep_extra(c, a1, 1.0, true, check_done));
     MM_CHECK(run_field(c, a1, nullptr));
     FieldArgs f = base_args(c, m);
     f.sd.nk = 2;
@@ -611,6 +650,7 @@ int embedded_step(mm_ctx* c, float* m, const Tableau& tb, int solver, double* t,
 int energy_pass(mm_ctx* c, const float* m, double* out5) {
     FieldArgs a = base_args(c, m);
     a.flags = EPI_ENERGY;
+    MM_CHECK(prep_extra(c, a, 0.0, false, false));
     int nb = 0;
     MM_CHECK(run_field(c, a, &nb));
     MM_TRY(launch_reduce_energy(c->partials, nb, c->st, c->dx * c->dy * c->dz, c->stream));
@@ -623,6 +663,7 @@ int maxtorque_pass(mm_ctx* c, const float* m, int precess, double* out) {
     MM_TRY(launch_reset_accum(c->st, c->stream));
     FieldArgs a = base_args(c, m);
     a.flags = EPI_MAXTQ | (precess ? EPI_PRECESS : 0);
+    MM_CHECK(prep_extra(c, a, 0.0, false, false));
     MM_CHECK(run_field(c, a, nullptr));
     MM_CHECK(sync_state(c));
     unsigned int bits = c->hst->tq_bits;
@@ -851,6 +892,15 @@ int mm_set_dmi(mm_ctx* c, const double* dind) {
     return MM_OK;
 }
 
+int mm_set_excitation(mm_ctx* c, int32_t slot, const float* g_dev, double a, double b, double omega, double phi) {
+    if (!c || slot < 0 || slot >= MAX_EXC) return MM_EINVAL;
+    if (g_dev && !(isfinite(a) && isfinite(b) && isfinite(omega) && isfinite(phi))) return MM_EINVAL;
+    if (g_dev && !c->bth) MM_TRY(dalloc(c, (void**)&c->bth, (size_t)3 * c->ncell * sizeof(float)));
+    c->exc[slot] = ExcTerm{g_dev, a, b, omega, phi};
+    c->fsal_valid = false;
+    return MM_OK;
+}
+
 int mm_set_run_graphs(mm_ctx* c, int32_t enable) {
     if (!c) return MM_EINVAL;
     c->run_graphs = enable != 0;
@@ -877,6 +927,7 @@ int mm_beff(mm_ctx* c, const float* m_dev, float* beff_dev, float* bdemag_dev) {
     a.beff = beff_dev;
     a.bdemag = bdemag_dev;
     a.flags = EPI_BEFF | (bdemag_dev ? EPI_BDEMAG : 0);
+    MM_CHECK(prep_extra(c, a, 0.0, false, false));
     return run_field(c, a, nullptr);
 }
 
@@ -891,11 +942,13 @@ int mm_torque(mm_ctx* c, const float* m_dev, float* tau_dev, int32_t precess) {
     FieldArgs a = base_args(c, m_dev);
     a.tau = tau_dev;
     a.flags = EPI_TORQUE | (precess ? EPI_PRECESS : 0);
+    MM_CHECK(prep_extra(c, a, 0.0, false, false));
     return run_field(c, a, nullptr);
 }
 
 int mm_rk4_step(mm_ctx* c, float* m_dev, double dt, int32_t precess) {
     if (!c || !m_dev || !finite_pos(dt)) return MM_EINVAL;
+    if (n_exc(c) > 0) return MM_EUNSUPPORTED;  // no time argument for the excitations
     c->fsal_valid = false;
     MM_TRY(launch_set_state(c->st, 0.0, dt, INFINITY, 1e-5, 0.8, 0.0, 0.0, 4, 0, 1, 0, c->stream));
     const int pf = precess ? EPI_PRECESS : 0;
@@ -1035,9 +1088,8 @@ int mm_max_torque(mm_ctx* c, const float* m_dev, int32_t precess, double* out) {
     return maxtorque_pass(c, m_dev, precess ? 1 : 0, out);
 }
 
-int mm_relax(mm_ctx* c, float* m_dev, const mm_solver_opts* o, double min_max_err, int64_t max_steps,
-             double* energy_out, double* max_torque_out, int64_t* steps_out) {
-    if (!c || !m_dev || max_steps < 0) return MM_EINVAL;
+static int relax_impl(mm_ctx* c, float* m_dev, const mm_solver_opts* o, double min_max_err, int64_t max_steps,
+                      double* energy_out, double* max_torque_out, int64_t* steps_out) {
     Opts op = get_opts(o);
     op.precess = 0;
     if (!(min_max_err > 0.0)) min_max_err = 1e-9;
@@ -1105,6 +1157,16 @@ int mm_relax(mm_ctx* c, float* m_dev, const mm_solver_opts* o, double min_max_er
     if (max_torque_out) *max_torque_out = tq;
     if (steps_out) *steps_out = steps;
     return hit_cap ? MM_ENOTCONVERGED : MM_OK;
+}
+
+// relax minimises the energy of the static problem: no excitations, 0 K
+int mm_relax(mm_ctx* c, float* m_dev, const mm_solver_opts* o, double min_max_err, int64_t max_steps,
+             double* energy_out, double* max_torque_out, int64_t* steps_out) {
+    if (!c || !m_dev || max_steps < 0) return MM_EINVAL;
+    c->relaxing = true;
+    const int r = relax_impl(c, m_dev, o, min_max_err, max_steps, energy_out, max_torque_out, steps_out);
+    c->relaxing = false;
+    return r;
 }
 
 int mm_solver_reset(mm_ctx* c) {

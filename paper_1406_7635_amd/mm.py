@@ -60,6 +60,7 @@ EXPORTS = {
     "mm_set_cubic_anisotropy": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mm_set_dmi": (c_int32, [c_void_p, c_void_p]),
     "mm_set_run_graphs": (c_int32, [c_void_p, c_int32]),
+    "mm_set_excitation": (c_int32, [c_void_p, c_int32, c_void_p, c_double, c_double, c_double, c_double]),
     "mm_beff": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mm_llg_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32]),
     "mm_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
@@ -298,6 +299,19 @@ class Context:
         self._cub = arrs
         _check(load().mm_set_cubic_anisotropy(self._h, *(x.ctypes.data_as(c_void_p) for x in arrs)),
                "mm_set_cubic_anisotropy")
+
+    def set_excitation(self, slot, g, a=0.0, b=1.0, omega=0.0, phi=0.0):
+        """Excitation term `slot`: (a + b sin(omega t + phi)) * g, g a float32
+        [3, nz, ny, nx] tensor on the device (kept alive here); g None clears."""
+        if not hasattr(self, "_exc"):
+            self._exc = {}
+        if g is None:
+            self._exc.pop(slot, None)
+            _check(load().mm_set_excitation(self._h, int(slot), None, 0.0, 0.0, 0.0, 0.0), "mm_set_excitation")
+            return
+        self._exc[slot] = self._vec(g, "g")
+        _check(load().mm_set_excitation(self._h, int(slot), _ptr(self._exc[slot]), float(a), float(b), float(omega),
+                                        float(phi)), "mm_set_excitation")
 
     def set_run_graphs(self, enable):
         """Replay a captured attempt in run() (on by default)."""
