@@ -31,4 +31,9 @@ struct ExtraArgs {
 hipError_t launch_extra_field(const ExtraArgs& e, const DevState* st, double cs, int check_done, float* bth,
                               hipStream_t s);
 
+// nsteps fixed Heun steps of uncoupled cells in one launch, then the solver
+// state advanced by nsteps accepted steps (kernels_local.hip)
+hipError_t launch_heun_uncoupled(const FieldArgs& a, const float* sigma, unsigned long long seed, int nsteps,
+                                 int precess, hipStream_t s);
+
 }  // namespace mm

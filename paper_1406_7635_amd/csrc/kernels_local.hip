@@ -3,6 +3,7 @@
 #include <math.h>
 
 #include "../../include/mm.h"
+#include "extra_field.h"
 #include "field_epilogue.h"
 #include "thermal_noise.h"
 #include "step_control.h"
@@ -136,6 +137,88 @@ __global__ void __launch_bounds__(NT) k_local_heun(const FieldArgs a, HeunLocal 
         }
     }
     if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NT>(a, acc, red, blockIdx.x);
+}
+
+// Heun steps of uncoupled cells: no magnetostatic term, no exchange coupling
+// (Aex = 0 in every magnetic region), no DMI, no excitation -- the thermal
+// switching workload of the paper's figure figSwitch.  Each cell then evolves
+// alone, so one launch advances it by nsteps fixed steps with its state in
+// registers: per step the thermal field of (cell, step), k1 and k2 from the
+// cell's local field (uniaxial and cubic anisotropy, applied field, thermal
+// field: the terms of the field epilogue, in its order), the new state
+// m0 + dt (k1 + k2)/2 normalised.  The solver state is advanced afterwards by
+// k_advance_steps.
+__device__ inline float3 uncoupled_torque(const RegionLut& L, const float4* __restrict__ cub, int r, float3 m,
+                                          float3 bth, bool precess) {
+    const float3 u = make_float3(L.b.x, L.b.y, L.b.z);
+    const float um = f3dot(u, m);
+    const float3 ban1 = f3scale(L.a.y * um, u);
+    const float3 ban2 = f3scale(L.a.z * um * um * um, u);
+    const float3 bz = make_float3(L.c.x, L.c.y, L.c.z);
+    float3 B = f3add(make_float3(0.f, 0.f, 0.f), f3add(f3add(ban1, ban2), bz));
+    B = f3add(B, bth);
+    if (cub) {
+        const float4 p = cub[3 * r], q = cub[3 * r + 1], w = cub[3 * r + 2];
+        const float3 c1 = make_float3(p.x, p.y, p.z), c2 = make_float3(q.x, q.y, q.z),
+                     c3 = make_float3(w.x, w.y, w.z);
+        const float a1 = f3dot(c1, m), a2 = f3dot(c2, m), a3 = f3dot(c3, m);
+        const float s1 = a1 * a1, s2 = a2 * a2, s3 = a3 * a3;
+        const float g1 = a1 * (p.w * (s2 + s3) + q.w * s2 * s3 + w.w * s1 * (s2 * s2 + s3 * s3));
+        const float g2 = a2 * (p.w * (s1 + s3) + q.w * s1 * s3 + w.w * s2 * (s1 * s1 + s3 * s3));
+        const float g3 = a3 * (p.w * (s1 + s2) + q.w * s1 * s2 + w.w * s3 * (s1 * s1 + s2 * s2));
+        B = f3add(B, f3add(f3add(f3scale(g1, c1), f3scale(g2, c2)), f3scale(g3, c3)));
+    }
+    const float3 mxb = f3cross(m, B);
+    const float3 mxmxb = f3cross(m, mxb);
+    const float alpha = L.a.w;
+    return precess ? f3scale(L.b.w, f3add(mxb, f3scale(alpha, mxmxb))) : f3scale(L.b.w * alpha, mxmxb);
+}
+
+__global__ void __launch_bounds__(NT) k_heun_uncoupled(const FieldArgs a, const float* __restrict__ sigma,
+                                                       unsigned long long seed, int nsteps, int precess) {
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    if (i >= a.ncell) return;
+    const double dtd = a.st->dt;
+    const float dt = (float)dtd, hd = 0.5f * dt;
+    const unsigned long long step0 = a.st->therm_step;
+    const int r = a.region[i];
+    const RegionLut L = a.lut[r];
+    const float sc = sigma ? sigma[r] * (float)(1.0 / sqrt(dtd)) : 0.f;
+    float3 m = ld3(a.m0, a.ncell, i);
+    for (int s = 0; s < nsteps; ++s) {
+        float3 mn = m;
+        if (L.a.x != 0.f) {
+            const float3 bth = sc != 0.f ? thermal_eta(i, step0 + (unsigned long long)s, seed, sc)
+                                         : make_float3(0.f, 0.f, 0.f);
+            const float3 k1 = uncoupled_torque(L, a.cub, r, m, bth, precess != 0);
+            const float3 ms = make_float3(m.x + dt * k1.x, m.y + dt * k1.y, m.z + dt * k1.z);
+            const float3 k2 = uncoupled_torque(L, a.cub, r, ms, bth, precess != 0);
+            mn = make_float3(m.x + hd * (k1.x + k2.x), m.y + hd * (k1.y + k2.y), m.z + hd * (k1.z + k2.z));
+        }
+        const float n2 = f3dot(mn, mn);
+        m = f3scale(n2 > 0.f ? rsqrtf(n2) : 0.f, mn);
+    }
+    st3(const_cast<float*>(a.m0), a.ncell, i, m);
+}
+
+// n accepted fixed steps: time, counters and the thermal generator's step;
+// like the controller, the next step is clipped to land on t_end
+__global__ void k_advance_steps(DevState* st, int n) {
+    for (int s = 0; s < n; ++s) st->t = st->t + st->dt;
+    st->steps += n;
+    st->therm_step += (unsigned long long)n;
+    st->evals += 2LL * n;
+    st->accepted = 1;
+    if (isfinite(st->t_end) && st->t + st->dt > st->t_end && st->t < st->t_end) st->dt = st->t_end - st->t;
+}
+
+hipError_t launch_heun_uncoupled(const FieldArgs& a, const float* sigma, unsigned long long seed, int nsteps,
+                                 int precess, hipStream_t s) {
+    hipLaunchKernelGGL(k_heun_uncoupled, dim3((unsigned)((a.ncell + NT - 1) / NT)), dim3(NT), 0, s, a, sigma, seed,
+                       nsteps, precess);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    hipLaunchKernelGGL(k_advance_steps, dim3(1), dim3(1), 0, s, a.st, nsteps);
+    return hipGetLastError();
 }
 
 hipError_t launch_local_heun(const FieldArgs& a, const HeunLocal& h, hipStream_t s) {

@@ -1,5 +1,6 @@
 // mm_api.cpp -- the C ABI of include/mm.h: context, validation, solver
 // drivers (Runge-Kutta stage sequencing, device-side step control, relax).
+#include <algorithm>
 #include <math.h>
 #include <string.h>
 
@@ -378,6 +379,17 @@ Opts get_opts(const mm_solver_opts* o) {
         r.precess = o->precess ? 1 : 0;
     }
     return r;
+}
+
+// Cells that do not interact: no magnetostatic term, no exchange (Aex = 0 in
+// every magnetic region), no DMI, no excitation.
+bool uncoupled(const mm_ctx* c) {
+    if (c->demag_on || c->dmi_on) return false;
+    for (const auto& e : c->exc)
+        if (e.g) return false;
+    for (int r = 0; r < NREG; ++r)
+        if (c->hparams->msat[r] > 0.0 && c->hparams->aex[r] != 0.0) return false;
+    return true;
 }
 
 int n_exc(const mm_ctx* c) {
@@ -1019,6 +1031,40 @@ int mm_run(mm_ctx* c, float* m_dev, int32_t solver, double t_end, int64_t max_at
     // with the surrogate every attempt is checked on the host: after a miss the
     // rest of the run takes the exact path
     c->sur_active = c->sno != nullptr && solver == 45 && c->demag_on;
+    // Heun at finite temperature on uncoupled cells: whole chunks of fixed
+    // steps in one launch each (every cell alone, its state in registers); the
+    // last, clipped step of a run takes the general path
+    if (heun && c->therm_on && uncoupled(c)) {
+        MM_CHECK(sync_state(c));
+        long long done_attempts = 0;
+        while (done_attempts < max_attempts && !c->hst->done) {
+            const long long cap = std::min<long long>(max_attempts - done_attempts, 4096);
+            double tt = c->hst->t;
+            long long n = 0;
+            while (n < cap && !(isfinite(t_end) && tt + dt0 >= t_end)) {
+                tt += dt0;
+                ++n;
+            }
+            if (n > 0)
+                MM_TRY(launch_heun_uncoupled(base_args(c, m_dev), c->sigma, c->seed, (int)n, op.precess, c->stream));
+            else
+                MM_CHECK(heun_attempt(c, m_dev, op.precess, true));
+            done_attempts += n > 0 ? n : 1;
+            MM_CHECK(sync_state(c));
+        }
+        c->fsal_valid = false;
+        *t = c->hst->t;
+        *dt = c->hst->dt;
+        if (stats) {
+            stats->steps = c->hst->steps;
+            stats->rejects = c->hst->rejects;
+            stats->evals = c->hst->evals;
+            stats->t = c->hst->t;
+            stats->dt = c->hst->dt;
+            stats->err = c->hst->err;
+        }
+        return c->hst->status != 0 ? c->hst->status : MM_OK;
+    }
     // many attempts: replay one captured attempt (fewer host launches)
     hipGraphExec_t ge = nullptr;
     if (c->run_graphs && !c->sur_active && !timing_any(c) && max_attempts >= 16) {

@@ -170,3 +170,37 @@ def test_arrhenius_switching_rate(gpu):
                                                                                    st["steps"]))
     assert abs(math.log(f_meas / f_th)) < math.log(1.35)
     ctx.close()
+
+
+def test_uncoupled_fast_path_matches_oracle(gpu):
+    """Free spins (Aex = 0, no demag) take the one-launch-per-chunk path:
+    40 fixed steps plus a final step clipped to t_end (general path), with
+    uniaxial and cubic anisotropy and an applied field, against the oracle's
+    Heun steps with the same random field."""
+    import torch
+
+    n, dt = 32, 5e-14
+    params = synth.material(8e5, 0.0, alpha=0.05, ku1=3e4, anis_u=(0.6, 0.0, 0.8), bext=(0.01, -0.02, 0.03))
+    params["kc"] = np.zeros((256, 3))
+    params["kc"][0] = (2e4, -1e4, 5e3)
+    params["anis_c1"] = np.zeros((256, 3))
+    params["anis_c2"] = np.zeros((256, 3))
+    params["anis_c1"][0] = (1.0, 0.0, 0.0)
+    params["anis_c2"][0] = (0.0, 1.0, 0.0)
+    region = np.zeros((1, n, n), np.uint8)
+    m0 = synth.random_problem((n, n, 1), (4e-9,) * 3, seed=3)["m0"]
+    ctx = mm.Context((n, n, 1), (4e-9,) * 3, region, params, demag=False)
+    prob = __import__("oracle.fields", fromlist=["Problem"]).Problem((n, n, 1), (4e-9,) * 3, region, params,
+                                                                      demag=False)
+    temp = _temps([(0, 300.0)])
+    ctx.set_temperature(temp, 77)
+    m = torch.from_numpy(np.ascontiguousarray(m0)).cuda()
+    t, _, st = ctx.run(m, 40.5 * dt, dt=dt, solver=12)
+    assert st["steps"] == 41 and t == pytest.approx(40.5 * dt, rel=1e-12)
+    ref = othermal.run_thermal(prob, m0, dt, 40, temp, seed=77)
+    bth = othermal.thermal_field(region, params, temp, prob.cell, 0.5 * dt, 40, 77)
+    ref, _ = othermal.heun_step(lambda x: prob.torque(x, extra=bth), ref, 0.5 * dt)
+    err = np.max(np.abs(to_np(m) - ref))
+    log("uncoupled fast path: 40 + 1 steps, max |dm| %.2e" % err)
+    assert err < 1e-4
+    ctx.close()
