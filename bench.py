@@ -17,6 +17,7 @@ Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -361,6 +362,20 @@ def thermal_variant(steps, warmup):
     t, _, st = ctx.run(m, float("inf"), t=t, dt=dt, solver=12, max_attempts=steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
+    # the paper's check (Eq. eqSwitch): after 10 ns inside the wells, the
+    # population difference decays as exp(-2 f t) over 0.2 us
+    kt = ku * cell ** 3 / 8.0
+    ctx.set_temperature(kt / 1.380649e-23, 2024)
+    m.zero_()
+    m[2] = 1.0
+    t, _, _ = ctx.run(m, 10e-9, dt=dt, solver=12)
+    mz1 = float(m[2].double().mean())
+    t, _, _ = ctx.run(m, t + 0.2e-6, t=t, dt=dt, solver=12)
+    mz2 = float(m[2].double().mean())
+    f_meas = -math.log(mz2 / mz1) / (2 * 0.2e-6)
+    alpha, msat, gamma = 0.1, 1e6, 1.7595e11
+    f_th = gamma * alpha / (1 + alpha ** 2) * math.sqrt(8 * ku ** 3 * cell ** 3 / (2 * math.pi * msat ** 2 * kt)) \
+        * math.exp(-ku * cell ** 3 / kt)
     ctx.close()
     ncell = n * n
     launches = -(-steps // HEUN_UNCOUPLED_CHUNK)
@@ -368,6 +383,7 @@ def thermal_variant(steps, warmup):
     return {"value": ncell * st["evals"] / wall, "unit": "Beff evals*cells/s", "us_per_step": 1e6 * wall / steps,
             "steps": st["steps"], "cell_steps_per_s": ncell * steps / wall, "bound": "alu",
             "alg_GBs": gbs, "path": "uncoupled cells: one launch per chunk of up to %d steps" % HEUN_UNCOUPLED_CHUNK,
+            "switching_rate_per_s": f_meas, "eq_switch_rate_per_s": f_th,
             "workload": "512x512 uncoupled 10 nm cubes, Msat 1e6, alpha 0.1, Ku1 1e4 (z), no demag; Heun, fixed "
                         "dt 1e-12 s, thermal field at KV/kT = 8 (90.5 K)",
             "dtype": "f32"}
