@@ -12,7 +12,7 @@ number of attempts has every field-pass launch record HIP events at its own
 start and end; those durations give the per-kernel figures and the roofline
 fraction of the dominant kernel.
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the benchmark runs on one GPU.
 """
 import argparse
 import hashlib
