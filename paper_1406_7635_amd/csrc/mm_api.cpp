@@ -1045,12 +1045,15 @@ int mm_run(mm_ctx* c, float* m_dev, int32_t solver, double t_end, int64_t max_at
                 tt += dt0;
                 ++n;
             }
+            const long long before = c->hst->steps + c->hst->rejects;
             if (n > 0)
                 MM_TRY(launch_heun_uncoupled(base_args(c, m_dev), c->sigma, c->seed, (int)n, op.precess, c->stream));
             else
                 MM_CHECK(heun_attempt(c, m_dev, op.precess, true));
             done_attempts += n > 0 ? n : 1;
             MM_CHECK(sync_state(c));
+            // every attempt either ends the run or counts a step or a reject
+            if (!c->hst->done && c->hst->steps + c->hst->rejects == before) return MM_EDEVICE;
         }
         c->fsal_valid = false;
         *t = c->hst->t;
@@ -1072,7 +1075,9 @@ int mm_run(mm_ctx* c, float* m_dev, int32_t solver, double t_end, int64_t max_at
     }
     long long done_attempts = 0;
     int rst = MM_OK;
+    MM_CHECK(sync_state(c));
     while (done_attempts < max_attempts) {
+        const long long before = c->hst->steps + c->hst->rejects;
         long long nb = max_attempts - done_attempts;
         if (nb > per) nb = per;
         if (c->sur_active) nb = 1;
@@ -1094,6 +1099,12 @@ int mm_run(mm_ctx* c, float* m_dev, int32_t solver, double t_end, int64_t max_at
         done_attempts += nb;
         rst = sync_state(c);
         if (rst != MM_OK) break;
+        // every attempt either ends the run or counts a step or a reject (a
+        // surrogate miss counts neither: it repeats the step on the exact path)
+        if (!c->sur_active && !c->hst->done && c->hst->steps + c->hst->rejects == before) {
+            rst = MM_EDEVICE;
+            break;
+        }
         if (c->sur_active) {
             if (c->hst->sur_fail) {
                 c->sur_active = false;
