@@ -216,7 +216,8 @@ int mm_rk23_step(mm_ctx *c, float *m_dev, double *t, double *dt, const mm_solver
  * the step limits are ignored) with the thermal field of each step added to
  * B_eff in both stages; the other solvers return MM_EUNSUPPORTED.  *t and *dt
  * are read and updated.  stats may be NULL.  Returns MM_ESTEP / MM_ENONFINITE
- * if the run stopped on those conditions. */
+ * if the run stopped on those conditions, MM_EDEVICE if a chunk of attempts
+ * left the device-side solver state unchanged (no step, reject or end). */
 int mm_run(mm_ctx *c, float *m_dev, int32_t solver, double t_end, int64_t max_attempts,
            double *t, double *dt, const mm_solver_opts *o, mm_run_stats *stats);
 
