@@ -78,3 +78,27 @@ def test_precision_switch_rejects_other_grids(gpu):
         ctx.set_conv_precision("bf16")
     ctx.set_conv_precision("fp32")
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_periodic_film_demag_error(gpu, prec):
+    """The matrix-core column pass with periodic images (the images live in
+    the kernel only): a 96 x 1024 film periodic along x (2 images per side)
+    against the FP64 oracle's image sum, within 1e-4."""
+    import torch
+
+    from oracle import fields as ofields
+    from paper_1406_7635_amd import mm
+
+    case = synth.random_problem((96, 1024, 1), (3e-9, 3e-9, 3e-9), seed=9, nregions=2)
+    pbc = (2, 0, 0)
+    ctx = mm.Context(case["grid"], case["cell"], case["region"], case["params"], pbc=pbc)
+    prob = ofields.Problem(case["grid"], case["cell"], case["region"], case["params"], pbc=pbc, workers=-1)
+    ref = prob.demag_field(case["m0"].astype(np.float64))
+    m = torch.from_numpy(case["m0"]).cuda()
+    ctx.set_conv_precision(prec)
+    _, bd = ctx.beff(m, want_demag=True)
+    err = rel_inf(to_np(bd), ref)
+    log("periodic film demag rel error", prec, "%.3e" % err)
+    assert err < 1e-4
+    ctx.close()
