@@ -89,11 +89,13 @@ def _dmi_neighbours(m, region, params, cell, pbc):
     "Dzyaloshinskii-Moriya interaction", Eqs. eqDMIBC1 - eqDMIBC2), and
     whether the neighbour is real.
 
-    A neighbour is real when it lies inside the grid (or across a periodic
-    boundary) and is coupled to the cell by exchange (pair coefficient > 0);
-    otherwise it is replaced by the ghost m + n Delta dm/di|_boundary with n = -1
-    on the low side and +1 on the high side, where, with xi = D/(2A) of the
-    cell's region, dm/dx|_b = (-xi m_z, 0, xi m_x) and dm/dy|_b = (0, -xi m_z, xi m_y).
+    The paper replaces a neighbour only where it is missing at the boundary
+    of the magnet.  A neighbour is therefore real when it lies inside the grid
+    (or across a periodic boundary) and is magnetic (Msat > 0), whatever its
+    Aex or the interface scale; a missing one is replaced by the ghost
+    m + n Delta dm/di|_boundary with n = -1 on the low side and +1 on the high
+    side, where, with xi = D/(2A) of the cell's region (0 where A = 0),
+    dm/dx|_b = (-xi m_z, 0, xi m_x) and dm/dy|_b = (0, -xi m_z, xi m_y).
     Returns a list of (value [3, ...], real mask, sign n, axis letter)."""
     m = np.asarray(m, dtype=np.float64)
     aex = _lut(params, "aex", region)
@@ -110,7 +112,7 @@ def _dmi_neighbours(m, region, params, cell, pbc):
             shape = [1, 1, 1]
             shape[axis - 1] = n
             inside = np.broadcast_to(inside.reshape(shape), region.shape)
-            real = inside & (exchange_coefficient(params, region, rnb) > 0)
+            real = inside & (_lut(params, "msat", rnb) > 0)
             if name == "x":
                 dm = np.stack([-xi * m[2], 0.0 * m[0], xi * m[0]])
             else:

@@ -8,13 +8,19 @@ eps = max over cells |tau_high - tau_low| dt, compared with MaxErr and used to
 rescale dt with a headroom of 0.8.  Classical fixed-step RK4 is not among the
 paper's solvers; it is provided for fixed-step trajectory comparisons.
 
-Readings of points the paper leaves open (parity unpinned beyond the order and
-closed-form tests): the step factor is headroom * (MaxErr/eps)^(1/(q+1)) with
-q the order of the embedded (lower-order) solution, clamped to [0.1, 2] (2
-when eps = 0); a rejected step is retried with the new dt; the last step is
-clipped to land on t_end; after each accepted step m is renormalised to unit
-length (stage states stay raw); first-same-as-last reuses the last stage's
-torque, evaluated at the un-normalised stage state, as the next step's first.
+Readings of points the paper leaves open: the step factor is
+headroom * (MaxErr/eps)^(1/(q+1)) with q the order of the embedded
+(lower-order) solution, clamped to [0.1, 2] (2 when eps = 0); a rejected step
+is retried with the new dt; the last step is clipped to land on t_end; after
+each accepted step m is renormalised to unit length (stage states stay raw);
+first-same-as-last reuses the last stage's torque, evaluated at the
+un-normalised stage state, as the next step's first.  The step law is pinned
+by what the paper fixes -- the error per step is kept close to MaxErr with
+headroom 0.8 -- together with eps = C dt^(q+1): a step rejected (or accepted)
+with eps = r MaxErr is followed by one at eps = 0.8^(q+1) MaxErr whatever r
+(tests/test_oracle_integrate.py); the clamps are readings checked as such.
+relax() is pinned by its outcome: energy not increasing, known minima, and
+the residual torque band of section "Energy minimization".
 """
 from fractions import Fraction as F
 

@@ -106,3 +106,48 @@ def test_boundary_ghost_only_at_missing_neighbours():
         inner[y, x] = False
     assert np.all(b[:, 0][:, inner] == 0)
     assert np.all(np.abs(b[:, 0][:, ~inner]).sum(axis=0)[region[0][~inner] == 0] > 0)
+
+
+@pytest.mark.parametrize("case", ["aex0", "scale0"])
+def test_cycloid_closed_form_without_exchange_coupling(case):
+    """A neighbour is replaced by its boundary ghost only where it is missing
+    (outside the grid or non-magnetic).  In a periodic cycloid every neighbour
+    is a magnetic cell, so Eq. eqBDMI with central differences is exactly
+    -(2D/Msat)(sin k Delta/Delta) m in every cell, also where the cells are
+    not coupled by exchange: with Aex = 0 in the region, or with two regions
+    alternating along x and a zero interface scale between them.  A rule that
+    treats exchange-uncoupled neighbours as missing gives 0 (Aex = 0: the
+    ghost equals m) or a different field at every interface."""
+    n, delta, turns, d = 64, 1e-9, 3, 1.5e-3
+    k = 2 * math.pi * turns / (n * delta)
+    region = np.zeros((1, 1, n), np.uint8)
+    if case == "aex0":
+        p = _params(aex=0.0, dind=d)
+    else:
+        p = _params(aex=1e-11, dind=d)
+        p = synth.material(8e5, 1.3e-11, alpha=0.1, region=1, params=p)
+        p["dind"][1] = d
+        p["exch_scale"][1] = 0.0   # pair (1, 0)
+        region[0, 0, 1::2] = 1
+    m = _cycloid(n, k, delta)
+    b = fields.dmi_field(m, region, p, (delta,) * 3, pbc=(1, 1, 0))
+    ref = -2 * d / 8e5 * math.sin(k * delta) / delta * m
+    assert np.allclose(b, ref, rtol=1e-12, atol=1e-12 * np.max(np.abs(ref)))
+    assert np.all(fields.dmi_boundary_exchange(m, region, p, (delta,) * 3, pbc=(1, 1, 0)) == 0)
+
+
+def test_open_chain_aex0_interior_is_central_difference():
+    """An open chain with Aex = 0: interior cells take the central difference
+    of their real neighbours (closed form of the cycloid), and only the two
+    end cells see a ghost, which equals m when A = 0 (xi = 0)."""
+    n, delta, d = 40, 1e-9, 2e-3
+    k = 2 * math.pi / (16 * delta)
+    p = _params(aex=0.0, dind=d)
+    m = _cycloid(n, k, delta)
+    b = fields.dmi_field(m, np.zeros((1, 1, n), np.uint8), p, (delta,) * 3, pbc=(0, 1, 0))
+    ref = -2 * d / 8e5 * math.sin(k * delta) / delta * m
+    assert np.allclose(b[..., 1:-1], ref[..., 1:-1], rtol=1e-12, atol=1e-12 * np.max(np.abs(ref)))
+    # end cells: one-sided difference (m_1 - m_0)/(2 Delta), resp. (m_{n-1} - m_{n-2})/(2 Delta)
+    pre = 2 * d / 8e5 / (2 * delta)
+    e0 = pre * np.array([m[2, 0, 0, 1] - m[2, 0, 0, 0], 0.0, -(m[0, 0, 0, 1] - m[0, 0, 0, 0])])
+    assert np.allclose(b[:, 0, 0, 0], e0, rtol=1e-12, atol=1e-20)

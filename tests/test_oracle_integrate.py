@@ -156,3 +156,78 @@ def test_error_estimate_order(solver):
     slopes = [math.log(eps[i] / eps[i + 1]) / math.log(2.0) for i in range(2)]
     q = tab["order_low"]
     assert all(abs(s - (q + 1)) < 0.3 for s in slopes), slopes
+
+
+def _dt_for_eps(prob, m, tab, target):
+    """The step whose error estimate is `target`, from eps = C dt^(q+1)
+    (pinned by test_error_estimate_order), refined twice."""
+    q = tab["order_low"]
+    k1 = prob.torque(m)
+    dt = 1e-12
+    for _ in range(3):
+        eps = integrate.embedded_step(prob.torque, m, k1, dt, tab)[2]
+        dt *= (target / eps) ** (1.0 / (q + 1))
+    return dt
+
+
+@pytest.mark.parametrize("solver", ["rk45", "rk23"])
+@pytest.mark.parametrize("ratio", [4.0, 30.0])
+def test_rejected_step_retries_at_headroom_target(solver, ratio):
+    """Section "Adaptive time step": the controller keeps the error per step
+    close to MaxErr, with headroom 0.8.  Since eps = C dt^(q+1) for an
+    embedded pair of orders (q+1, q), a step rejected with eps = r MaxErr must
+    be retried at the step that brings eps to 0.8^(q+1) MaxErr whatever r
+    (r = 4, 30; both below the 0.1 clamp).  An exponent other than 1/(q+1)
+    misses this target by r^(1 - (q+1)/p) for exponent 1/p (about 30 % at
+    r = 4 for p = q), and a headroom applied to eps instead of dt misses it by
+    0.8^q."""
+    prob = _macrospin(alpha=0.1)
+    tab = integrate.SOLVERS[solver]
+    q = tab["order_low"]
+    m = _m((1, 0.2, 0.4))
+    max_err = 1e-6
+    dt = _dt_for_eps(prob, m, tab, ratio * max_err)
+    it = integrate.Integrator(prob.torque, m, solver, dt=dt, max_err=max_err)
+    acc, eps1 = it.step()
+    assert not acc and eps1 == pytest.approx(ratio * max_err, rel=1e-3)
+    acc, eps2 = it.step()
+    assert acc
+    assert eps2 / max_err == pytest.approx(0.8 ** (q + 1), rel=0.03), eps2 / max_err
+
+
+@pytest.mark.parametrize("solver", ["rk45", "rk23"])
+def test_accepted_step_grows_to_headroom_target(solver):
+    """An accepted step with eps well below MaxErr grows dt so that the next
+    attempt's eps lands near 0.8^(q+1) MaxErr (the state moves a little
+    between the two attempts, hence the looser bound)."""
+    prob = _macrospin(alpha=0.1)
+    tab = integrate.SOLVERS[solver]
+    q = tab["order_low"]
+    m = _m((1, 0.2, 0.4))
+    max_err = 1e-6
+    # eps = r MaxErr with 0.8 (1/r)^(1/(q+1)) = 1.6 keeps the growth below the clamp
+    r = (0.8 / 1.6) ** (q + 1)
+    dt = _dt_for_eps(prob, m, tab, r * max_err)
+    it = integrate.Integrator(prob.torque, m, solver, dt=dt, max_err=max_err)
+    acc, eps1 = it.step()
+    assert acc
+    assert it.dt / dt == pytest.approx(0.8 * (max_err / eps1) ** (1.0 / (q + 1)), rel=1e-12)
+    acc, eps2 = it.step()
+    assert eps2 / max_err == pytest.approx(0.8 ** (q + 1), rel=0.08), eps2 / max_err
+
+
+@pytest.mark.parametrize("solver", ["rk45", "rk23"])
+def test_step_factor_clamps(solver):
+    """Readings of the step law at its extremes: eps = 0 (m along B, no
+    torque) doubles dt; an error far above MaxErr shrinks dt tenfold."""
+    prob = _macrospin(alpha=0.1)
+    it = integrate.Integrator(prob.torque, _m((0, 0, 1)), solver, dt=1e-13, max_err=1e-6)
+    acc, eps = it.step()
+    assert acc and eps == 0.0 and it.dt == 2e-13
+    m = _m((1, 0.2, 0.4))
+    tab = integrate.SOLVERS[solver]
+    dt = _dt_for_eps(prob, m, tab, 1e-5) * 1e3 ** (1.0 / (tab["order_low"] + 1))
+    it = integrate.Integrator(prob.torque, m, solver, dt=dt, max_err=1e-9)
+    acc, eps = it.step()
+    assert not acc and eps > 1e6 * 1e-9
+    assert it.dt == pytest.approx(0.1 * dt, rel=1e-15)
