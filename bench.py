@@ -118,24 +118,43 @@ def xrow_pass_bytes(ctx, k_reads):
 DP45_XROW_K = (1 + 2 + 3 + 4 + 4) / 5.0
 
 
-def cpu_baseline(case, budget_s=12.0):
-    """The FP64 oracle timed on this host: torque evaluations of the same state."""
+def cpu_model():
+    """The host CPU's model name (/proc/cpuinfo), or the platform string."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(case, reps=5):
+    """The FP64 oracle timed on this host: the median of `reps` B_eff + torque
+    evaluations of the same state (after one untimed evaluation that pays
+    scipy's plan setup), scipy.fft with one worker per host thread."""
     from oracle import fields as ofields
 
+    t_init = time.perf_counter()
     prob = ofields.Problem(case["grid"], case["cell"], case["region"], case["params"], workers=-1)
+    t_init = time.perf_counter() - t_init
     m = case["m0"].astype(np.float64)
-    prob.torque(m)  # first call pays scipy's plan setup
-    n, t0 = 0, time.perf_counter()
-    while True:
+    prob.torque(m)
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
         prob.torque(m)
-        n += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or n >= 50:
-            break
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
     ncell = int(np.prod(case["grid"]))
-    return {"value": ncell * n / el, "unit": "Beff evals*cells/s", "cores": os.cpu_count(), "kind": "oracle",
-            "sample": "%d FP64 B_eff+torque evaluations of the %dx%dx%d vortex state (scipy.fft, all cores), "
-                      "%.1f s" % (n, case["grid"][0], case["grid"][1], case["grid"][2], el)}
+    threads = os.cpu_count()
+    return {"value": ncell / med, "unit": "Beff evals*cells/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "median_eval_s": med, "eval_s": times, "kernel_init_s": t_init,
+            "sample": "median of %d FP64 B_eff+torque evaluations of the %dx%dx%d vortex state (scipy.fft with "
+                      "%d workers); the oracle's demag tensor set-up (%.1f s) not included"
+                      % (reps, case["grid"][0], case["grid"][1], case["grid"][2], threads, t_init)}
 
 
 def mfma_variants(ctx, m, opts, ncell, steps):

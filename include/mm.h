@@ -301,10 +301,11 @@ int mm_set_cubic_anisotropy(mm_ctx *c, const double *kc, const double *c1, const
  * (host array; NULL removes it).  Adds to the exchange field
  *   B_DM = 2D/Msat (dm_z/dx, dm_z/dy, -dm_x/dx - dm_y/dy)
  * with central differences (m_{i+1} - m_{i-1})/(2 Delta_i) and the boundary
- * rule of the paper: an in-plane neighbour outside an open boundary, or not
- * coupled by exchange (Msat = 0, Aex = 0 or a zero interface scale), is
- * replaced by m + n Delta dm/di|_b (n = -1 on the low side, +1 on the high
- * side), dm/dx|_b = D/(2A) (-m_z, 0, m_x), dm/dy|_b = D/(2A) (0, -m_z, m_y)
+ * rule of the paper: an in-plane neighbour missing at the boundary of the
+ * magnet -- outside an open edge of the grid, or a non-magnetic cell
+ * (Msat = 0) -- is replaced by m + n Delta dm/di|_b (n = -1 on the low side,
+ * +1 on the high side), dm/dx|_b = D/(2A) (-m_z, 0, m_x), dm/dy|_b = D/(2A)
+ * (0, -m_z, m_y)
  * (D, A, Msat of the cell's region), and that ghost also enters the exchange
  * field as 2A/Msat (ghost - m)/Delta^2.  Its energy is counted with the
  * exchange energy (-1/2 M.B).  Tables are rebuilt by mm_set_params.

@@ -157,8 +157,8 @@ __device__ inline float3 stage_state(const FieldArgs& a, const Resolved& r, long
 // layer along that axis.
 // DMI = false compiles the DMI branch out (the hot x passes of grids without it).
 template <bool DMI = true>
-__device__ inline float3 exchange_at(const FieldArgs& a, const float* __restrict__ mp, long long cell,
-                                     int x, int y, int z, int r, float3 mc) {
+__device__ inline float3 exchange_at(const FieldArgs& a, const RegionLut* lut, const float* __restrict__ mp,
+                                     long long cell, int x, int y, int z, int r, float3 mc) {
     const long long n = a.ncell;
     const int sxy = a.nx * a.ny;
     const bool use_y = a.ny > 1, use_z = a.nz > 1;
@@ -195,8 +195,9 @@ __device__ inline float3 exchange_at(const FieldArgs& a, const float* __restrict
     if (DMI && a.dmi) {
         // induced DMI (section "Dzyaloshinskii-Moriya interaction"):
         // B = 2D/Msat (dm_z/dx, dm_z/dy, -dm_x/dx - dm_y/dy), central
-        // differences; an in-plane neighbour that is missing (outside an open
-        // boundary) or not exchange-coupled is replaced by the ghost
+        // differences; an in-plane neighbour that is missing at the boundary
+        // of the magnet (outside an open edge of the grid, or a cell with
+        // Msat = 0) is replaced by the ghost
         // m + n Delta dm/di|_b (n = -1 low side, +1 high side) with
         // dm/dx|_b = xi (-m_z, 0, m_x), dm/dy|_b = xi (0, -m_z, m_y), xi = D/(2A);
         // the exchange field then takes 2A/Msat (ghost - m)/Delta^2 from it too.
@@ -213,7 +214,7 @@ __device__ inline float3 exchange_at(const FieldArgs& a, const float* __restrict
             const bool loaded = i < 2 || use_y;
             const int rr = loaded ? rn[i] : r;
             const float3 val = loaded ? mn[i] : mc;
-            const bool real = geo[i] && a.ptab[pair_index(r, rr)] > 0.f;
+            const bool real = geo[i] && lut[rr].a.x > 0.f;
             const float3 g = i < 2 ? gx : gy;
             const float h = i < 2 ? hx : hy;
             const float3 ghost = f3add(mc, f3scale((i & 1) ? h : -h, g));
@@ -226,6 +227,10 @@ __device__ inline float3 exchange_at(const FieldArgs& a, const float* __restrict
     }
     return b;
 }
+
+// fmaxf drops a NaN operand, so a NaN norm would vanish from a max reduction:
+// it enters as +inf instead (the controller then stops with a non-finite error).
+__device__ inline float finite_or_inf(float v) { return v == v ? v : INFINITY; }
 
 // Per-thread accumulators of the reductions.
 struct EpiAcc {
@@ -260,7 +265,7 @@ __device__ inline float3 epilogue(const FieldArgs& a, const Resolved& rs, const 
         return tq;
     }
     const float3 m = ld3o(mp, n, c4);
-    const float3 bex = exchange_at<DMI>(a, mp, cell, x, y, z, r, m);
+    const float3 bex = exchange_at<DMI>(a, lut, mp, cell, x, y, z, r, m);
     const float3 u = make_float3(L.b.x, L.b.y, L.b.z);
     const float um = f3dot(u, m);
     const float3 ban1 = f3scale(L.a.y * um, u);
@@ -298,7 +303,7 @@ __device__ inline float3 epilogue(const FieldArgs& a, const Resolved& rs, const 
         tq = (flags & EPI_PRECESS) ? f3scale(L.b.w, f3add(mxb, f3scale(alpha, mxmxb)))
                                    : f3scale(L.b.w * alpha, mxmxb);
         if (flags & EPI_TORQUE) st3o(rs.kout, n, c4, tq);
-        if (flags & EPI_MAXTQ) acc.tqmax = fmaxf(acc.tqmax, sqrtf(f3dot(tq, tq)));
+        if (flags & EPI_MAXTQ) acc.tqmax = fmaxf(acc.tqmax, finite_or_inf(sqrtf(f3dot(tq, tq))));
         if (flags & EPI_ERR) {
             float3 kv[7];
 #pragma unroll
@@ -308,7 +313,7 @@ __device__ inline float3 epilogue(const FieldArgs& a, const Resolved& rs, const 
 #pragma unroll
             for (int j = 0; j < 7; ++j)
                 if (j < a.sd.nerr) d = f3add(d, f3scale(a.sd.e[j], kv[j]));
-            acc.errmax = fmaxf(acc.errmax, sqrtf(f3dot(d, d)));
+            acc.errmax = fmaxf(acc.errmax, finite_or_inf(sqrtf(f3dot(d, d))));
         }
     }
     if (flags & EPI_ENERGY) {

@@ -92,12 +92,15 @@ __device__ inline void controller_update(DevState* st, int last_k, int evals, in
     st->accepted = acc ? 1 : 0;
     double dtn = dt * fac;
     if (st->dt_max > 0.0) dtn = fmin(dtn, st->dt_max);
-    if (dtn < st->dt_min) {
+    if (acc && clipped) st->done = 1;
+    if (st->target_steps > 0 && st->steps >= st->target_steps) st->done = 1;
+    // the step law's proposal below dt_min stops the run, unless the run has
+    // just ended (a step clipped to t_end proposes from its short length);
+    // clipping the next step to t_end below does not count
+    if (!st->done && dtn < st->dt_min) {
         st->status = -6;  // MM_ESTEP
         st->done = 1;
     }
-    if (acc && clipped) st->done = 1;
-    if (st->target_steps > 0 && st->steps >= st->target_steps) st->done = 1;
     if (isfinite(st->t_end) && st->t + dtn > st->t_end && st->t < st->t_end) dtn = st->t_end - st->t;
     st->dt = dtn;
 }

@@ -107,8 +107,12 @@ def test_relax_macrospin_and_film(gpu):
     film = synth.random_problem((16, 12, 2), (3e-9, 3e-9, 3e-9), seed=4, nregions=2)
     ctx, prob, m = make_pair(film)
     e0 = ctx.energy(m)["total"]
-    r = ctx.relax(m, max_steps=4000)
+    r = ctx.relax(m, max_steps=20000)
+    log("film relax: steps", r["steps"], "converged", r["converged"], "max torque / gamma",
+        r["max_torque"] / GAMMA_LL, "T")
+    assert r["converged"]
     assert r["energy"] < e0
     ref = prob.energy(to_np(m))["total"]
     assert r["energy"] == pytest.approx(ref, rel=1e-4)
-    assert r["max_torque"] / GAMMA_LL < 1e-2
+    # section "Energy minimization": residual torques of 1e-4 ... 1e-7 gamma_LL T
+    assert r["max_torque"] / GAMMA_LL < 1e-4
