@@ -468,6 +468,33 @@ int mm_set_surrogate(mm_ctx *c, const mm_sno *s, double tol);
  * fallbacks since the last solver restart, err of the last checked attempt. */
 int mm_surrogate_stats(mm_ctx *c, int64_t *sur_steps, int64_t *fallbacks, double *last_err);
 
+/* Training of the surrogate on the GPU (hand-written forward pass that keeps
+ * its activations, backward pass and Adam; FP32 weights and arithmetic).  A
+ * trainer holds the FP32 master weights (initialised from `weights`, host,
+ * MM_SNO_NWEIGHTS values in the order above), Adam's two moments and the
+ * activations of one batch of `batch` samples on an nx x ny grid
+ * (32 <= nx <= 512, 16 <= ny <= 512, 1 <= batch <= 256).  m_dev and
+ * target_dev are device arrays [batch][3][ny][nx] (target: B_demag /
+ * out_scale, the network's output units).  The loss is the mean over the
+ * batch of ||y_b - t_b||_2 / ||t_b||_2, y_b the network's output (the
+ * gradient of a norm at 0 is taken as 0).
+ *   mm_sno_train_grad: loss and its gradient with respect to the weights
+ *     (grad_dev: MM_SNO_NWEIGHTS floats on the device, or NULL to keep it
+ *     inside the trainer); no update.
+ *   mm_sno_train_step: the same, then one Adam step (beta1 0.9, beta2 0.999,
+ *     eps 1e-8, bias-corrected) with learning rate lr.
+ * loss_out may be NULL: the call then returns without synchronising.  Work
+ * is enqueued on hip_stream.  mm_sno_train_get_weights copies the current
+ * FP32 weights to the host (synchronises). */
+typedef struct mm_sno_trainer mm_sno_trainer;
+int mm_sno_train_create(mm_sno_trainer **out, int32_t nx, int32_t ny, int32_t batch, const float *weights,
+                        int64_t nweights, void *hip_stream);
+int mm_sno_train_grad(mm_sno_trainer *t, const float *m_dev, const float *target_dev, float *grad_dev,
+                      double *loss_out);
+int mm_sno_train_step(mm_sno_trainer *t, const float *m_dev, const float *target_dev, double lr, double *loss_out);
+int mm_sno_train_get_weights(mm_sno_trainer *t, float *weights_host);
+void mm_sno_train_destroy(mm_sno_trainer *t);
+
 void mm_destroy(mm_ctx *c);
 const char *mm_strerror(int status);
 

@@ -22,7 +22,8 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 SOURCES = ["kernels_fft.hip", "kernels_mfma.hip", "kernels_batch.hip", "kernels_local.hip", "kernels_demag.hip",
-           "kernels_sno.hip", "kernels_thermal.hip", "mm_api.cpp", "mm_batch.cpp", "mm_sno.cpp"]
+           "kernels_sno.hip", "kernels_sno_train.hip", "kernels_thermal.hip", "mm_api.cpp", "mm_batch.cpp",
+           "mm_sno.cpp", "mm_sno_train.cpp"]
 
 
 def _compile(src):

@@ -105,6 +105,12 @@ EXPORTS = {
     "mm_set_surrogate": (c_int32, [c_void_p, c_void_p, c_double]),
     "mm_surrogate_stats": (c_int32, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64),
                                      ctypes.POINTER(c_double)]),
+    "mm_sno_train_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, c_int32, c_int32, c_void_p, c_int64,
+                                      c_void_p]),
+    "mm_sno_train_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double)]),
+    "mm_sno_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(c_double)]),
+    "mm_sno_train_get_weights": (c_int32, [c_void_p, c_void_p]),
+    "mm_sno_train_destroy": (None, [c_void_p]),
     "mm_destroy": (None, [c_void_p]),
     "mm_strerror": (ctypes.c_char_p, [c_int32]),
 }
@@ -577,6 +583,67 @@ class Surrogate:
     def close(self):
         if getattr(self, "_h", None):
             load().mm_sno_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SurrogateTrainer:
+    """Training of the surrogate on the GPU (mm_sno_train_*): FP32 master
+    weights, Adam, batches of `batch` samples on an nx x ny grid.  m and
+    target: float32 tensors [batch, 3, ny, nx] (or [batch, 3, 1, ny, nx]) on
+    the device, target in the network's output units (B_demag / out_scale)."""
+
+    def __init__(self, nx, ny, batch, weights, stream=None):
+        import torch
+
+        self._torch = torch
+        self.grid = (int(nx), int(ny))
+        self.batch = int(batch)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        h = c_void_p()
+        _check(load().mm_sno_train_create(ctypes.byref(h), int(nx), int(ny), int(batch), w.ctypes.data_as(c_void_p),
+                                          w.size, c_void_p(self._stream.cuda_stream)), "mm_sno_train_create")
+        self._h = h
+
+    def _batch(self, x, name):
+        t = self._torch
+        nx, ny = self.grid
+        if not isinstance(x, t.Tensor) or x.dtype != t.float32 or x.device != self.device \
+                or x.numel() != self.batch * 3 * nx * ny or not x.is_contiguous():
+            raise ValueError("%s must be a contiguous float32 tensor of %d x 3 x %d x %d on %s"
+                             % (name, self.batch, ny, nx, self.device))
+        return x
+
+    def grad(self, m, target):
+        """(loss, gradient tensor of MM_SNO_NWEIGHTS floats) without an update."""
+        g = self._torch.empty(SNO_NWEIGHTS, dtype=self._torch.float32, device=self.device)
+        loss = c_double()
+        _check(load().mm_sno_train_grad(self._h, _ptr(self._batch(m, "m")), _ptr(self._batch(target, "target")),
+                                        _ptr(g), ctypes.byref(loss)), "mm_sno_train_grad")
+        return loss.value, g
+
+    def step(self, m, target, lr, want_loss=True):
+        """One Adam step; returns the batch loss before the update (or None)."""
+        loss = c_double()
+        _check(load().mm_sno_train_step(self._h, _ptr(self._batch(m, "m")), _ptr(self._batch(target, "target")),
+                                        float(lr), ctypes.byref(loss) if want_loss else None), "mm_sno_train_step")
+        return loss.value if want_loss else None
+
+    def weights(self):
+        out = np.empty(SNO_NWEIGHTS, dtype=np.float32)
+        _check(load().mm_sno_train_get_weights(self._h, out.ctypes.data_as(c_void_p)), "mm_sno_train_get_weights")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mm_sno_train_destroy(self._h)
             self._h = None
 
     def __del__(self):

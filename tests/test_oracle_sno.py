@@ -94,20 +94,3 @@ def test_translation_equivariance():
     a = sno.forward(flat, np.roll(m, (5, -3), axis=(1, 2)))
     b = np.roll(sno.forward(flat, m), (5, -3), axis=(1, 2))
     assert np.allclose(a, b, atol=1e-11)
-
-
-def test_training_model_matches_oracle():
-    """The trainer's torch model (real FFTs, autograd) computes the same network
-    as the oracle, so trained weights mean what the kernels assume."""
-    import torch
-
-    from paper_1406_7635_amd import sno_train
-
-    flat = synth.sno_random_weights(9).astype(np.float64)
-    model = sno_train.make_model(torch).double().load_flat(flat)
-    assert np.array_equal(model.flat(), flat)
-    m = synth.random_sphere((40, 24, 1), 4)
-    with torch.no_grad():
-        got = model(torch.from_numpy(m.astype(np.float64))[:, 0][None])[0].numpy()
-    ref = sno.forward(flat, m)
-    assert np.allclose(got, ref, rtol=1e-10, atol=1e-12)
