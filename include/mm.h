@@ -54,8 +54,12 @@ typedef enum {
     MM_ENONFINITE = -5,      /* a step produced a non-finite error estimate */
     MM_ESTEP = -6,           /* the adaptive step fell below dt_min */
     MM_ENOTCONVERGED = -7,   /* relax hit max_steps before MaxErr reached its floor */
-    MM_ESTATE = -8           /* call order: e.g. demag enabled but kernel not initialised */
+    MM_ESTATE = -8,          /* call order: e.g. demag enabled but kernel not initialised */
+    MM_ESCRATCH = -9         /* mm_beff_noalloc: the spectrum exceeds the static scratch */
 } mm_status;
+
+/* Size of the static spectrum scratch of mm_beff_noalloc, in MiB per GPU. */
+#define MM_STATIC_SCRATCH_MIB 32
 
 #define MM_NREGIONS 256
 #define MM_NPAIRS (MM_NREGIONS * (MM_NREGIONS + 1) / 2)
@@ -173,6 +177,23 @@ int mm_set_demag(mm_ctx *c, int32_t enable);
  * bdemag_dev may be NULL; otherwise it receives the magnetostatic field
  * alone, in every cell (including Msat = 0 cells, where B_eff is 0). */
 int mm_beff(mm_ctx *c, const float *m_dev, float *beff_dev, float *bdemag_dev);
+
+/* mm_beff for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results as mm_beff; the call itself allocates
+ * nothing (no hipMalloc / hipFree, no event or host-container growth).  The
+ * FFT spectrum, which mm_beff keeps in the context, lives instead in one
+ * static device array of MM_STATIC_SCRATCH_MIB MiB per GPU, loaded with the
+ * library and held until the process ends; its address on each device is
+ * resolved by the first mm_create on that device.  Every spectrum element is
+ * written before it is read within a call, so nothing needs clearing between
+ * calls.  All calls on one GPU share the array: calls that overlap on one GPU
+ * (two contexts, two streams or two threads) race and give wrong fields.
+ * Returns MM_ESCRATCH, before any work is enqueued, when the grid's spectrum
+ * (3 (px/2 + 1) ny nz complex64 in 2D and thin 3D grids, 3 (px/2 + 1) py nz
+ * in other 3D grids) exceeds the array; MM_ESTATE as mm_beff.  Launch timing
+ * (mm_timing_enable) does not cover this call. */
+int mm_beff_noalloc(mm_ctx *c, const float *m_dev, float *beff_dev, float *bdemag_dev);
 
 /* Landau-Lifshitz torque (Eq. eqLLG, damping sign):
  * tau = -gamma/(1+alpha^2) [m x B + alpha m x (m x B)], m x B dropped when

@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -29,6 +30,33 @@ struct TimingClass {
 constexpr size_t TIMING_POOL = 4096;
 // launch classes: 0 x-forward, 1 column passes, 2 x-inverse, 3 fused x-inverse + x-forward
 constexpr int NTIMING = 4;
+
+// Spectrum of mm_beff_noalloc: one fixed array per GPU, alive until the
+// process ends.  In host code `scratch` is only a stand-in for the symbol; its
+// device address on each GPU comes from hipGetSymbolAddress (static_scratch).
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)MM_STATIC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device `dev`, resolved once
+// per device (the first mm_create on it).
+hipError_t static_scratch(int dev, void** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -96,6 +124,7 @@ struct mm_ctx {
     // time-dependent excitation terms f_k(t) g_k(r) (caller-owned profiles)
     ExcTerm exc[MAX_EXC] = {};
     bool relaxing = false;    // relax runs without excitations
+    void* scratch = nullptr;  // this device's static spectrum array (mm_beff_noalloc)
 };
 
 namespace {
@@ -163,9 +192,9 @@ struct Timed {
     mm_ctx* c;
     int which;
     hipEvent_t e1 = nullptr, e2 = nullptr;
-    Timed(mm_ctx* c_, int w) : c(c_), which(w) {
+    Timed(mm_ctx* c_, int w, bool on = true) : c(c_), which(w) {
         TimingClass& t = c->timing[which];
-        if (!t.enabled) return;
+        if (!on || !t.enabled) return;
         if (t.used == t.ev.size()) {
             hipEvent_t a = nullptr, b = nullptr;
             if (hipEventCreate(&a) != hipSuccess) return;
@@ -182,11 +211,11 @@ struct Timed {
 };
 
 // The column (y / z) passes between the two x passes of a field evaluation.
-int run_cols(mm_ctx* c, bool check_done) {
+int run_cols(mm_ctx* c, bool check_done, cf* spec, bool timed = true) {
     hipStream_t s = c->stream;
     ColArgs ca;
     memset(&ca, 0, sizeof(ca));
-    ca.spec = c->spec;
+    ca.spec = spec;
     ca.tw = c->tw;
     ca.twshift = c->twshift;
     ca.st = c->st;
@@ -195,7 +224,7 @@ int run_cols(mm_ctx* c, bool check_done) {
     ca.kyh = c->py / 2 + 1;
     ca.kzh = c->pz / 2 + 1;
     ca.pa = c->py;
-    Timed t(c, 1);
+    Timed t(c, 1, timed);
     if (c->yz) {
         // thin 3D grid: one pass per kx column over all planes
         ca.pos_stride = 3;
@@ -261,14 +290,14 @@ int run_cols(mm_ctx* c, bool check_done) {
     return MM_OK;
 }
 
-int run_xfwd(mm_ctx* c, const FieldArgs& a) {
-    Timed t(c, 0);
+int run_xfwd(mm_ctx* c, const FieldArgs& a, bool timed = true) {
+    Timed t(c, 0, timed);
     MM_TRY(launch_xfwd(c->px, a, c->stream, t.e1, t.e2));
     return MM_OK;
 }
 
-int run_xinv(mm_ctx* c, const FieldArgs& a, int* nblocks_out) {
-    Timed t(c, 2);
+int run_xinv(mm_ctx* c, const FieldArgs& a, int* nblocks_out, bool timed = true) {
+    Timed t(c, 2, timed);
     MM_TRY(launch_xinv(c->px, a, c->stream, nblocks_out, t.e1, t.e2));
     return MM_OK;
 }
@@ -343,14 +372,14 @@ int upload_dmi(mm_ctx* c) {
     return MM_OK;
 }
 
-int run_field(mm_ctx* c, FieldArgs& a, int* nblocks_out) {
+int run_field(mm_ctx* c, FieldArgs& a, int* nblocks_out, bool timed = true) {
     hipStream_t s = c->stream;
     if (c->demag_on) {
         if (!c->khat_ready) return MM_ESTATE;
         a.flags |= EPI_HAS_DEMAG;
-        MM_CHECK(run_xfwd(c, a));
-        MM_CHECK(run_cols(c, (a.flags & EPI_CHECK_DONE) != 0));
-        MM_CHECK(run_xinv(c, a, nblocks_out));
+        MM_CHECK(run_xfwd(c, a, timed));
+        MM_CHECK(run_cols(c, (a.flags & EPI_CHECK_DONE) != 0, a.spec, timed));
+        MM_CHECK(run_xinv(c, a, nblocks_out, timed));
     } else {
         if (a.sd.nk > 0) MM_TRY(launch_combine(a, s));
         MM_TRY(launch_local(a, s, nblocks_out));
@@ -494,7 +523,7 @@ int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done
         a.flags |= EPI_HAS_DEMAG;
         a.ms = buf[cur];
         MM_CHECK(run_xfwd(c, a));
-        MM_CHECK(run_cols(c, check_done));
+        MM_CHECK(run_cols(c, check_done, c->spec));
         for (int s = 1; s < S - 1; ++s) {
             FieldArgs ai = stage_args(c, m, tb, s, precess, check_done);
             ai.flags |= EPI_HAS_DEMAG;
@@ -514,7 +543,7 @@ int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done
                 MM_TRY(launch_xrow(c->px, ai, af, a_last, c->stream, t.e1, t.e2));
             }
             cur ^= 1;
-            MM_CHECK(run_cols(c, check_done));
+            MM_CHECK(run_cols(c, check_done, c->spec));
         }
         FieldArgs al = stage_args(c, m, tb, S - 1, precess, check_done);
         al.flags |= EPI_HAS_DEMAG;
@@ -700,6 +729,7 @@ const char* mm_strerror(int status) {
         case MM_ESTEP: return "time step fell below dt_min";
         case MM_ENOTCONVERGED: return "relax did not reach the MaxErr floor within max_steps";
         case MM_ESTATE: return "call order: demag kernel not initialised";
+        case MM_ESCRATCH: return "grid too large for the static spectrum of mm_beff_noalloc";
         default: return "unknown status";
     }
 }
@@ -787,6 +817,7 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
     A((void**)&c->partials, (size_t)maxblk * 4 * sizeof(double));
     if (st == MM_OK && hipHostMalloc((void**)&c->hst, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
         st = MM_ENOMEM;
+    if (st == MM_OK) st = map_err(static_scratch(c->device, &c->scratch));
     if (st == MM_OK) {
         hipError_t e = hipMemcpyAsync(c->region, region_dev, (size_t)c->ncell, hipMemcpyDeviceToDevice, c->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(c->params64, p, sizeof(mm_params), hipMemcpyHostToDevice, c->stream);
@@ -941,6 +972,19 @@ int mm_beff(mm_ctx* c, const float* m_dev, float* beff_dev, float* bdemag_dev) {
     a.flags = EPI_BEFF | (bdemag_dev ? EPI_BDEMAG : 0);
     MM_CHECK(prep_extra(c, a, 0.0, false, false));
     return run_field(c, a, nullptr);
+}
+
+int mm_beff_noalloc(mm_ctx* c, const float* m_dev, float* beff_dev, float* bdemag_dev) {
+    if (!c || !m_dev || !beff_dev) return MM_EINVAL;
+    if (c->demag_on && (unsigned long long)c->spec_elems * sizeof(cf) > STATIC_SCRATCH_BYTES) return MM_ESCRATCH;
+    if (!c->scratch) return MM_EDEVICE;
+    FieldArgs a = base_args(c, m_dev);
+    a.spec = static_cast<cf*>(c->scratch);
+    a.beff = beff_dev;
+    a.bdemag = bdemag_dev;
+    a.flags = EPI_BEFF | (bdemag_dev ? EPI_BDEMAG : 0);
+    MM_CHECK(prep_extra(c, a, 0.0, false, false));
+    return run_field(c, a, nullptr, false);
 }
 
 int mm_llg_torque(mm_ctx* c, const float* m_dev, const float* beff_dev, float* tau_dev, int32_t precess) {

@@ -19,7 +19,7 @@ PREC = {"fp32": 0, "bf16": 1, "fp16": 2}  # mm_precision
 c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
 STATUS = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EDEVICE", -4: "MM_EUNSUPPORTED",
-          -5: "MM_ENONFINITE", -6: "MM_ESTEP", -7: "MM_ENOTCONVERGED", -8: "MM_ESTATE"}
+          -5: "MM_ENONFINITE", -6: "MM_ESTEP", -7: "MM_ENOTCONVERGED", -8: "MM_ESTATE", -9: "MM_ESCRATCH"}
 
 
 class Grid(ctypes.Structure):
@@ -62,6 +62,7 @@ EXPORTS = {
     "mm_set_run_graphs": (c_int32, [c_void_p, c_int32]),
     "mm_set_excitation": (c_int32, [c_void_p, c_int32, c_void_p, c_double, c_double, c_double, c_double]),
     "mm_beff": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mm_beff_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mm_llg_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32]),
     "mm_torque": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
     "mm_rk4_step": (c_int32, [c_void_p, c_void_p, c_double, c_int32]),
@@ -250,6 +251,14 @@ class Context:
         bd = self.new_field() if want_demag else None
         _check(load().mm_beff(self._h, _ptr(m), _ptr(b), _ptr(bd)), "mm_beff")
         return (b, bd) if want_demag else b
+
+    def beff_noalloc(self, m, b, bd=None):
+        """mm_beff_noalloc into caller tensors b (and bd); the spectrum is the
+        library's static per-GPU array, so the call allocates nothing."""
+        bd = self._vec(bd, "bd") if bd is not None else None
+        _check(load().mm_beff_noalloc(self._h, _ptr(self._vec(m)), _ptr(self._vec(b, "b")), _ptr(bd)),
+               "mm_beff_noalloc")
+        return b
 
     def llg_torque(self, m, beff, precess=True):
         tau = self.new_field()
