@@ -39,9 +39,13 @@ __host__ __device__ inline int ilog2_rt(int n) {
     return l;
 }
 
-// one spare element every 8 spreads stride-8 Stockham writes over the LDS banks
-__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 3); }
-__host__ __device__ constexpr int seq_len(int P) { return P + (P >> 3); }
+// LDS position of sequence element i: three spare elements after every 32.
+// The contiguous reads of a wave then meet at most one spare run and the
+// Stockham writes of stride 1, 4 and 32 land on nearly disjoint banks; being
+// additive, the per-register offsets still fold into the instructions'
+// immediate offsets.
+__host__ __device__ constexpr int lds_pad(int i) { return i + 3 * (i >> 5); }
+__host__ __device__ constexpr int seq_len(int P) { return P + 3 * (P >> 5); }
 
 // R-point DFTs in registers -------------------------------------------------
 template <int R, bool INV>

@@ -793,8 +793,10 @@ __device__ inline void yz_body(const ColArgs& a, int blk, cf* lds, int tid) {
 // (three sequences through one LDS exchange buffer).  The K^ product is then
 // local to the thread, and the twiddles and exchange addresses of a stage
 // serve all three components.  Workgroup: T columns of TPF threads; LDS per
-// column: the exchange buffer, then a region that holds the column's K^ rows
-// (or, in the workgroup of the packed DC/Nyquist column, a second buffer).
+// column: the exchange buffer and a second one that only the workgroup of the
+// packed DC/Nyquist column uses.  The K^ rows come straight from global
+// memory (L2 / MALL) at the product: staging them in LDS before the forward
+// transforms made every workgroup wait for them before its first butterfly.
 template <int P>
 struct Col3Cfg {
     static constexpr int TPF = Cfg<P>::TPF;
@@ -802,8 +804,7 @@ struct Col3Cfg {
     static constexpr int NTH = T * TPF;
     static constexpr int SEQ = seq_len(P);
     static constexpr int KHP = P / 2 + 1;
-    // complex elements per column: buffer + max(K^ rows (2 cf each), buffer)
-    static constexpr int CL = SEQ + (2 * KHP > SEQ ? 2 * KHP : SEQ);
+    static constexpr int CL = 2 * SEQ;  // complex elements per column
 };
 
 // the three-components-per-thread 2D convolution serves 64 <= P <= 2048
@@ -819,11 +820,11 @@ constexpr size_t col3_lds() {
 
 template <int P>
 __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
-    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, T = Col3Cfg<P>::T, NTH = Col3Cfg<P>::NTH;
+    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, T = Col3Cfg<P>::T;
     constexpr int SEQ = Col3Cfg<P>::SEQ, KHP = Col3Cfg<P>::KHP, CL = Col3Cfg<P>::CL, MH = PPT / 2;
     if (a.check_done && a.st->done) return;
     const int t = tid % TPF, ci = tid / TPF;
-    const int c0 = blk * T, c = c0 + ci;
+    const int c = blk * T + ci;
     const bool valid = c < a.ncol;
     const bool wg_packed = a.pack_col > 0 && blk == 0;  // uniform over the workgroup
     const bool packed = wg_packed && ci == 0;
@@ -831,6 +832,7 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
     cf* reg2 = buf + SEQ;
     const cf* base = a.spec + (long long)(valid ? c : 0) * a.col_stride;
     const cf* baseN = a.spec + (long long)a.pack_col * a.col_stride;
+    const float4* kh = reinterpret_cast<const float4*>(a.khat);
 
     // rows y < ny <= P/2 hold data; the rest is zero padding
     cf v[3][PPT];
@@ -845,36 +847,23 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
             v[k][m] = x;
         }
     }
-    // the K^ rows of every column of the workgroup into LDS (their latency
-    // overlaps that of the column loads); column kx is contiguous
-    {
-        constexpr int TOT = T * KHP, NIT = (TOT + NTH - 1) / NTH;
-        const float4* kh = reinterpret_cast<const float4*>(a.khat);
-        float4 kt[NIT];
-#pragma unroll
-        for (int i = 0; i < NIT; ++i) {
-            const int e = tid + NTH * i;
-            const int ce = e / KHP, r = e - ce * KHP;
-            const bool in = (i < NIT - 1 || e < TOT) && c0 + ce < a.ncol;
-            kt[i] = in ? kh[(long long)(c0 + ce) * KHP + r] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int i = 0; i < NIT; ++i) {
-            const int e = tid + NTH * i;
-            const int ce = e / KHP, r = e - ce * KHP;
-            if (i < NIT - 1 || e < TOT) reinterpret_cast<float4*>(lds + ce * CL + SEQ)[r] = kt[i];
-        }
-    }
     RegFft<P, TPF, 3, false, true>::run(v, buf, a.tw, a.twshift, t);
 
-    // B^ = K^ M^ (2D: K^ = [[xx, xy, 0], [xy, yy, 0], [0, 0, zz]], xy odd in y)
+    // B^ = K^ M^ (2D: K^ = [[xx, xy, 0], [xy, yy, 0], [0, 0, zz]], xy odd in y);
+    // row q of column kx is (xx, yy, zz, xy) at K^[kx][min(q, P - q)]
     if (!wg_packed) {
-        const float4* lk = reinterpret_cast<const float4*>(reg2);
+        const float4* kc = kh + (long long)(valid ? c : 0) * KHP;
+        float4 kg[PPT];
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
+            const int q = t + TPF * m;
+            kg[m] = kc[2 * q > P ? P - q : q];
+        }
 #pragma unroll
         for (int m = 0; m < PPT; ++m) {
             const int q = t + TPF * m;
             const bool fq = 2 * q > P;
-            const float4 k4 = lk[fq ? P - q : q];
+            const float4 k4 = kg[m];
             const float kxy = fq ? -k4.w : k4.w;
             const cf mx = v[0][m], my = v[1][m];
             v[0][m] = k4.x * mx + kxy * my;
@@ -885,12 +874,13 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
         // Packed column Z = A0 + i AN (A0: kx = 0, AN: kx = px/2, both real along
         // y): B = K0 A0 + i KN AN = Kp Z(q) + Km conj Z(-q), Kp = (K0 + KN)/2,
         // Km = (K0 - KN)/2.  Z(-q) comes through LDS: z first (one buffer), then
-        // x and y together (two buffers).
+        // x and y together (two buffers).  The other columns of this workgroup
+        // (T > 1) take the plain product.
         auto kpm = [&](int q, float4& kp, float4& km) {
             const bool fq = 2 * q > P;
             const int qh = fq ? P - q : q;
-            float4 k0 = reinterpret_cast<const float4*>(a.khat)[qh];
-            float4 kn = reinterpret_cast<const float4*>(a.khat)[(long long)a.pack_col * KHP + qh];
+            float4 k0 = kh[qh];
+            float4 kn = kh[(long long)a.pack_col * KHP + qh];
             if (fq) {
                 k0.w = -k0.w;
                 kn.w = -kn.w;
@@ -936,12 +926,12 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
                 v[1][m] = kp.w * zx + kp.y * zy + km.w * xr + km.y * yr;
             }
         } else {
-            const float4* lk = reinterpret_cast<const float4*>(reg2);
+            const float4* kc = kh + (long long)(valid ? c : 0) * KHP;
 #pragma unroll
             for (int m = 0; m < PPT; ++m) {
                 const int q = t + TPF * m;
                 const bool fq = 2 * q > P;
-                const float4 k4 = lk[fq ? P - q : q];
+                const float4 k4 = kc[fq ? P - q : q];
                 const float kxy = fq ? -k4.w : k4.w;
                 const cf mx = v[0][m], my = v[1][m];
                 v[0][m] = k4.x * mx + kxy * my;
@@ -952,17 +942,17 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
     }
     RegFft<P, TPF, 3, true>::run(v, buf, a.tw, a.twshift, t);
 
-    // rows y < ny <= P/2 are kept
+    // rows y < ny <= P/2 are kept; one component after the other
     cf* out = a.spec + (long long)(valid ? c : 0) * a.col_stride;
     cf* outN = a.spec + (long long)a.pack_col * a.col_stride;
     int t2 = t;
     asm volatile("" : "+v"(t2));  // form the store addresses here, not at load time
 #pragma unroll
-    for (int m = 0; m < MH; ++m) {
-        const int q = t2 + TPF * m;
-        if (valid && q < a.n_out) {
+    for (int k = 0; k < 3; ++k) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
+        for (int m = 0; m < MH; ++m) {
+            const int q = t2 + TPF * m;
+            if (valid && q < a.n_out) {
                 if (!packed) {
                     out[3LL * q + k] = v[k][m];
                 } else {
