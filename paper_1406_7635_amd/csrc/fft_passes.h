@@ -355,14 +355,12 @@ __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds
     EpiAcc acc;
     epi_init(acc);
     const float* mp = a.sd.nk > 0 || FUSED ? a.ms : a.m0;
-    for (int idx = tid; idx < 2 * GI * a.nx; idx += NTH) {
-        const int rr = idx / a.nx, x = idx - rr * a.nx;
-        const int row = 2 * pair0 + rr;
-        if (row >= a.nrows) continue;
+    // one cell of row rr at x; rows past the grid are skipped
+    auto cell = [&](int rr, int x, int y, int z) {
         cf* b3 = lds + (rr >> 1) * GL;
         const cf v01 = b3[(rr & 1) * SEQ + lds_pad(x)];
         const cf v2 = b3[2 * SEQ + lds_pad(x)];
-        const int z = row / a.ny, y = row - z * a.ny;
+        const int row = 2 * pair0 + rr;
         const float3 tq = epilogue<DMI>(a, rs, lut_l, mp, (long long)row * a.nx + x, x, y, z,
                                    make_float3(v01.x, v01.y, (rr & 1) ? v2.y : v2.x), acc);
         if constexpr (FUSED) {
@@ -370,6 +368,26 @@ __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds
             ks_stage<P>(b3, 0)[o] = tq.x;
             ks_stage<P>(b3, 1)[o] = tq.y;
             ks_stage<P>(b3, 2)[o] = tq.z;
+        }
+    };
+    constexpr int NROW = 2 * GI;
+    if constexpr (NTH % NROW == 0) {
+        // NTH / NROW threads per row: the row (and its y, z) is fixed per
+        // thread, x advances by a compile-time stride
+        constexpr int TR = NTH / NROW;
+        const int rr = tid / TR, x0 = tid - rr * TR;
+        const int row = 2 * pair0 + rr;
+        if (row < a.nrows) {
+            const int z = row / a.ny, y = row - z * a.ny;
+            for (int x = x0; x < a.nx; x += TR) cell(rr, x, y, z);
+        }
+    } else {
+        for (int idx = tid; idx < NROW * a.nx; idx += NTH) {
+            const int rr = idx / a.nx, x = idx - rr * a.nx;
+            const int row = 2 * pair0 + rr;
+            if (row >= a.nrows) continue;
+            const int z = row / a.ny, y = row - z * a.ny;
+            cell(rr, x, y, z);
         }
     }
     // the fused pass serves inner stages only (no error norm, no reductions)
