@@ -399,7 +399,9 @@ def thermal_variant(steps, warmup):
     ncell = n * n
     launches = -(-steps // HEUN_UNCOUPLED_CHUNK)
     gbs = HEUN_UNCOUPLED_BYTES_PER_CELL_PER_LAUNCH * ncell * launches / wall / 1e9
-    return {"value": ncell * st["evals"] / wall, "unit": "Beff evals*cells/s", "us_per_step": 1e6 * wall / steps,
+    return {"value": ncell * st["evals"] / wall, "unit": "Beff evals*cells/s (uncoupled cells, no demag)",
+            "us_per_step": 1e6 * wall / steps,
+            "comparable_to_metric": False,
             "steps": st["steps"], "cell_steps_per_s": ncell * steps / wall, "bound": "alu",
             "alg_GBs": gbs, "path": "uncoupled cells: one launch per chunk of up to %d steps" % HEUN_UNCOUPLED_CHUNK,
             "switching_rate_per_s": f_meas, "eq_switch_rate_per_s": f_th,
@@ -568,6 +570,12 @@ def main():
         per[k]["gbs"] = bytes_per_launch[k] / (per[k]["avg_us"] * 1e-6) / 1e9
     ach = per[dominant]["gbs"]
     traffic = measured_traffic(args.traffic, args.n).get(dominant)
+    # whole path: the algorithmic bytes of one attempt (x-forward, 6 column
+    # passes, 5 fused passes, x-inverse with the error norm, and the
+    # commit's read + write of m) over the measured time per attempt
+    path_bytes = (bytes_per_launch["x_forward"] + 6 * bytes_per_launch["column_conv"] +
+                  5 * bytes_per_launch["x_row"] + bytes_per_launch["x_inverse"] + 24 * ncell)
+    path_gbs = path_bytes / (wall / args.steps) / 1e9
     out = {
         "metric": METRIC, "value": value, "unit": "Beff evals*cells/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
@@ -580,7 +588,9 @@ def main():
                    "kernel_timing": "second pass of %d attempts, dispatch-recorded HIP events" % args.steps},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
-                     "copy_GBs": copy_gbs, "frac_of_copy": ach / copy_gbs},
+                     "copy_GBs": copy_gbs, "frac_of_copy": ach / copy_gbs,
+                     "path": {"alg_bytes_per_step": path_bytes, "achieved": path_gbs,
+                              "frac": path_gbs / HBM_PEAK_GBS, "frac_of_copy": path_gbs / copy_gbs}},
         "kernels": per,
     }
     out["variants"] = mfma_variants(ctx, m, opts, ncell, args.steps)

@@ -51,17 +51,6 @@ def build(verbose=False):
     return LIB
 
 
-def build_fft_host_check():
-    """Host executable emulating the LDS FFT stages (fft_host_check.cpp)."""
-    os.makedirs(OBJ, exist_ok=True)
-    exe = os.path.join(OBJ, "fft_host_check")
-    cmd = [HIPCC] + FLAGS + ["-x", "hip", os.path.join(CSRC, "fft_host_check.cpp"), "-o", exe]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
-    return exe
-
-
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

@@ -52,10 +52,62 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(mm.Grid) == 3 * 4 + 4 + 3 * 8 + 3 * 4 + 4  # natural alignment padding
 
 
+def build_fft_host_check(sanitize=False):
+    """The host emulation of the LDS FFT stages (tests/fft_host_check.cpp);
+    with sanitize, host code built with AddressSanitizer and UBSan."""
+    os.makedirs(mmbuild.OBJ, exist_ok=True)
+    exe = os.path.join(mmbuild.OBJ, "fft_host_check" + ("_san" if sanitize else ""))
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fft_host_check.cpp")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer"] if sanitize else []
+    cmd = [mmbuild.HIPCC] + mmbuild.FLAGS + san + ["-x", "hip", src, "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, " ".join(cmd) + "\n" + r.stderr
+    return exe
+
+
 def test_fft_stage_emulation():
     """Host emulation of the LDS Stockham FFT (every length 1..4096, both
     directions) against a direct DFT."""
-    exe = mmbuild.build_fft_host_check()
+    exe = build_fft_host_check()
     r = subprocess.run([exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "ALL OK" in r.stdout
+
+
+def test_fft_stage_emulation_sanitized():
+    """The same emulation with AddressSanitizer and UBSan on the host code."""
+    exe = build_fft_host_check(sanitize=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "ALL OK" in r.stdout
+    assert "runtime error" not in r.stderr
+
+
+def test_abi_validation_sanitized():
+    """Argument validation and error cleanup of the C ABI's host code, built
+    with AddressSanitizer (leak checks included) and UBSan and run without a
+    GPU (tests/abi_host_check.cpp): every documented status, no report."""
+    os.makedirs(mmbuild.OBJ, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer"]
+    objs = []
+    for src in [x for x in mmbuild.SOURCES if x.endswith(".cpp")]:
+        obj = os.path.join(mmbuild.OBJ, "san_" + os.path.splitext(src)[0] + ".o")
+        cmd = [mmbuild.HIPCC] + mmbuild.FLAGS + san + ["-x", "hip", "-c", os.path.join(mmbuild.CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        assert r.returncode == 0, " ".join(cmd) + "\n" + r.stderr
+        objs.append(obj)
+    kern = [os.path.join(mmbuild.OBJ, os.path.splitext(x)[0] + ".o") for x in mmbuild.SOURCES if x.endswith(".hip")]
+    if not all(os.path.exists(k) for k in kern):
+        mmbuild.build()
+    exe = os.path.join(mmbuild.OBJ, "abi_host_check_san")
+    drv = os.path.join(os.path.dirname(os.path.abspath(__file__)), "abi_host_check.cpp")
+    cmd = [mmbuild.HIPCC] + mmbuild.FLAGS + san + ["-x", "hip", drv, "-x", "none"] + objs + kern + ["-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, " ".join(cmd) + "\n" + r.stderr
+    env = dict(os.environ, HIP_VISIBLE_DEVICES="-1", ROCR_VISIBLE_DEVICES="-1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "ALL OK" in r.stdout
+    assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
