@@ -322,8 +322,11 @@ def size_sweep():
 
 def grains_variant(steps, warmup):
     """The 3D workload: 256 x 256 x 64 cells of 3 nm, 256 Voronoi grains
-    (random m, the worst-case spectrum), plain FP32 Dormand-Prince: throughput
-    and the three-pass 3D path's algorithmic bytes."""
+    (random m, the worst-case spectrum), Dormand-Prince with the column passes
+    (y forward, z convolution, y inverse) in FP32 and with their DFT stages on
+    the matrix cores (BF16 / FP16 split precision): throughput of each from the
+    same state, the three-pass path's algorithmic bytes, and each matrix-core
+    form's B_demag difference from the FP32 path at that state."""
     import torch
 
     from paper_1406_7635_amd import mm, synth
@@ -331,23 +334,37 @@ def grains_variant(steps, warmup):
     case = synth.grains(seed=3)
     ncell = int(np.prod(case["grid"]))
     ctx = mm.Context(case["grid"], case["cell"], case["region"], case["params"])
-    m = torch.from_numpy(case["m0"]).cuda()
+    m0 = torch.from_numpy(case["m0"]).cuda()
     opts = mm.solver_opts(max_err=1e-5)
-    t, dt, _ = ctx.run(m, float("inf"), dt=1e-14, max_attempts=warmup, opts=opts)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    t, dt, st = ctx.run(m, float("inf"), t=t, dt=dt, max_attempts=steps, opts=opts)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ctx.close()
     b_att = ensemble_attempt_bytes([case])
-    gbs = b_att * steps / wall / 1e9
-    return {"value": ncell * st["evals"] / wall, "unit": "Beff evals*cells/s", "ms_per_attempt": 1e3 * wall / steps,
-            "attempts": steps, "accepted": st["steps"], "alg_bytes_per_attempt": b_att, "alg_GBs": gbs,
-            "alg_frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
-            "workload": "256x256x64 grains, 3 nm cells, 256 Voronoi regions (Msat U(6e5,1e6), Ku1 U(0,5e5), "
-                        "S 0.9), random m; DP45 MaxErr 1e-5; plain FP32 (y-forward, z convolution, y-inverse)",
-            "dtype": "f32"}
+    out = {}
+    bd32 = None
+    for prec in ("fp32", "bf16", "fp16"):
+        ctx.set_conv_precision(prec)
+        m = m0.clone()
+        _, bd = ctx.beff(m, want_demag=True)
+        if prec == "fp32":
+            bd32 = bd
+        diff = float((bd - bd32).abs().max() / bd32.abs().max())
+        t, dt, _ = ctx.run(m, float("inf"), dt=1e-14, max_attempts=warmup, opts=opts)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        t, dt, st = ctx.run(m, float("inf"), t=t, dt=dt, max_attempts=steps, opts=opts)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        gbs = b_att * steps / wall / 1e9
+        out[prec] = {"value": ncell * st["evals"] / wall, "ms_per_attempt": 1e3 * wall / steps,
+                     "attempts": steps, "accepted": st["steps"], "alg_GBs": gbs,
+                     "alg_frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "demag_rel_diff_vs_fp32": diff}
+    ctx.close()
+    res = dict(out["fp32"])
+    res.update({"unit": "Beff evals*cells/s", "alg_bytes_per_attempt": b_att,
+                "matrix_core": {"bf16": out["bf16"], "fp16": out["fp16"]},
+                "workload": "256x256x64 grains, 3 nm cells, 256 Voronoi regions (Msat U(6e5,1e6), Ku1 U(0,5e5), "
+                            "S 0.9), random m; DP45 MaxErr 1e-5; column passes FP32 (value) and matrix-core "
+                            "split BF16 / FP16",
+                "dtype": "f32"})
+    return res
 
 
 # the uncoupled Heun path moves m (12 B read, 12 B written) and the region

@@ -370,11 +370,14 @@ int mm_timing_read(mm_ctx *c, int32_t which, int64_t *launches, double *total_ms
  * default) runs them in FP32 on the vector units.  MM_PREC_BF16 and
  * MM_PREC_FP16 run them as matrix-core GEMMs (16 x 16 x 32) on operands split
  * into two low-precision parts, x = x_hi + x_lo, keeping hi.hi + hi.lo + lo.hi
- * in FP32 accumulators (FP16 inputs scaled per column by powers of two); the
- * K^ product, the twiddles and everything outside the y pass stay FP32.  The
- * matrix-core form exists for 2D grids whose padded y length is 2048; other
- * grids return MM_EUNSUPPORTED and keep FP32.  Takes effect for later field
- * evaluations; the FSAL derivative is recomputed. */
+ * in FP32 accumulators (FP16 inputs scaled per column, or per workgroup of
+ * columns in 3D, by powers of two); the K^ product, the twiddles and
+ * everything outside the column passes stay FP32.  The matrix-core form
+ * exists for 2D grids whose padded y length is 2048 (the y convolution) and
+ * for 3D grids of more than four layers whose padded y and z lengths lie in
+ * 64 ... 1024 (y forward, z convolution and y inverse); other grids return
+ * MM_EUNSUPPORTED and keep FP32.  Takes effect for later field evaluations;
+ * the FSAL derivative is recomputed. */
 typedef enum { MM_PREC_FP32 = 0, MM_PREC_BF16 = 1, MM_PREC_FP16 = 2 } mm_precision;
 int mm_set_conv_precision(mm_ctx *c, int32_t prec);
 

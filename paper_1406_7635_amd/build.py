@@ -21,7 +21,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
-SOURCES = ["kernels_fft.hip", "kernels_mfma.hip", "kernels_batch.hip", "kernels_local.hip", "kernels_demag.hip",
+SOURCES = ["kernels_fft.hip", "kernels_mfma.hip", "kernels_mfma3d.hip", "kernels_batch.hip", "kernels_local.hip", "kernels_demag.hip",
            "kernels_sno.hip", "kernels_sno_train.hip", "kernels_thermal.hip", "mm_api.cpp", "mm_batch.cpp",
            "mm_sno.cpp", "mm_sno_train.cpp"]
 

@@ -245,10 +245,16 @@ int run_cols(mm_ctx* c, bool check_done, cf* spec, bool timed = true) {
         ca.outer_stride = c->colstride;
         ca.nouter = c->kx;
         const bool ypass = c->py > 1;
+        // matrix-core DFT stages (BF16 / FP16 split products) when selected
+        const bool mc = c->conv_prec != MM_PREC_FP32;
+        if (mc) ca.dft_tab = c->dft_tab;
         if (ypass) {
             ca.n_in = c->ny;
             ca.n_out = c->py;
-            MM_TRY(launch_col(c->py, COL_FWD, ca, 6, s, t.e1, nullptr));
+            if (mc)
+                MM_TRY(launch_colm3d(c->py, COL_FWD, c->conv_prec, ca, s, t.e1, nullptr));
+            else
+                MM_TRY(launch_col(c->py, COL_FWD, ca, 6, s, t.e1, nullptr));
         }
         // z convolution of every (kx, ky) column; tiles of adjacent ky
         ca.pos_stride = c->zstride;
@@ -258,7 +264,10 @@ int run_cols(mm_ctx* c, bool check_done, cf* spec, bool timed = true) {
         ca.nouter = c->kx;
         ca.n_in = c->nz;
         ca.n_out = c->nz;
-        MM_TRY(launch_col(c->pz, COL_CONV, ca, 6, s, ypass ? nullptr : t.e1, ypass ? nullptr : t.e2));
+        if (mc)
+            MM_TRY(launch_colm3d(c->pz, COL_CONV, c->conv_prec, ca, s, ypass ? nullptr : t.e1, ypass ? nullptr : t.e2));
+        else
+            MM_TRY(launch_col(c->pz, COL_CONV, ca, 6, s, ypass ? nullptr : t.e1, ypass ? nullptr : t.e2));
         if (ypass) {
             ca.pos_stride = 3;
             ca.col_stride = c->zstride;
@@ -267,7 +276,10 @@ int run_cols(mm_ctx* c, bool check_done, cf* spec, bool timed = true) {
             ca.nouter = c->kx;
             ca.n_in = c->py;
             ca.n_out = c->ny;
-            MM_TRY(launch_col(c->py, COL_INV, ca, 6, s, nullptr, t.e2));
+            if (mc)
+                MM_TRY(launch_colm3d(c->py, COL_INV, c->conv_prec, ca, s, nullptr, t.e2));
+            else
+                MM_TRY(launch_col(c->py, COL_INV, ca, 6, s, nullptr, t.e2));
         }
     } else {
         // 2D: y convolution of every kx column; the DC and Nyquist columns
@@ -826,6 +838,7 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
         if (e == hipSuccess) e = configure_field_kernels(c->px, c->py, c->pz);
         if (e == hipSuccess) e = launch_dft_tables(c->dft_tab, c->stream);
         if (e == hipSuccess) e = configure_colm();
+        if (e == hipSuccess) e = configure_colm3d();
         if (e == hipSuccess)
             e = launch_set_state(c->st, 0.0, 1e-14, INFINITY, 1e-5, 0.8, 0.0, 0.0, 4, 1, 1, 0, c->stream);
         if (e == hipSuccess) e = launch_set_therm_step(c->st, 0, c->stream);
@@ -1320,7 +1333,13 @@ int mm_exchange_dump(mm_ctx* c, float* out_dev) {
 int mm_set_conv_precision(mm_ctx* c, int32_t prec) {
     if (!c) return MM_EINVAL;
     if (prec != MM_PREC_FP32 && prec != MM_PREC_BF16 && prec != MM_PREC_FP16) return MM_EINVAL;
-    if (prec != MM_PREC_FP32 && !(c->pz == 1 && c->py == 2048 && c->px >= 2)) return MM_EUNSUPPORTED;
+    if (prec != MM_PREC_FP32) {
+        // 2D: the y convolution at padded y length 2048; 3D (the three-pass
+        // column path): padded y and z lengths the matrix-core passes serve
+        const bool film = c->pz == 1 && c->py == 2048 && c->px >= 2;
+        const bool vol = c->pz > 1 && !c->yz && (c->py == 1 || colm3d_supported(c->py)) && colm3d_supported(c->pz);
+        if (!film && !vol) return MM_EUNSUPPORTED;
+    }
     MM_TRY(hipStreamSynchronize(c->stream));
     c->conv_prec = prec;
     c->fsal_valid = false;

@@ -139,6 +139,12 @@ hipError_t launch_colm(int p, int prec, const ColArgs& a, hipStream_t s, hipEven
                        hipEvent_t e1 = nullptr);
 hipError_t launch_dft_tables(void* tab, hipStream_t s);
 hipError_t configure_colm(void);
+// Matrix-core column passes of 3D grids (y forward / inverse, z convolution)
+// for padded lengths 64 ... 1024; mode COL_FWD, COL_INV or COL_CONV.
+bool colm3d_supported(int p);
+hipError_t launch_colm3d(int p, int mode, int prec, const ColArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
+hipError_t configure_colm3d(void);
 
 // Fused x-inverse of one stage and x-forward of the next (px >= 8): ai is the
 // finishing stage (reads m_s from ai.ms), af the next one (its combine holds
