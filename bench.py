@@ -157,6 +157,35 @@ def cpu_baseline(case, reps=5):
                       % (reps, case["grid"][0], case["grid"][1], case["grid"][2], threads, t_init)}
 
 
+def periodic_variant(n, steps, warmup):
+    """The vortex film made periodic in x and y (one image per side): the
+    periodic axes are transformed at their own length (no zero padding), so
+    every transform is half as long and the spectrum a quarter of the open
+    film's.  Dormand-Prince throughput from the vortex state."""
+    import torch
+
+    from paper_1406_7635_amd import mm, synth
+
+    case = synth.vortex_film(seed=2, n=n)
+    ncell = int(np.prod(case["grid"]))
+    ctx = mm.Context(case["grid"], case["cell"], case["region"], case["params"], pbc=(1, 1, 0))
+    info = ctx.info()
+    m = torch.from_numpy(case["m0"]).cuda()
+    opts = mm.solver_opts(max_err=1e-5)
+    t, dt, _ = ctx.run(m, float("inf"), dt=1e-14, max_attempts=warmup, opts=opts)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t, dt, st = ctx.run(m, float("inf"), t=t, dt=dt, max_attempts=steps, opts=opts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ctx.close()
+    return {"value": ncell * st["evals"] / wall, "unit": "Beff evals*cells/s", "ms_per_attempt": 1e3 * wall / steps,
+            "attempts": steps, "accepted": st["steps"], "padded": [info["px"], info["py"], info["pz"]],
+            "workload": "vortex film %dx%dx1 periodic in x and y (1 image per side), 2 nm cells; RK45 MaxErr 1e-5; "
+                        "plain FP32, periodic axes unpadded" % (n, n),
+            "dtype": "f32"}
+
+
 def mfma_variants(ctx, m, opts, ncell, steps):
     """The same RK45 attempts with the y-convolution DFT stages on the matrix
     cores (BF16 / FP16 split precision): throughput, column-pass duration and
@@ -508,6 +537,7 @@ def main():
     ap.add_argument("--no-grains", action="store_true", help="skip the 3D grain-workload variant")
     ap.add_argument("--no-sweep", action="store_true", help="skip the n x n x 1 size sweep")
     ap.add_argument("--no-thermal", action="store_true", help="skip the thermal-switching (Heun) variant")
+    ap.add_argument("--no-periodic", action="store_true", help="skip the periodic-film variant")
     ap.add_argument("--grains-only", action="store_true",
                     help="only the 3D grain-workload variant (one JSON line; for profiling)")
     ap.add_argument("--surrogate-only", action="store_true",
@@ -620,6 +650,8 @@ def main():
         out["variants"]["grains"] = grains_variant(max(5, args.steps // 20), max(2, args.warmup // 10))
     if not args.no_sweep:
         out["variants"]["size_sweep"] = size_sweep()
+    if not args.no_periodic:
+        out["variants"]["periodic"] = periodic_variant(args.n, args.steps, args.warmup)
     if not args.no_thermal:
         out["variants"]["thermal"] = thermal_variant(max(200, args.steps * 10), max(20, args.warmup))
     if not args.no_cpu:

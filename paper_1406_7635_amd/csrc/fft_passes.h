@@ -149,9 +149,10 @@ __device__ inline float* ks_stage(cf* gbuf, int c) {
 // zero-padded rows, separation of the two real transforms, staged coalesced
 // spectrum write.  The region table is in LDS at lut_l once the first barrier
 // has passed (the non-fused pass writes it from lut after issuing its loads).
-template <int P, bool FUSED>
+template <int P, bool FUSED, bool FULL = false>
 __device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
                                  RegionLut* lut_l, const XLut<P>* lut, float a_last, int blk, int tid) {
+    static_assert(!(FUSED && FULL), "the fused pass hands k over in the upper half of the rows");
     constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI;
     constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL;
     constexpr int MH = PPT / 2 + 1;
@@ -176,10 +177,11 @@ __device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds
     const int c1 = slot == 2 ? 2 : 1;
     const int rr0 = slot == 1 ? 1 : 0, rr1 = slot == 0 ? 0 : 1;  // rows within the pair
 
-    // Only x < P/2 can hold cells (P >= 2 nx - 1); rows and columns past the
-    // grid are clamped for the loads and masked afterwards, so every load of
-    // the thread is issued before the first one is used.
-    constexpr int MV = PPT > 1 ? PPT / 2 : 1;
+    // Only x < P/2 can hold cells (P >= 2 nx - 1), except along an unpadded
+    // periodic axis (FULL: P = nx); rows and columns past the grid are clamped
+    // for the loads and masked afterwards, so every load of the thread is
+    // issued before the first one is used.
+    constexpr int MV = FULL ? PPT : (PPT > 1 ? PPT / 2 : 1);
     const int r0c = v0 ? r0 : 0, r1c = v1 ? r1 : 0;
     cf v[1][PPT];
 #pragma unroll
@@ -237,8 +239,8 @@ __device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds
         const float im = (in && v1) ? lut_l[g1[m]].a.x * sv[MV + m] : 0.f;
         v[0][m] = mkc(re, im);
     }
-    // x >= nx is zero padding (nx <= P/2)
-    RegFft<P, TPF, 1, false, (P >= 2)>::run(v, buf, a.tw, a.twshift, t);
+    // x >= nx is zero padding (nx <= P/2) unless the axis is unpadded
+    RegFft<P, TPF, 1, false, (P >= 2 && !FULL)>::run(v, buf, a.tw, a.twshift, t);
 
     // separate the two real transforms of this slot
     __syncthreads();
@@ -284,9 +286,10 @@ __device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds
 // extension, inverse FFT, crop, per-cell epilogue (FUSED: the torque also to
 // LDS for the next stage's combine), reductions.  The region table goes to
 // LDS at lut_l.
-template <int P, bool FUSED, bool DMI = false>
+template <int P, bool FUSED, bool DMI = false, bool FULL = false>
 __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
                                  RegionLut* lut_l, double* red, int blk, int tid) {
+    static_assert(!(FUSED && FULL), "the fused pass hands k over in the upper half of the rows");
     constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI, NTH = XCfg<P>::NTH;
     constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL;
     constexpr int MH = PPT / 2 + 1;
@@ -344,8 +347,8 @@ __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds
 #pragma unroll
     for (int m = 0; m < PPT; ++m) v[0][m] = buf[lds_pad(t + TPF * m)];
     RegFft<P, TPF, 1, true>::run(v, buf, a.tw, a.twshift, t);
-    // only x < nx <= P/2 is kept
-    constexpr int MOUT = P >= 2 ? PPT / 2 : PPT;
+    // only x < nx <= P/2 is kept (every x along an unpadded periodic axis)
+    constexpr int MOUT = (P >= 2 && !FULL) ? PPT / 2 : PPT;
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < MOUT; ++m) buf[lds_pad(t + TPF * m)] = v[0][m];
@@ -836,10 +839,13 @@ constexpr size_t col3_lds() {
     return (size_t)Col3Cfg<P>::T * Col3Cfg<P>::CL * sizeof(cf);
 }
 
-template <int P>
+// FULL: the y axis is periodic and unpadded (P = ny): every row holds data
+// and every row is kept.
+template <int P, bool FULL = false>
 __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
     constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, T = Col3Cfg<P>::T;
-    constexpr int SEQ = Col3Cfg<P>::SEQ, KHP = Col3Cfg<P>::KHP, CL = Col3Cfg<P>::CL, MH = PPT / 2;
+    constexpr int SEQ = Col3Cfg<P>::SEQ, KHP = Col3Cfg<P>::KHP, CL = Col3Cfg<P>::CL;
+    constexpr int MH = FULL ? PPT : PPT / 2;  // registers that load and store rows
     if (a.check_done && a.st->done) return;
     const int t = tid % TPF, ci = tid / TPF;
     const int c = blk * T + ci;
@@ -852,7 +858,7 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
     const cf* baseN = a.spec + (long long)a.pack_col * a.col_stride;
     const float4* kh = reinterpret_cast<const float4*>(a.khat);
 
-    // rows y < ny <= P/2 hold data; the rest is zero padding
+    // rows y < ny <= P/2 hold data, the rest is zero padding (all P rows with FULL)
     cf v[3][PPT];
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
@@ -865,7 +871,7 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
             v[k][m] = x;
         }
     }
-    RegFft<P, TPF, 3, false, true>::run(v, buf, a.tw, a.twshift, t);
+    RegFft<P, TPF, 3, false, !FULL>::run(v, buf, a.tw, a.twshift, t);
 
     // B^ = K^ M^ (2D: K^ = [[xx, xy, 0], [xy, yy, 0], [0, 0, zz]], xy odd in y);
     // row q of column kx is (xx, yy, zz, xy) at K^[kx][min(q, P - q)]
@@ -960,7 +966,7 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
     }
     RegFft<P, TPF, 3, true>::run(v, buf, a.tw, a.twshift, t);
 
-    // rows y < ny <= P/2 are kept; one component after the other
+    // rows y < ny (<= P/2 unless FULL) are kept; one component after the other
     cf* out = a.spec + (long long)(valid ? c : 0) * a.col_stride;
     cf* outN = a.spec + (long long)a.pack_col * a.col_stride;
     int t2 = t;

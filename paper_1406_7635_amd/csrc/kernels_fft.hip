@@ -8,7 +8,8 @@
 namespace mm {
 
 
-template <int P>
+// FULL: x is a periodic axis transformed at its own length (P = nx)
+template <int P, bool FULL>
 __global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
     constexpr int GI = XCfg<P>::GI, GL = XCfg<P>::GL;
     extern __shared__ cf lds[];
@@ -19,10 +20,11 @@ __global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
     row_bases<GI>(a, blk * GI, rbs, threadIdx.x);
     XLut<P> lut;
     lut.load(a, threadIdx.x);
-    xfwd_part<P, false>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), &lut, 0.f, blk, threadIdx.x);
+    xfwd_part<P, false, FULL>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), &lut, 0.f, blk,
+                              threadIdx.x);
 }
 
-template <int P, bool DMI>
+template <int P, bool DMI, bool FULL>
 __global__ void __launch_bounds__(XCfg<P>::NTH) __attribute__((amdgpu_waves_per_eu(P >= 4096 ? 4 : 6)))
 k_xinv(const FieldArgs a) {
     constexpr int GI = XCfg<P>::GI, GL = XCfg<P>::GL, NTH = XCfg<P>::NTH;
@@ -34,7 +36,8 @@ k_xinv(const FieldArgs a) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     row_bases<GI>(a, blk * GI, rbs, threadIdx.x);
     __syncthreads();
-    xinv_part<P, false, DMI>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), red, blk, threadIdx.x);
+    xinv_part<P, false, DMI, FULL>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), red, blk,
+                                   threadIdx.x);
 }
 
 // Fused pass: the x-inverse of stage s (torque k_s, read m_s from ai.ms)
@@ -68,10 +71,10 @@ __global__ void __launch_bounds__(ColCfg<P>::NTH) k_col(const ColArgs a) {
     col_body<P, MODE, NC, CFAST>(a, xcd_remap(blockIdx.x, gridDim.x), lds, threadIdx.x);
 }
 
-template <int P>
+template <int P, bool FULL>
 __global__ void __launch_bounds__(Col3Cfg<P>::NTH, 4) k_col3(const ColArgs a) {
     extern __shared__ cf lds[];
-    col3_body<P>(a, xcd_remap(blockIdx.x, gridDim.x), lds, threadIdx.x);
+    col3_body<P, FULL>(a, xcd_remap(blockIdx.x, gridDim.x), lds, threadIdx.x);
 }
 
 // two workgroups per CU for the two-layer case (the z step of more layers
@@ -96,8 +99,12 @@ static int x_blocks(int nrows) {
 template <int P>
 static hipError_t xfwd_p(const FieldArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const size_t lds = x_lds<P>();
-    hipExtLaunchKernelGGL((k_xfwd<P>), dim3(x_blocks<P>(a.nrows)), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0,
-                          a);
+    if (a.full_x)
+        hipExtLaunchKernelGGL((k_xfwd<P, true>), dim3(x_blocks<P>(a.nrows)), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0,
+                              e1, 0, a);
+    else
+        hipExtLaunchKernelGGL((k_xfwd<P, false>), dim3(x_blocks<P>(a.nrows)), dim3(XCfg<P>::NTH), (uint32_t)lds, s,
+                              e0, e1, 0, a);
     return hipGetLastError();
 }
 
@@ -106,10 +113,19 @@ static hipError_t xinv_p(const FieldArgs& a, hipStream_t s, int* nb_out, hipEven
     const size_t lds = x_lds<P>();
     const int nb = x_blocks<P>(a.nrows);
     if (nb_out) *nb_out = nb;
-    if (a.dmi)
-        hipExtLaunchKernelGGL((k_xinv<P, true>), dim3(nb), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0, a);
-    else
-        hipExtLaunchKernelGGL((k_xinv<P, false>), dim3(nb), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0, a);
+#define MM_XI(D, F) hipExtLaunchKernelGGL((k_xinv<P, D, F>), dim3(nb), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0, a)
+    if (a.dmi) {
+        if (a.full_x)
+            MM_XI(true, true);
+        else
+            MM_XI(true, false);
+    } else {
+        if (a.full_x)
+            MM_XI(false, true);
+        else
+            MM_XI(false, false);
+    }
+#undef MM_XI
     return hipGetLastError();
 }
 
@@ -146,8 +162,12 @@ static hipError_t yz_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_
 template <int P>
 static hipError_t col3_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const long long nb = (a.ncol + Col3Cfg<P>::T - 1) / Col3Cfg<P>::T;
-    hipExtLaunchKernelGGL((k_col3<P>), dim3((unsigned)nb), dim3(Col3Cfg<P>::NTH), (uint32_t)col3_lds<P>(), s, e0, e1,
-                          0, a);
+    if (a.full)
+        hipExtLaunchKernelGGL((k_col3<P, true>), dim3((unsigned)nb), dim3(Col3Cfg<P>::NTH), (uint32_t)col3_lds<P>(), s,
+                              e0, e1, 0, a);
+    else
+        hipExtLaunchKernelGGL((k_col3<P, false>), dim3((unsigned)nb), dim3(Col3Cfg<P>::NTH), (uint32_t)col3_lds<P>(), s,
+                              e0, e1, 0, a);
     return hipGetLastError();
 }
 
@@ -160,9 +180,12 @@ static hipError_t allow_lds(const void* f, size_t bytes) {
 
 template <int P>
 static hipError_t configure_x(void) {
-    hipError_t e = allow_lds<P>((const void*)k_xfwd<P>, x_lds<P>());
-    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, false>, x_lds<P>());
-    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, true>, x_lds<P>());
+    hipError_t e = allow_lds<P>((const void*)k_xfwd<P, false>, x_lds<P>());
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xfwd<P, true>, x_lds<P>());
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, false, false>, x_lds<P>());
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, true, false>, x_lds<P>());
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, false, true>, x_lds<P>());
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, true, true>, x_lds<P>());
     if constexpr (P >= 8) {
         if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, false>, x_lds<P>());
         if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, true>, x_lds<P>());
@@ -264,7 +287,11 @@ hipError_t launch_yz(int py, int pz, const ColArgs& a, hipStream_t s, hipEvent_t
 template <int P>
 static hipError_t configure_col(bool three_d) {
     if (!three_d) {
-        if constexpr (use_col3<P>()) return allow_lds<P>((const void*)k_col3<P>, col3_lds<P>());
+        if constexpr (use_col3<P>()) {
+            const hipError_t e = allow_lds<P>((const void*)k_col3<P, false>, col3_lds<P>());
+            if (e != hipSuccess) return e;
+            return allow_lds<P>((const void*)k_col3<P, true>, col3_lds<P>());
+        }
         return allow_lds<P>((const void*)k_col<P, COL_CONV, 4, false>, col_lds<P, COL_CONV, 4>());
     }
     hipError_t e = allow_lds<P>((const void*)k_col<P, COL_FWD, 4, false>, col_lds<P, COL_FWD, 4>());

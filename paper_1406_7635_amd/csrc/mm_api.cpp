@@ -71,6 +71,9 @@ struct mm_ctx {
     int pt = 1, twshift = 0;
     bool demag_on = true, khat_ready = false;
     int pbc[3] = {0, 0, 0};  // images per side (0: open boundary)
+    // periodic axes transformed at their own length (no zero padding): x of
+    // any grid, y of 2D grids whose column pass holds whole columns
+    bool full_x = false, full_y = false;
     int win[3] = {1, 1, 1};  // tensor window per axis: n P, or n
     uint8_t* region = nullptr;
     double* params64 = nullptr;
@@ -182,6 +185,7 @@ FieldArgs base_args(mm_ctx* c, const float* m0) {
     a.pbc = (c->pbc[0] > 0 ? 1 : 0) | (c->pbc[1] > 0 ? 2 : 0) | (c->pbc[2] > 0 ? 4 : 0);
     a.cub = c->cub_on ? c->cub : nullptr;
     a.dmi = c->dmi_on ? c->dmi : nullptr;
+    a.full_x = c->full_x ? 1 : 0;
     return a;
 }
 
@@ -221,6 +225,7 @@ int run_cols(mm_ctx* c, bool check_done, cf* spec, bool timed = true) {
     ca.st = c->st;
     ca.check_done = check_done ? 1 : 0;
     ca.khat = c->khat;
+    ca.full = c->full_y ? 1 : 0;
     ca.kyh = c->py / 2 + 1;
     ca.kzh = c->pz / 2 + 1;
     ca.pa = c->py;
@@ -527,7 +532,9 @@ int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done
         return attempt_surrogate(c, m, tb, precess, check_done);
     }
     float* fin_ms = c->ms;
-    if (c->demag_on && c->px >= 8 && S > 2) {
+    // the fused pass hands k_s over in the zero-padded half of the rows, which
+    // an unpadded periodic x does not have
+    if (c->demag_on && c->px >= 8 && S > 2 && !c->full_x) {
         if (!c->khat_ready) return MM_ESTATE;
         float* buf[2] = {c->ms, c->ms2};
         int cur = 0;
@@ -781,8 +788,13 @@ int mm_create(mm_ctx** out, const mm_grid* g, const mm_params* p, const uint8_t*
         c->pbc[ax] = g->pbc[ax];
         c->win[ax] = (int)win[ax];
     }
-    c->px = pad_len(g->nx);
-    c->py = pad_len(g->ny);
+    // A periodic axis needs no zero padding (the convolution along it is
+    // cyclic): one whose length is a power of two is transformed at that length
+    auto pow2 = [](int n) { return n >= 2 && (n & (n - 1)) == 0; };
+    c->full_x = g->pbc[0] > 0 && pow2(g->nx);
+    c->full_y = g->pbc[1] > 0 && g->nz == 1 && pow2(g->ny) && g->ny >= 64 && g->ny <= 2048;
+    c->px = c->full_x ? g->nx : pad_len(g->nx);
+    c->py = c->full_y ? g->ny : pad_len(g->ny);
     c->pz = pad_len(g->nz);
     if (c->px > 4096 || c->py > 4096 || c->pz > 4096) {
         delete c;
@@ -1336,7 +1348,7 @@ int mm_set_conv_precision(mm_ctx* c, int32_t prec) {
     if (prec != MM_PREC_FP32) {
         // 2D: the y convolution at padded y length 2048; 3D (the three-pass
         // column path): padded y and z lengths the matrix-core passes serve
-        const bool film = c->pz == 1 && c->py == 2048 && c->px >= 2;
+        const bool film = c->pz == 1 && c->py == 2048 && c->px >= 2 && !c->full_y;
         const bool vol = c->pz > 1 && !c->yz && (c->py == 1 || colm3d_supported(c->py)) && colm3d_supported(c->pz);
         if (!film && !vol) return MM_EUNSUPPORTED;
     }

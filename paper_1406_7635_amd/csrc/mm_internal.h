@@ -100,6 +100,7 @@ struct FieldArgs {
     const float4* cub;
     // induced DMI per region (null: none): (2 D/Msat, D/(2 A))
     const float2* dmi;
+    int full_x;                   // x is periodic and transformed unpadded (px = nx)
 };
 
 struct ColArgs {
@@ -120,6 +121,7 @@ struct ColArgs {
     int check_done;
     const void* dft_tab;          // matrix-core variant: split DFT matrices of its precision
     const float* zker;            // ensembles: base of the members' z-space kernels (thin grids)
+    int full;                     // 2D convolution: y periodic and unpadded (py = ny)
 };
 
 // ---- launchers (kernels_fft.hip) -------------------------------------------

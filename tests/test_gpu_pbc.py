@@ -30,6 +30,11 @@ CASES = [
     ((12, 10, 6), (3e-9, 2e-9, 1.5e-9), (0, 2, 1)),     # 3D
     ((8, 8, 8), (2e-9, 2e-9, 2e-9), (2, 2, 2)),         # every axis periodic
     ((100, 70, 1), (3e-9, 3e-9, 3e-9), (4, 4, 0)),      # several tiles
+    # periodic power-of-two axes transformed at their own length (no padding)
+    ((128, 64, 1), (2e-9, 2e-9, 2e-9), (2, 2, 0)),      # x and y unpadded
+    ((64, 256, 1), (3e-9, 2e-9, 2e-9), (0, 3, 0)),      # y unpadded, x open
+    ((256, 100, 1), (2e-9, 3e-9, 2e-9), (1, 0, 0)),     # x unpadded, y open
+    ((32, 20, 5), (2e-9, 2e-9, 2e-9), (2, 0, 1)),       # 3D, x unpadded
 ]
 
 
@@ -165,6 +170,34 @@ def test_adaptive_run_matches_oracle(gpu):
     it.run(t_end)
     err = np.max(np.abs(to_np(m) - it.m))
     log("pbc DP45 steps", st["steps"], "oracle steps", it.nsteps, "max |dm|", err)
+    assert err < 1e-3
+    ctx.close()
+
+
+def test_unpadded_periodic_lengths_and_run(gpu):
+    """A periodic axis whose length is a power of two is transformed at that
+    length (the paper's remark that periodic directions need no padding):
+    the padded lengths the library reports, and a Dormand-Prince run of a
+    64 x 64 film periodic in x and y against the oracle."""
+    for grid, pbc, want in (((128, 64, 1), (2, 2, 0), (128, 64, 1)), ((64, 256, 1), (0, 3, 0), (128, 256, 1)),
+                            ((256, 100, 1), (1, 0, 0), (256, 256, 1)), ((32, 20, 5), (2, 0, 1), (32, 64, 16)),
+                            ((48, 64, 1), (1, 1, 0), (128, 64, 1))):
+        case = synth.random_problem(grid, (2e-9, 2e-9, 2e-9), seed=4)
+        ctx = mm.Context(case["grid"], case["cell"], case["region"], case["params"], pbc=pbc, demag=False)
+        info = ctx.info()
+        assert (info["px"], info["py"], info["pz"]) == want, (grid, pbc)
+        ctx.close()
+    case = synth.vortex_film(seed=2, n=64)
+    case["params"]["alpha"][0] = 0.1
+    pbc = (1, 1, 0)
+    ctx, prob, m = pair(case, pbc)
+    t_end = 5e-12
+    t, dt, st = ctx.run(m, t_end, dt=1e-14, solver=45, opts=mm.solver_opts(max_err=1e-5))
+    assert t == pytest.approx(t_end, rel=1e-12)
+    it = ointegrate.Integrator(prob.torque, case["m0"], "rk45", dt=1e-14, max_err=1e-5)
+    it.run(t_end)
+    err = np.max(np.abs(to_np(m) - it.m))
+    log("unpadded pbc DP45 steps", st["steps"], "oracle steps", it.nsteps, "max |dm|", err)
     assert err < 1e-3
     ctx.close()
 
