@@ -876,7 +876,9 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
     // B^ = K^ M^ (2D: K^ = [[xx, xy, 0], [xy, yy, 0], [0, 0, zz]], xy odd in y);
     // row q of column kx is (xx, yy, zz, xy) at K^[kx][min(q, P - q)]
     if (!wg_packed) {
-        const float4* kc = kh + (long long)(valid ? c : 0) * KHP;
+        int cq = valid ? c : 0;
+        asm volatile("" : "+v"(cq));  // the K^ loads go out here, not during the transform
+        const float4* kc = kh + (long long)cq * KHP;
         float4 kg[PPT];
 #pragma unroll
         for (int m = 0; m < PPT; ++m) {
@@ -964,7 +966,11 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
             }
         }
     }
-    RegFft<P, TPF, 3, true>::run(v, buf, a.tw, a.twshift, t);
+    // the inverse transform derives its exchange addresses afresh (nothing of
+    // the forward one stays live across the product)
+    int ti = t;
+    asm volatile("" : "+v"(ti));
+    RegFft<P, TPF, 3, true>::run(v, buf, a.tw, a.twshift, ti);
 
     // rows y < ny (<= P/2 unless FULL) are kept; one component after the other
     cf* out = a.spec + (long long)(valid ? c : 0) * a.col_stride;
