@@ -47,9 +47,15 @@ struct Cfg {
 // row pair: the three exchange sequences, reused afterwards as the staging
 // area [kx][row][component] through which the spectrum is written / read in
 // contiguous runs (rows a, b are adjacent in the spectrum when a is even).
-template <int P>
+// W = 0: wide workgroups (768 threads for P <= 2048); W = 1: narrow ones of
+// about 192 threads, for grids with too few rows to give every CU two wide
+// workgroups.
+template <int P, int W = 0>
 struct XCfg {
-    static constexpr int GI = Cfg<P>::TPF >= 256 ? 1 : (Cfg<P>::TPF >= 128 ? 2 : 256 / Cfg<P>::TPF);
+    static constexpr int TPF = Cfg<P>::TPF;
+    static constexpr int GIW = TPF >= 256 ? 1 : (TPF >= 128 ? 2 : 256 / TPF);
+    static constexpr int GIN = TPF >= 64 ? 1 : 64 / TPF;
+    static constexpr int GI = (W && GIN < GIW) ? GIN : GIW;
     static constexpr int NTH = 3 * GI * Cfg<P>::TPF;
     static constexpr int KH = P / 2 + 1;
     static constexpr int GL = 3 * seq_len(P) > 6 * KH ? 3 * seq_len(P) : 6 * KH;
@@ -89,9 +95,9 @@ __device__ inline void row_bases(const FieldArgs& a, int pair0, long long* rbs, 
 // thread tid handles the elements u = tid + NTH i.  NTH is a multiple of 6, so
 // the (row, component) of a thread's elements is fixed and kx advances by
 // NTH/6 per step; offsets need no division per element.
-template <int P>
+template <int P, int W = 0>
 struct Staged {
-    static constexpr int GI = XCfg<P>::GI, NTH = XCfg<P>::NTH, KH = XCfg<P>::KH, GL = XCfg<P>::GL;
+    static constexpr int GI = XCfg<P, W>::GI, NTH = XCfg<P, W>::NTH, KH = XCfg<P, W>::KH, GL = XCfg<P, W>::GL;
     static constexpr int TOT = GI * KH * 6, NIT = (TOT + NTH - 1) / NTH, KS = NTH / 6;
     static_assert(NTH % 6 == 0, "workgroup size must be a multiple of 6");
     int comp, h, kq0;
@@ -116,9 +122,9 @@ struct Staged {
 
 // ---------------------------------------------------------------------------
 // x passes.  Both stage the region table in LDS after the row-pair area.
-template <int P>
+template <int P, int W = 0>
 struct XLut {
-    static constexpr int NTH = XCfg<P>::NTH;
+    static constexpr int NTH = XCfg<P, W>::NTH;
     static constexpr int NL4 = NREG * (int)(sizeof(RegionLut) / sizeof(float4));
     static constexpr int NLI = (NL4 + NTH - 1) / NTH;
     float4 lt[NLI];
@@ -149,12 +155,12 @@ __device__ inline float* ks_stage(cf* gbuf, int c) {
 // zero-padded rows, separation of the two real transforms, staged coalesced
 // spectrum write.  The region table is in LDS at lut_l once the first barrier
 // has passed (the non-fused pass writes it from lut after issuing its loads).
-template <int P, bool FUSED, bool FULL = false>
+template <int P, bool FUSED, bool FULL = false, int XW = 0>
 __device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
-                                 RegionLut* lut_l, const XLut<P>* lut, float a_last, int blk, int tid) {
+                                 RegionLut* lut_l, const XLut<P, XW>* lut, float a_last, int blk, int tid) {
     static_assert(!(FUSED && FULL), "the fused pass hands k over in the upper half of the rows");
-    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI;
-    constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL;
+    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P, XW>::GI;
+    constexpr int SEQ = seq_len(P), GL = XCfg<P, XW>::GL;
     constexpr int MH = PPT / 2 + 1;
     // in the fused pass, derive every index afresh here (nothing of the first
     // part stays live across the boundary)
@@ -272,9 +278,9 @@ __device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds
         }
     }
     __syncthreads();
-    const Staged<P> sc(tid);
+    const Staged<P, XW> sc(tid);
 #pragma unroll
-    for (int i = 0; i < Staged<P>::NIT; ++i) {
+    for (int i = 0; i < Staged<P, XW>::NIT; ++i) {
         int li;
         long long off;
         sc.at(a, rbs, i, li, off);
@@ -286,24 +292,24 @@ __device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds
 // extension, inverse FFT, crop, per-cell epilogue (FUSED: the torque also to
 // LDS for the next stage's combine), reductions.  The region table goes to
 // LDS at lut_l.
-template <int P, bool FUSED, bool DMI = false, bool FULL = false>
+template <int P, bool FUSED, bool DMI = false, bool FULL = false, int XW = 0>
 __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
                                  RegionLut* lut_l, double* red, int blk, int tid) {
     static_assert(!(FUSED && FULL), "the fused pass hands k over in the upper half of the rows");
-    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P>::GI, NTH = XCfg<P>::NTH;
-    constexpr int SEQ = seq_len(P), GL = XCfg<P>::GL;
+    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P, XW>::GI, NTH = XCfg<P, XW>::NTH;
+    constexpr int SEQ = seq_len(P), GL = XCfg<P, XW>::GL;
     constexpr int MH = PPT / 2 + 1;
     const int t = tid % TPF, slot = (tid / TPF) % 3, g = tid / (3 * TPF);
     const int pair0 = blk * GI;
     cf* gbuf = lds + g * GL;
     cf* buf = gbuf + slot * SEQ;
 
-    XLut<P> lut;
+    XLut<P, XW> lut;
     lut.load(a, tid);
     // read the half spectra of the row pairs in contiguous runs into
     // [kx][row][component]: every load of the thread first, then the LDS writes
-    const Staged<P> sc(tid);
-    constexpr int NIT = Staged<P>::NIT;
+    const Staged<P, XW> sc(tid);
+    constexpr int NIT = Staged<P, XW>::NIT;
     cf tmp[NIT];
     int li[NIT];
 #pragma unroll
@@ -314,7 +320,7 @@ __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds
     }
 #pragma unroll
     for (int i = 0; i < NIT; ++i)
-        if (i < NIT - 1 || sc.kq0 + Staged<P>::KS * i < Staged<P>::GI * XCfg<P>::KH) lds[li[i]] = tmp[i];
+        if (i < NIT - 1 || sc.kq0 + Staged<P, XW>::KS * i < Staged<P, XW>::GI * XCfg<P, XW>::KH) lds[li[i]] = tmp[i];
     lut.store(lut_l, tid);
     __syncthreads();
     // slot s = u + i w (slot 0: x, y of row a; slot 1: x, y of row b; slot 2: z of
@@ -818,10 +824,12 @@ __device__ inline void yz_body(const ColArgs& a, int blk, cf* lds, int tid) {
 // packed DC/Nyquist column uses.  The K^ rows come straight from global
 // memory (L2 / MALL) at the product: staging them in LDS before the forward
 // transforms made every workgroup wait for them before its first butterfly.
-template <int P>
+template <int P, int W = 0>
 struct Col3Cfg {
     static constexpr int TPF = Cfg<P>::TPF;
-    static constexpr int T = TPF >= 256 ? 1 : 256 / TPF;
+    // W = 0: 256-thread workgroups; W = 1: about one wave, for grids with too
+    // few columns to give every CU two wide workgroups
+    static constexpr int T = W ? (TPF >= 64 ? 1 : 64 / TPF) : (TPF >= 256 ? 1 : 256 / TPF);
     static constexpr int NTH = T * TPF;
     static constexpr int SEQ = seq_len(P);
     static constexpr int KHP = P / 2 + 1;
@@ -834,17 +842,17 @@ constexpr bool use_col3() {
     return P >= 64 && P <= 2048;
 }
 
-template <int P>
+template <int P, int W = 0>
 constexpr size_t col3_lds() {
-    return (size_t)Col3Cfg<P>::T * Col3Cfg<P>::CL * sizeof(cf);
+    return (size_t)Col3Cfg<P, W>::T * Col3Cfg<P, W>::CL * sizeof(cf);
 }
 
 // FULL: the y axis is periodic and unpadded (P = ny): every row holds data
 // and every row is kept.
-template <int P, bool FULL = false>
+template <int P, bool FULL = false, int W = 0>
 __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
-    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, T = Col3Cfg<P>::T;
-    constexpr int SEQ = Col3Cfg<P>::SEQ, KHP = Col3Cfg<P>::KHP, CL = Col3Cfg<P>::CL;
+    constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, T = Col3Cfg<P, W>::T;
+    constexpr int SEQ = Col3Cfg<P, W>::SEQ, KHP = Col3Cfg<P, W>::KHP, CL = Col3Cfg<P, W>::CL;
     constexpr int MH = FULL ? PPT : PPT / 2;  // registers that load and store rows
     if (a.check_done && a.st->done) return;
     const int t = tid % TPF, ci = tid / TPF;
@@ -995,9 +1003,9 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
 }
 
 // Dynamic LDS of each pass (bytes per workgroup).
-template <int P>
+template <int P, int W = 0>
 constexpr size_t x_lds() {
-    return (size_t)XCfg<P>::GI * XCfg<P>::GL * sizeof(cf) + NREG * sizeof(RegionLut);
+    return (size_t)XCfg<P, W>::GI * XCfg<P, W>::GL * sizeof(cf) + NREG * sizeof(RegionLut);
 }
 template <int P, int MODE, int NC, bool CFAST = false>
 constexpr size_t col_lds() {

@@ -194,7 +194,7 @@ __device__ inline void bx_item(const FieldArgs& fi, const FieldArgs& ff, float a
         __syncthreads();
         const FieldArgs af = member_field(ff, mb, i);
         const Resolved rsf = resolve(af);
-        xfwd_part<P, true>(af, rsf, lds, rbs, lut_l, nullptr, a_last, blk, tid);
+        xfwd_part<P, true, false, 0>(af, rsf, lds, rbs, lut_l, nullptr, a_last, blk, tid);
     }
 }
 

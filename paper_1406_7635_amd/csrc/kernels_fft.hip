@@ -8,26 +8,27 @@
 namespace mm {
 
 
-// FULL: x is a periodic axis transformed at its own length (P = nx)
-template <int P, bool FULL>
-__global__ void __launch_bounds__(XCfg<P>::NTH) k_xfwd(const FieldArgs a) {
-    constexpr int GI = XCfg<P>::GI, GL = XCfg<P>::GL;
+// FULL: x is a periodic axis transformed at its own length (P = nx).
+// W: workgroup width (XCfg): 0 wide, 1 narrow (grids with few rows).
+template <int P, bool FULL, int W>
+__global__ void __launch_bounds__((XCfg<P, W>::NTH)) k_xfwd(const FieldArgs a) {
+    constexpr int GI = XCfg<P, W>::GI, GL = XCfg<P, W>::GL;
     extern __shared__ cf lds[];
     __shared__ long long rbs[2 * GI];
     const Resolved rs = resolve(a);
     if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     row_bases<GI>(a, blk * GI, rbs, threadIdx.x);
-    XLut<P> lut;
+    XLut<P, W> lut;
     lut.load(a, threadIdx.x);
-    xfwd_part<P, false, FULL>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), &lut, 0.f, blk,
-                              threadIdx.x);
+    xfwd_part<P, false, FULL, W>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), &lut, 0.f, blk,
+                                 threadIdx.x);
 }
 
-template <int P, bool DMI, bool FULL>
-__global__ void __launch_bounds__(XCfg<P>::NTH) __attribute__((amdgpu_waves_per_eu(P >= 4096 ? 4 : 6)))
+template <int P, bool DMI, bool FULL, int W>
+__global__ void __launch_bounds__((XCfg<P, W>::NTH)) __attribute__((amdgpu_waves_per_eu(P >= 4096 ? 4 : 6)))
 k_xinv(const FieldArgs a) {
-    constexpr int GI = XCfg<P>::GI, GL = XCfg<P>::GL, NTH = XCfg<P>::NTH;
+    constexpr int GI = XCfg<P, W>::GI, GL = XCfg<P, W>::GL, NTH = XCfg<P, W>::NTH;
     extern __shared__ cf lds[];
     __shared__ double red[(NTH / 64 > 0 ? NTH / 64 : 1) * 6];
     __shared__ long long rbs[2 * GI];
@@ -36,18 +37,18 @@ k_xinv(const FieldArgs a) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     row_bases<GI>(a, blk * GI, rbs, threadIdx.x);
     __syncthreads();
-    xinv_part<P, false, DMI, FULL>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), red, blk,
-                                   threadIdx.x);
+    xinv_part<P, false, DMI, FULL, W>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), red, blk,
+                                      threadIdx.x);
 }
 
 // Fused pass: the x-inverse of stage s (torque k_s, read m_s from ai.ms)
 // followed, row pair by row pair, by the x-forward of stage s + 1 (combine
 // with k_s from LDS as the last term, m_{s+1} to af.ms, a second buffer since
 // other workgroups still read m_s for the exchange field).
-template <int P, bool DMI>
-__global__ void __launch_bounds__(XCfg<P>::NTH) __attribute__((amdgpu_waves_per_eu(6)))
+template <int P, bool DMI, int W>
+__global__ void __launch_bounds__((XCfg<P, W>::NTH)) __attribute__((amdgpu_waves_per_eu(6)))
 k_xrow(const FieldArgs ai, const FieldArgs af, float a_last) {
-    constexpr int GI = XCfg<P>::GI, GL = XCfg<P>::GL, NTH = XCfg<P>::NTH;
+    constexpr int GI = XCfg<P, W>::GI, GL = XCfg<P, W>::GL, NTH = XCfg<P, W>::NTH;
     extern __shared__ cf lds[];
     __shared__ double red[(NTH / 64 > 0 ? NTH / 64 : 1) * 6];
     __shared__ long long rbs[2 * GI];
@@ -57,11 +58,11 @@ k_xrow(const FieldArgs ai, const FieldArgs af, float a_last) {
     row_bases<GI>(ai, blk * GI, rbs, threadIdx.x);
     __syncthreads();
     RegionLut* lut_l = reinterpret_cast<RegionLut*>(lds + GI * GL);
-    xinv_part<P, true, DMI>(ai, rsi, lds, rbs, lut_l, red, blk, threadIdx.x);
+    xinv_part<P, true, DMI, false, W>(ai, rsi, lds, rbs, lut_l, red, blk, threadIdx.x);
     __syncthreads();
     // the next stage's pointers only now (short live ranges across the first part)
     const Resolved rsf = resolve(af);
-    xfwd_part<P, true>(af, rsf, lds, rbs, lut_l, nullptr, a_last, blk, threadIdx.x);
+    xfwd_part<P, true, false, W>(af, rsf, lds, rbs, lut_l, nullptr, a_last, blk, threadIdx.x);
 }
 
 
@@ -71,10 +72,10 @@ __global__ void __launch_bounds__(ColCfg<P>::NTH) k_col(const ColArgs a) {
     col_body<P, MODE, NC, CFAST>(a, xcd_remap(blockIdx.x, gridDim.x), lds, threadIdx.x);
 }
 
-template <int P, bool FULL>
-__global__ void __launch_bounds__(Col3Cfg<P>::NTH, 4) k_col3(const ColArgs a) {
+template <int P, bool FULL, int W>
+__global__ void __launch_bounds__((Col3Cfg<P, W>::NTH), 4) k_col3(const ColArgs a) {
     extern __shared__ cf lds[];
-    col3_body<P, FULL>(a, xcd_remap(blockIdx.x, gridDim.x), lds, threadIdx.x);
+    col3_body<P, FULL, W>(a, xcd_remap(blockIdx.x, gridDim.x), lds, threadIdx.x);
 }
 
 // two workgroups per CU for the two-layer case (the z step of more layers
@@ -90,30 +91,46 @@ __global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(PZ == 
 // Launch helpers: dispatch the run-time padded length to a template instance.
 
 
+template <int P, int W>
+static int x_blocks_w(int nrows) {
+    const int npairs = (nrows + 1) / 2;
+    return (npairs + XCfg<P, W>::GI - 1) / XCfg<P, W>::GI;
+}
+
+// Narrow x workgroups when the wide ones would not give every CU two
+// (and the narrow form actually holds fewer row pairs).
+constexpr int NARROW_BELOW = 512;
+template <int P>
+static int x_width(int nrows) {
+    return (XCfg<P, 1>::GI < XCfg<P, 0>::GI && x_blocks_w<P, 0>(nrows) < NARROW_BELOW) ? 1 : 0;
+}
 template <int P>
 static int x_blocks(int nrows) {
-    const int npairs = (nrows + 1) / 2;
-    return (npairs + XCfg<P>::GI - 1) / XCfg<P>::GI;
+    return x_width<P>(nrows) ? x_blocks_w<P, 1>(nrows) : x_blocks_w<P, 0>(nrows);
 }
 
-template <int P>
-static hipError_t xfwd_p(const FieldArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const size_t lds = x_lds<P>();
+template <int P, int W>
+static hipError_t xfwd_pw(const FieldArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const size_t lds = x_lds<P, W>();
+    const dim3 g(x_blocks_w<P, W>(a.nrows)), b(XCfg<P, W>::NTH);
     if (a.full_x)
-        hipExtLaunchKernelGGL((k_xfwd<P, true>), dim3(x_blocks<P>(a.nrows)), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0,
-                              e1, 0, a);
+        hipExtLaunchKernelGGL((k_xfwd<P, true, W>), g, b, (uint32_t)lds, s, e0, e1, 0, a);
     else
-        hipExtLaunchKernelGGL((k_xfwd<P, false>), dim3(x_blocks<P>(a.nrows)), dim3(XCfg<P>::NTH), (uint32_t)lds, s,
-                              e0, e1, 0, a);
+        hipExtLaunchKernelGGL((k_xfwd<P, false, W>), g, b, (uint32_t)lds, s, e0, e1, 0, a);
     return hipGetLastError();
 }
-
 template <int P>
-static hipError_t xinv_p(const FieldArgs& a, hipStream_t s, int* nb_out, hipEvent_t e0, hipEvent_t e1) {
-    const size_t lds = x_lds<P>();
-    const int nb = x_blocks<P>(a.nrows);
+static hipError_t xfwd_p(const FieldArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    return x_width<P>(a.nrows) ? xfwd_pw<P, 1>(a, s, e0, e1) : xfwd_pw<P, 0>(a, s, e0, e1);
+}
+
+template <int P, int W>
+static hipError_t xinv_pw(const FieldArgs& a, hipStream_t s, int* nb_out, hipEvent_t e0, hipEvent_t e1) {
+    const size_t lds = x_lds<P, W>();
+    const int nb = x_blocks_w<P, W>(a.nrows);
     if (nb_out) *nb_out = nb;
-#define MM_XI(D, F) hipExtLaunchKernelGGL((k_xinv<P, D, F>), dim3(nb), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0, e1, 0, a)
+#define MM_XI(D, F) \
+    hipExtLaunchKernelGGL((k_xinv<P, D, F, W>), dim3(nb), dim3(XCfg<P, W>::NTH), (uint32_t)lds, s, e0, e1, 0, a)
     if (a.dmi) {
         if (a.full_x)
             MM_XI(true, true);
@@ -128,18 +145,26 @@ static hipError_t xinv_p(const FieldArgs& a, hipStream_t s, int* nb_out, hipEven
 #undef MM_XI
     return hipGetLastError();
 }
+template <int P>
+static hipError_t xinv_p(const FieldArgs& a, hipStream_t s, int* nb_out, hipEvent_t e0, hipEvent_t e1) {
+    return x_width<P>(a.nrows) ? xinv_pw<P, 1>(a, s, nb_out, e0, e1) : xinv_pw<P, 0>(a, s, nb_out, e0, e1);
+}
 
+template <int P, int W>
+static hipError_t xrow_pw(const FieldArgs& ai, const FieldArgs& af, float a_last, hipStream_t s, hipEvent_t e0,
+                          hipEvent_t e1) {
+    const size_t lds = x_lds<P, W>();
+    const dim3 g(x_blocks_w<P, W>(ai.nrows)), b(XCfg<P, W>::NTH);
+    if (ai.dmi)
+        hipExtLaunchKernelGGL((k_xrow<P, true, W>), g, b, (uint32_t)lds, s, e0, e1, 0, ai, af, a_last);
+    else
+        hipExtLaunchKernelGGL((k_xrow<P, false, W>), g, b, (uint32_t)lds, s, e0, e1, 0, ai, af, a_last);
+    return hipGetLastError();
+}
 template <int P>
 static hipError_t xrow_p(const FieldArgs& ai, const FieldArgs& af, float a_last, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
-    const size_t lds = x_lds<P>();
-    if (ai.dmi)
-        hipExtLaunchKernelGGL((k_xrow<P, true>), dim3(x_blocks<P>(ai.nrows)), dim3(XCfg<P>::NTH), (uint32_t)lds, s, e0,
-                              e1, 0, ai, af, a_last);
-    else
-        hipExtLaunchKernelGGL((k_xrow<P, false>), dim3(x_blocks<P>(ai.nrows)), dim3(XCfg<P>::NTH), (uint32_t)lds, s,
-                              e0, e1, 0, ai, af, a_last);
-    return hipGetLastError();
+    return x_width<P>(ai.nrows) ? xrow_pw<P, 1>(ai, af, a_last, s, e0, e1) : xrow_pw<P, 0>(ai, af, a_last, s, e0, e1);
 }
 
 template <int P, int MODE, int NC, bool CFAST>
@@ -159,16 +184,23 @@ static hipError_t yz_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_
     return hipGetLastError();
 }
 
+template <int P, int W>
+static hipError_t col3_pw(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const long long nb = (a.ncol + Col3Cfg<P, W>::T - 1) / Col3Cfg<P, W>::T;
+    const dim3 g((unsigned)nb), b(Col3Cfg<P, W>::NTH);
+    if (a.full)
+        hipExtLaunchKernelGGL((k_col3<P, true, W>), g, b, (uint32_t)col3_lds<P, W>(), s, e0, e1, 0, a);
+    else
+        hipExtLaunchKernelGGL((k_col3<P, false, W>), g, b, (uint32_t)col3_lds<P, W>(), s, e0, e1, 0, a);
+    return hipGetLastError();
+}
+// narrow (about one wave) column workgroups when the wide ones would not
+// give every CU two
 template <int P>
 static hipError_t col3_p(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const long long nb = (a.ncol + Col3Cfg<P>::T - 1) / Col3Cfg<P>::T;
-    if (a.full)
-        hipExtLaunchKernelGGL((k_col3<P, true>), dim3((unsigned)nb), dim3(Col3Cfg<P>::NTH), (uint32_t)col3_lds<P>(), s,
-                              e0, e1, 0, a);
-    else
-        hipExtLaunchKernelGGL((k_col3<P, false>), dim3((unsigned)nb), dim3(Col3Cfg<P>::NTH), (uint32_t)col3_lds<P>(), s,
-                              e0, e1, 0, a);
-    return hipGetLastError();
+    const long long nb_wide = (a.ncol + Col3Cfg<P, 0>::T - 1) / Col3Cfg<P, 0>::T;
+    if (Col3Cfg<P, 1>::T < Col3Cfg<P, 0>::T && nb_wide < NARROW_BELOW) return col3_pw<P, 1>(a, s, e0, e1);
+    return col3_pw<P, 0>(a, s, e0, e1);
 }
 
 #define MM_CASES(M) M(1) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048) M(4096)
@@ -178,18 +210,26 @@ static hipError_t allow_lds(const void* f, size_t bytes) {
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+template <int P, int W>
+static hipError_t configure_xw(void) {
+    constexpr size_t L = x_lds<P, W>();
+    hipError_t e = allow_lds<P>((const void*)k_xfwd<P, false, W>, L);
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xfwd<P, true, W>, L);
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, false, false, W>, L);
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, true, false, W>, L);
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, false, true, W>, L);
+    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, true, true, W>, L);
+    if constexpr (P >= 8) {
+        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, false, W>, L);
+        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, true, W>, L);
+    }
+    return e;
+}
+
 template <int P>
 static hipError_t configure_x(void) {
-    hipError_t e = allow_lds<P>((const void*)k_xfwd<P, false>, x_lds<P>());
-    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xfwd<P, true>, x_lds<P>());
-    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, false, false>, x_lds<P>());
-    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, true, false>, x_lds<P>());
-    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, false, true>, x_lds<P>());
-    if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, true, true>, x_lds<P>());
-    if constexpr (P >= 8) {
-        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, false>, x_lds<P>());
-        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, true>, x_lds<P>());
-    }
+    hipError_t e = configure_xw<P, 0>();
+    if (e == hipSuccess) e = configure_xw<P, 1>();
     return e;
 }
 
@@ -288,9 +328,11 @@ template <int P>
 static hipError_t configure_col(bool three_d) {
     if (!three_d) {
         if constexpr (use_col3<P>()) {
-            const hipError_t e = allow_lds<P>((const void*)k_col3<P, false>, col3_lds<P>());
-            if (e != hipSuccess) return e;
-            return allow_lds<P>((const void*)k_col3<P, true>, col3_lds<P>());
+            hipError_t e = allow_lds<P>((const void*)k_col3<P, false, 0>, col3_lds<P, 0>());
+            if (e == hipSuccess) e = allow_lds<P>((const void*)k_col3<P, true, 0>, col3_lds<P, 0>());
+            if (e == hipSuccess) e = allow_lds<P>((const void*)k_col3<P, false, 1>, col3_lds<P, 1>());
+            if (e == hipSuccess) e = allow_lds<P>((const void*)k_col3<P, true, 1>, col3_lds<P, 1>());
+            return e;
         }
         return allow_lds<P>((const void*)k_col<P, COL_CONV, 4, false>, col_lds<P, COL_CONV, 4>());
     }
