@@ -366,6 +366,24 @@ int mm_exchange_dump(mm_ctx *c, float *out_dev);
 int mm_timing_enable(mm_ctx *c, int32_t which, int32_t enable);
 int mm_timing_read(mm_ctx *c, int32_t which, int64_t *launches, double *total_ms);
 
+/* Checkpoint and resume.  A run continues bit for bit from a saved state
+ * given the same m (the caller's array, saved by the caller) and the (t, dt)
+ * that mm_run returned.  The saved state holds the device-side solver record
+ * (the map of stage-derivative buffers, the controller's scalars and
+ * counters, the thermal generator's step counter), the FSAL flags with the
+ * first-stage derivative of the next step (3 ncell floats, when valid), and
+ * the thermal seed.  mm_state_size gives the largest size; mm_state_save
+ * writes it to a host buffer (synchronous); mm_state_load restores it into a
+ * context created with the same grid and parameters (temperature, DMI,
+ * cubic anisotropy and excitations set again by the caller before the
+ * load: setting a temperature resets the generator step that the load
+ * restores), binding the
+ * FSAL derivative to m_dev.  MM_EINVAL for a short buffer, another grid or a
+ * buffer that is not a saved state. */
+int mm_state_size(mm_ctx *c, int64_t *bytes);
+int mm_state_save(mm_ctx *c, void *host_buf, int64_t bytes);
+int mm_state_load(mm_ctx *c, const void *host_buf, int64_t bytes, const float *m_dev);
+
 /* Arithmetic of the DFT stages of the y convolution.  MM_PREC_FP32 (the
  * default) runs them in FP32 on the vector units.  MM_PREC_BF16 and
  * MM_PREC_FP16 run them as matrix-core GEMMs (16 x 16 x 32) on operands split

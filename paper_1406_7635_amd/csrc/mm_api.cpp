@@ -1315,6 +1315,84 @@ int mm_get_info(mm_ctx* c, mm_info* info) {
     return MM_OK;
 }
 
+// Saved solver state: header, the device-side solver record, and (when the
+// FSAL derivative is valid) the first-stage derivative of the next step.
+namespace {
+struct StateHeader {
+    uint32_t magic, version;
+    int32_t nx, ny, nz, devstate_bytes;
+    int32_t fsal_valid, fsal_precess, fsal_solver, reserved;
+    uint64_t seed;
+};
+constexpr uint32_t STATE_MAGIC = 0x4d4d5354u;  // "MMST"
+long long state_bytes(const mm_ctx* c, bool with_k) {
+    return (long long)sizeof(StateHeader) + (long long)sizeof(DevState) +
+           (with_k ? 3LL * c->ncell * (long long)sizeof(float) : 0LL);
+}
+}  // namespace
+
+int mm_state_size(mm_ctx* c, int64_t* bytes) {
+    if (!c || !bytes) return MM_EINVAL;
+    *bytes = state_bytes(c, true);
+    return MM_OK;
+}
+
+int mm_state_save(mm_ctx* c, void* host_buf, int64_t bytes) {
+    if (!c || !host_buf || bytes < state_bytes(c, c->fsal_valid)) return MM_EINVAL;
+    MM_CHECK(sync_state(c));
+    StateHeader h;
+    memset(&h, 0, sizeof(h));
+    h.magic = STATE_MAGIC;
+    h.version = 1;
+    h.nx = c->nx;
+    h.ny = c->ny;
+    h.nz = c->nz;
+    h.devstate_bytes = (int32_t)sizeof(DevState);
+    h.fsal_valid = c->fsal_valid ? 1 : 0;
+    h.fsal_precess = c->fsal_precess;
+    h.fsal_solver = c->fsal_solver;
+    h.seed = c->seed;
+    char* out = static_cast<char*>(host_buf);
+    memcpy(out, &h, sizeof(h));
+    memcpy(out + sizeof(h), c->hst, sizeof(DevState));
+    if (c->fsal_valid) {
+        // logical derivative 0 (the next step's first stage) lives in the
+        // physical buffer the device-side map names
+        const int phys = c->hst->perm[0] & 7;
+        MM_TRY(hipMemcpyAsync(out + sizeof(h) + sizeof(DevState), c->kbuf + (long long)phys * 3 * c->ncell,
+                              (size_t)3 * c->ncell * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        MM_TRY(hipStreamSynchronize(c->stream));
+    }
+    return MM_OK;
+}
+
+int mm_state_load(mm_ctx* c, const void* host_buf, int64_t bytes, const float* m_dev) {
+    if (!c || !host_buf || !m_dev || bytes < (int64_t)sizeof(StateHeader)) return MM_EINVAL;
+    StateHeader h;
+    memcpy(&h, host_buf, sizeof(h));
+    if (h.magic != STATE_MAGIC || h.version != 1 || h.devstate_bytes != (int32_t)sizeof(DevState)) return MM_EINVAL;
+    if (h.nx != c->nx || h.ny != c->ny || h.nz != c->nz) return MM_EINVAL;
+    if (bytes < state_bytes(c, h.fsal_valid != 0)) return MM_EINVAL;
+    const char* in = static_cast<const char*>(host_buf);
+    DevState ds;
+    memcpy(&ds, in + sizeof(h), sizeof(DevState));
+    for (int i = 0; i < 8; ++i)
+        if (ds.perm[i] < 0 || ds.perm[i] > 7) return MM_EINVAL;
+    MM_TRY(hipMemcpyAsync(c->st, &ds, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+    if (h.fsal_valid) {
+        const int phys = ds.perm[0];
+        MM_TRY(hipMemcpyAsync(c->kbuf + (long long)phys * 3 * c->ncell, in + sizeof(h) + sizeof(DevState),
+                              (size_t)3 * c->ncell * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    }
+    MM_TRY(hipStreamSynchronize(c->stream));
+    c->seed = h.seed;
+    c->fsal_valid = h.fsal_valid != 0;
+    c->fsal_m = m_dev;
+    c->fsal_precess = h.fsal_precess;
+    c->fsal_solver = h.fsal_solver;
+    return MM_OK;
+}
+
 int mm_demag_tensor_dump(mm_ctx* c, double* out_dev) {
     if (!c || !out_dev) return MM_EINVAL;
     if (c->pbc[0] == 0 && c->pbc[1] == 0 && c->pbc[2] == 0)

@@ -78,6 +78,9 @@ EXPORTS = {
     "mm_max_torque": (c_int32, [c_void_p, c_void_p, c_int32, ctypes.POINTER(c_double)]),
     "mm_solver_reset": (c_int32, [c_void_p]),
     "mm_get_info": (c_int32, [c_void_p, ctypes.POINTER(Info)]),
+    "mm_state_size": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
+    "mm_state_save": (c_int32, [c_void_p, c_void_p, c_int64]),
+    "mm_state_load": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
     "mm_demag_tensor_dump": (c_int32, [c_void_p, c_void_p]),
     "mm_demag_kernel_dump": (c_int32, [c_void_p, c_void_p]),
     "mm_exchange_dump": (c_int32, [c_void_p, c_void_p]),
@@ -374,6 +377,20 @@ class Context:
         inf = Info()
         _check(load().mm_get_info(self._h, ctypes.byref(inf)), "mm_get_info")
         return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    def state_save(self):
+        """Solver state (bytes) that continues a run bit for bit with the same
+        m and the (t, dt) mm_run returned (mm_state_save)."""
+        n = c_int64()
+        _check(load().mm_state_size(self._h, ctypes.byref(n)), "mm_state_size")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(load().mm_state_save(self._h, buf, n.value), "mm_state_save")
+        return buf.raw
+
+    def state_load(self, state, m):
+        """Restore a saved solver state; m holds the saved magnetisation."""
+        buf = ctypes.create_string_buffer(bytes(state), len(state))
+        _check(load().mm_state_load(self._h, buf, len(state), _ptr(self._vec(m))), "mm_state_load")
 
     def tensor_dump(self):
         """FP64 real-space tensor octant [6, nz, ny, nx] as the GPU computes it."""
