@@ -142,12 +142,24 @@ struct XLut {
 };
 
 // In the fused pass the torque of the finished stage is handed to the next
-// stage's combine through LDS: component c of a row pair's two rows ([row][x],
-// floats) in the upper half of slot buffer c, which the x-inverse results
-// (x < nx <= P/2, the lower half) leave free.  Needs P >= 2.
+// stage's combine through LDS.  Padded x: component c of a row pair's two rows
+// ([row][x], floats) in the upper half of slot buffer c, which the x-inverse
+// results (x < nx <= P/2, the lower half) leave free.  Unpadded periodic x
+// (FULL: nx = P, no free half): in place of the cell's own x-inverse result,
+// which only that cell's epilogue reads (components x, y of row rr in slot
+// rr; z of both rows in slot 2, row rr in its float rr).  Needs P >= 2.
 template <int P>
 __device__ inline float* ks_stage(cf* gbuf, int c) {
     return reinterpret_cast<float*>(gbuf + c * seq_len(P) + seq_len(P) / 2);
+}
+template <int P, bool FULL>
+__device__ inline float* k_slot(cf* gbuf, int c, int rr, int x, int nx) {
+    if constexpr (FULL) {
+        if (c < 2) return reinterpret_cast<float*>(gbuf + rr * seq_len(P) + lds_pad(x)) + c;
+        return reinterpret_cast<float*>(gbuf + 2 * seq_len(P) + lds_pad(x)) + rr;
+    } else {
+        return ks_stage<P>(gbuf, c) + rr * nx + x;
+    }
 }
 
 // Forward x pass of one workgroup: stage combine m_s = m0 + dt sum a k (FUSED:
@@ -158,7 +170,6 @@ __device__ inline float* ks_stage(cf* gbuf, int c) {
 template <int P, bool FUSED, bool FULL = false, int XW = 0>
 __device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
                                  RegionLut* lut_l, const XLut<P, XW>* lut, float a_last, int blk, int tid) {
-    static_assert(!(FUSED && FULL), "the fused pass hands k over in the upper half of the rows");
     constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P, XW>::GI;
     constexpr int SEQ = seq_len(P), GL = XCfg<P, XW>::GL;
     constexpr int MH = PPT / 2 + 1;
@@ -219,15 +230,13 @@ __device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds
     if constexpr (FUSED) {
         // the last term of the combine, k of the stage the x-inverse part of
         // this workgroup just finished (after the barrier that published it)
-        const float* k0 = ks_stage<P>(gbuf, c0);
-        const float* k1 = ks_stage<P>(gbuf, c1);
         const float w = rs.dt * a_last;
 #pragma unroll
         for (int m = 0; m < MV; ++m) {
             const int x = t + TPF * m;
             const int xc = x < a.nx ? x : a.nx - 1;
-            sv[m] += w * k0[rr0 * a.nx + xc];
-            sv[MV + m] += w * k1[rr1 * a.nx + xc];
+            sv[m] += w * *k_slot<P, FULL>(gbuf, c0, rr0, xc, a.nx);
+            sv[MV + m] += w * *k_slot<P, FULL>(gbuf, c1, rr1, xc, a.nx);
         }
     } else {
         lut->store(lut_l, tid);
@@ -295,7 +304,6 @@ __device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds
 template <int P, bool FUSED, bool DMI = false, bool FULL = false, int XW = 0>
 __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
                                  RegionLut* lut_l, double* red, int blk, int tid) {
-    static_assert(!(FUSED && FULL), "the fused pass hands k over in the upper half of the rows");
     constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P, XW>::GI, NTH = XCfg<P, XW>::NTH;
     constexpr int SEQ = seq_len(P), GL = XCfg<P, XW>::GL;
     constexpr int MH = PPT / 2 + 1;
@@ -373,10 +381,9 @@ __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds
         const float3 tq = epilogue<DMI>(a, rs, lut_l, mp, (long long)row * a.nx + x, x, y, z,
                                    make_float3(v01.x, v01.y, (rr & 1) ? v2.y : v2.x), acc);
         if constexpr (FUSED) {
-            const int o = (rr & 1) * a.nx + x;
-            ks_stage<P>(b3, 0)[o] = tq.x;
-            ks_stage<P>(b3, 1)[o] = tq.y;
-            ks_stage<P>(b3, 2)[o] = tq.z;
+            *k_slot<P, FULL>(b3, 0, rr & 1, x, a.nx) = tq.x;
+            *k_slot<P, FULL>(b3, 1, rr & 1, x, a.nx) = tq.y;
+            *k_slot<P, FULL>(b3, 2, rr & 1, x, a.nx) = tq.z;
         }
     };
     constexpr int NROW = 2 * GI;

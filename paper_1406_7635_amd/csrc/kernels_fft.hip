@@ -45,8 +45,10 @@ k_xinv(const FieldArgs a) {
 // followed, row pair by row pair, by the x-forward of stage s + 1 (combine
 // with k_s from LDS as the last term, m_{s+1} to af.ms, a second buffer since
 // other workgroups still read m_s for the exchange field).
-template <int P, bool DMI, int W>
-__global__ void __launch_bounds__((XCfg<P, W>::NTH)) __attribute__((amdgpu_waves_per_eu(6)))
+// (FULL: every x holds data, so the combine keeps twice the loads in flight;
+// its register budget is that of four waves per SIMD instead of six)
+template <int P, bool DMI, bool FULL, int W>
+__global__ void __launch_bounds__((XCfg<P, W>::NTH)) __attribute__((amdgpu_waves_per_eu(FULL ? 4 : 6)))
 k_xrow(const FieldArgs ai, const FieldArgs af, float a_last) {
     constexpr int GI = XCfg<P, W>::GI, GL = XCfg<P, W>::GL, NTH = XCfg<P, W>::NTH;
     extern __shared__ cf lds[];
@@ -58,11 +60,11 @@ k_xrow(const FieldArgs ai, const FieldArgs af, float a_last) {
     row_bases<GI>(ai, blk * GI, rbs, threadIdx.x);
     __syncthreads();
     RegionLut* lut_l = reinterpret_cast<RegionLut*>(lds + GI * GL);
-    xinv_part<P, true, DMI, false, W>(ai, rsi, lds, rbs, lut_l, red, blk, threadIdx.x);
+    xinv_part<P, true, DMI, FULL, W>(ai, rsi, lds, rbs, lut_l, red, blk, threadIdx.x);
     __syncthreads();
     // the next stage's pointers only now (short live ranges across the first part)
     const Resolved rsf = resolve(af);
-    xfwd_part<P, true, false, W>(af, rsf, lds, rbs, lut_l, nullptr, a_last, blk, threadIdx.x);
+    xfwd_part<P, true, FULL, W>(af, rsf, lds, rbs, lut_l, nullptr, a_last, blk, threadIdx.x);
 }
 
 
@@ -155,10 +157,20 @@ static hipError_t xrow_pw(const FieldArgs& ai, const FieldArgs& af, float a_last
                           hipEvent_t e1) {
     const size_t lds = x_lds<P, W>();
     const dim3 g(x_blocks_w<P, W>(ai.nrows)), b(XCfg<P, W>::NTH);
-    if (ai.dmi)
-        hipExtLaunchKernelGGL((k_xrow<P, true, W>), g, b, (uint32_t)lds, s, e0, e1, 0, ai, af, a_last);
-    else
-        hipExtLaunchKernelGGL((k_xrow<P, false, W>), g, b, (uint32_t)lds, s, e0, e1, 0, ai, af, a_last);
+#define MM_XR(D, F) \
+    hipExtLaunchKernelGGL((k_xrow<P, D, F, W>), g, b, (uint32_t)lds, s, e0, e1, 0, ai, af, a_last)
+    if (ai.dmi) {
+        if (ai.full_x)
+            MM_XR(true, true);
+        else
+            MM_XR(true, false);
+    } else {
+        if (ai.full_x)
+            MM_XR(false, true);
+        else
+            MM_XR(false, false);
+    }
+#undef MM_XR
     return hipGetLastError();
 }
 template <int P>
@@ -220,8 +232,10 @@ static hipError_t configure_xw(void) {
     if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, false, true, W>, L);
     if (e == hipSuccess) e = allow_lds<P>((const void*)k_xinv<P, true, true, W>, L);
     if constexpr (P >= 8) {
-        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, false, W>, L);
-        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, true, W>, L);
+        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, false, false, W>, L);
+        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, true, false, W>, L);
+        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, false, true, W>, L);
+        if (e == hipSuccess) e = allow_lds<P>((const void*)k_xrow<P, true, true, W>, L);
     }
     return e;
 }

@@ -532,9 +532,9 @@ int attempt(mm_ctx* c, float* m, const Tableau& tb, int precess, bool check_done
         return attempt_surrogate(c, m, tb, precess, check_done);
     }
     float* fin_ms = c->ms;
-    // the fused pass hands k_s over in the zero-padded half of the rows, which
-    // an unpadded periodic x does not have
-    if (c->demag_on && c->px >= 8 && S > 2 && !c->full_x) {
+    // (an unpadded periodic x of 4096 points keeps the separate passes: its
+    // fused form would hold 16 points of both parts per thread)
+    if (c->demag_on && c->px >= 8 && S > 2 && !(c->full_x && c->px >= 4096)) {
         if (!c->khat_ready) return MM_ESTATE;
         float* buf[2] = {c->ms, c->ms2};
         int cur = 0;

@@ -202,6 +202,51 @@ def test_unpadded_periodic_lengths_and_run(gpu):
     ctx.close()
 
 
+FUSED_CASES = [
+    ((64, 32, 1), (1, 1, 0), False),    # x and y unpadded
+    ((128, 40, 1), (2, 0, 0), False),   # x unpadded, y open, ragged
+    ((32, 20, 5), (1, 0, 1), False),    # 3D, x unpadded
+    ((64, 24, 1), (1, 0, 0), True),     # x unpadded, with DMI
+    ((128, 40, 1), (0, 0, 0), False),   # open x (padded fused pass): the same bars
+]
+
+
+@pytest.mark.parametrize("grid,pbc,dmi", FUSED_CASES, ids=[str(c[0]) + str(c[1]) + str(c[2]) for c in FUSED_CASES])
+def test_fused_stage_pass_unpadded_x(gpu, grid, pbc, dmi):
+    """Dormand-Prince attempts on grids whose x axis is periodic and unpadded,
+    where the x-inverse of each inner stage and the x-forward of the next run
+    as one pass that hands the torque over in place of the cell's own
+    x-inverse result: three accepted attempts at a fixed step against the
+    oracle's embedded steps (m within 2e-6, error estimate within 5 %)."""
+    case = synth.random_problem(grid, (2e-9, 2e-9, 2e-9), seed=sum(grid) + 11, nregions=4)
+    if dmi:
+        rng = np.random.Generator(np.random.PCG64(5))
+        case["params"]["dind"] = np.zeros(256)
+        case["params"]["dind"][:4] = rng.uniform(-3e-3, 3e-3, 4)
+    ctx, prob, m = pair(case, pbc)
+    info = ctx.info()
+    assert info["px"] == (grid[0] if pbc[0] else 2 * grid[0])
+    f = prob.torque
+    m_ref = case["m0"].astype(np.float64)
+    k1 = f(m_ref)
+    dt = 2e-14
+    opts = mm.solver_opts(max_err=1.0)  # every attempt accepted, dt grows at most 2x
+    t = 0.0
+    for _ in range(3):
+        acc, t1, dtn, err = ctx.rk45_step(m, t, dt, opts)
+        assert acc
+        ms, k1, eps = ointegrate.embedded_step(f, m_ref, k1, dt, ointegrate.DP45)
+        m_ref = ointegrate.normalize(ms)  # k1 of the next attempt: the last stage's (first same as last)
+        d = float(np.max(np.abs(to_np(m) - m_ref)))
+        log("fused unpadded-x DP45", grid, pbc, "dmi" if dmi else "", "|dm| %.2e err %.3e / %.3e" % (d, err, eps))
+        assert d < 2e-6
+        # the estimate is a small difference of stage torques: FP32 leaves it a
+        # few per cent off the FP64 value (it only scales the next step)
+        assert abs(err - eps) <= 5e-2 * eps
+        t = t1
+    ctx.close()
+
+
 def test_bad_images_and_surrogate_rejected(gpu):
     """Negative image counts and oversized windows are refused; the surrogate
     (trained for open boundaries) refuses a periodic grid."""
