@@ -301,6 +301,7 @@ def ensemble_variant(steps, warmup, n=512):
     b.run(m, max(1, warmup))
     untuned = timed(max(1, steps // 4))
     grids = b.autotune(m)
+    tiles = {p: b.get_tile(p) for p in ("x", "conv2d")}
     b.run(m, max(1, warmup))
     val, wall, na, act, acc, rej = timed(steps)
     b.set_graph(False)
@@ -312,7 +313,7 @@ def ensemble_variant(steps, warmup, n=512):
     return {"value": val, "unit": "Beff evals*cells/s", "members": n, "cells": int(ncell.sum()),
             "attempts": na, "ms_per_attempt": 1e3 * wall / na, "accepted_steps": acc, "rejected_steps": rej,
             "running_after": act, "alg_bytes_per_attempt": bytes_att, "alg_GBs": gbs,
-            "alg_frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "persistent_grids": grids,
+            "alg_frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "persistent_grids": grids, "tile_shapes": tiles,
             "untuned_value": untuned[0], "direct_launch_value": direct[0],
             "workload": "512 independent sims: nx, ny from {32,64,128,256}, nz from {1,2}, cubic cells "
                         "U(2,5) nm, Msat U(4e5,1.2e6), Aex U(5e-12,2e-11), alpha U(0.005,0.5), random m0, "

@@ -463,9 +463,19 @@ int mm_batch_set_graph(mm_batch *b, int32_t enable);
  * the current value. */
 int mm_batch_set_grid(mm_batch *b, int32_t pass, int32_t grid);
 int mm_batch_get_grid(mm_batch *b, int32_t pass, int32_t *grid);
-/* Time every pass of one attempt at m_dev for a few persistent grid sizes
- * (whole-chip multiples of the pass's resident workgroups, and one
- * workgroup per tile) and keep the fastest.  Overwrites the stage buffers
+/* Tile shape of pass 0 (x passes) or 1 (2D y convolution): 0 wide (768 /
+ * 256 threads per workgroup, the row pairs or columns of the single-grid
+ * wide workgroup per work item) or 1 narrow (192 / 64 threads, a quarter of
+ * them).  The narrow shape serves padded lengths up to 512: MM_EUNSUPPORTED
+ * when a member's px (pass 0) or py (pass 1) is larger, or for another pass.
+ * Changing the shape resets the pass's grid to one workgroup per tile.
+ * Results do not depend on the shape.  mm_batch_get_tile reads it. */
+int mm_batch_set_tile(mm_batch *b, int32_t pass, int32_t tile);
+int mm_batch_get_tile(mm_batch *b, int32_t pass, int32_t *tile);
+/* Time every pass of one attempt at m_dev for each tile shape that serves
+ * every member and a few persistent grid sizes per shape (whole-chip
+ * multiples of the pass's resident workgroups, and one workgroup per tile),
+ * and keep the fastest (shape, grid) per pass.  Overwrites the stage buffers
  * (the next run recomputes the first derivative); m_dev is only read.
  * Synchronises. */
 int mm_batch_autotune(mm_batch *b, const float *m_dev);

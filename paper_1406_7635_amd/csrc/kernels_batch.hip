@@ -6,7 +6,10 @@
 // (fft_passes.h), instantiated for the member's padded length.  The x passes
 // and the 3D column passes of every padded length 64 ... 1024 have 768 threads
 // and 55 KB of exchange LDS, the 2D column pass 256 threads and 36 KB, so one
-// launch shape serves every member.
+// launch shape serves every member.  The x passes and the 2D column pass also
+// come in a narrow tile shape (a quarter of the row pairs or columns per item:
+// 192 and 64 threads) for ensembles whose padded lengths are all <= 512; the
+// host picks the shape per pass.
 //
 // Items are dealt XCD-aware: the work list is cut into 8 contiguous chunks,
 // and the workgroups of XCD x (dispatch index = x mod 8) walk chunk x, so the
@@ -27,6 +30,18 @@ namespace {
 constexpr int BX_NTH = 768;   // x passes and the 3D column passes
 constexpr int BC3_NTH = 256;  // 2D column pass
 constexpr int XMAX_GI = XCfg<64>::GI;
+// narrow tile shape (TILE_NARROW) of the x passes and the 2D column pass:
+// lengths up to 512
+constexpr int BXN_NTH = 192;
+constexpr int BC3N_NTH = 64;
+constexpr int NARROW_MAX = 512;
+template <int TILE>
+constexpr int bx_nth() { return TILE == TILE_NARROW ? BXN_NTH : BX_NTH; }
+template <int TILE>
+constexpr int bc3_nth() { return TILE == TILE_NARROW ? BC3N_NTH : BC3_NTH; }
+// lengths a tile shape serves
+template <int P, int TILE>
+constexpr bool tile_serves() { return TILE == TILE_WIDE || P <= NARROW_MAX; }
 
 #define MB_XCASES(M) M(64) M(128) M(256) M(512) M(1024)
 #define MB_ZCASES(M) M(4) M(8) M(16)
@@ -34,7 +49,8 @@ constexpr int XMAX_GI = XCfg<64>::GI;
 #define M(p)                                                                        \
     static_assert(XCfg<p>::NTH == BX_NTH && ColCfg<p>::NTH == BX_NTH, "x / y shape"); \
     static_assert(Col3Cfg<p>::NTH == BC3_NTH && use_col3<p>(), "2D column shape");    \
-    static_assert(XCfg<p>::GI <= XMAX_GI, "row-pair table");
+    static_assert(XCfg<p>::GI <= XMAX_GI, "row-pair table");                          \
+    static_assert(p > NARROW_MAX || (XCfg<p, 1>::NTH == BXN_NTH && Col3Cfg<p, 1>::NTH == BC3N_NTH), "narrow");
 MB_XCASES(M)
 #undef M
 #define M(p) static_assert(ColCfg<p>::NTH == BX_NTH, "z shape");
@@ -171,39 +187,41 @@ __device__ inline ColArgs member_col(const ColArgs& b, const BMember& mb, int i,
     return a;
 }
 
-// One x-pass item: row-pair tile blk of member i.
-template <int P, int KIND>
+// One x-pass item: row-pair tile blk of member i (tile shape TILE: row pairs
+// per item as in the single-grid pass of that width).
+template <int P, int KIND, int TILE>
 __device__ inline void bx_item(const FieldArgs& fi, const FieldArgs& ff, float a_last, const BMember& mb, int i,
                                int blk, int tid, cf* lds, long long* rbs, double* red) {
-    constexpr int GI = XCfg<P>::GI, GL = XCfg<P>::GL;
+    constexpr int XW = TILE == TILE_NARROW ? 1 : 0;
+    constexpr int GI = XCfg<P, XW>::GI, GL = XCfg<P, XW>::GL;
     RegionLut* lut_l = reinterpret_cast<RegionLut*>(lds + GI * GL);
     const FieldArgs a = member_field(fi, mb, i);
     const Resolved rs = resolve(a);
     if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
     row_bases<GI>(a, blk * GI, rbs, tid);
     if constexpr (KIND == BX_FWD) {
-        XLut<P> lut;
+        XLut<P, XW> lut;
         lut.load(a, tid);
-        xfwd_part<P, false>(a, rs, lds, rbs, lut_l, &lut, 0.f, blk, tid);
+        xfwd_part<P, false, false, XW>(a, rs, lds, rbs, lut_l, &lut, 0.f, blk, tid);
     } else if constexpr (KIND == BX_INV) {
         __syncthreads();
-        xinv_part<P, false>(a, rs, lds, rbs, lut_l, red, blk, tid);
+        xinv_part<P, false, false, false, XW>(a, rs, lds, rbs, lut_l, red, blk, tid);
     } else {
         __syncthreads();
-        xinv_part<P, true>(a, rs, lds, rbs, lut_l, red, blk, tid);
+        xinv_part<P, true, false, false, XW>(a, rs, lds, rbs, lut_l, red, blk, tid);
         __syncthreads();
         const FieldArgs af = member_field(ff, mb, i);
         const Resolved rsf = resolve(af);
-        xfwd_part<P, true, false, 0>(af, rsf, lds, rbs, lut_l, nullptr, a_last, blk, tid);
+        xfwd_part<P, true, false, XW>(af, rsf, lds, rbs, lut_l, nullptr, a_last, blk, tid);
     }
 }
 
-template <int KIND>
-__global__ void __launch_bounds__(BX_NTH) __attribute__((amdgpu_waves_per_eu(6))) k_bx(const BatchList l, const FieldArgs fi, const FieldArgs ff,
-                                               float a_last) {
+template <int KIND, int TILE>
+__global__ void __launch_bounds__(bx_nth<TILE>()) __attribute__((amdgpu_waves_per_eu(6)))
+k_bx(const BatchList l, const FieldArgs fi, const FieldArgs ff, float a_last) {
     extern __shared__ cf lds[];
     __shared__ long long rbs[2 * XMAX_GI];
-    __shared__ double red[(BX_NTH / 64) * 6];
+    __shared__ double red[(bx_nth<TILE>() / 64) * 6];
     const ItemRange r = item_range(l.nitems);
     for (int it = r.it; it < r.end; it += r.step) {
         const unsigned int item = uload(l.items + it);
@@ -212,9 +230,10 @@ __global__ void __launch_bounds__(BX_NTH) __attribute__((amdgpu_waves_per_eu(6))
         __syncthreads();  // the previous item is done with LDS
         const int tid = opaque_tid();
         switch (mb.px) {
-#define M(p)                                                     \
-    case p:                                                      \
-        bx_item<p, KIND>(fi, ff, a_last, mb, i, blk, tid, lds, rbs, red);  \
+#define M(p)                                                                       \
+    case p:                                                                        \
+        if constexpr (tile_serves<p, TILE>())                                      \
+            bx_item<p, KIND, TILE>(fi, ff, a_last, mb, i, blk, tid, lds, rbs, red);  \
         break;
             MB_XCASES(M)
 #undef M
@@ -224,7 +243,9 @@ __global__ void __launch_bounds__(BX_NTH) __attribute__((amdgpu_waves_per_eu(6))
     }
 }
 
-__global__ void __launch_bounds__(BC3_NTH, 3) k_bcol3(const BatchList l, const ColArgs b) {
+template <int TILE>
+__global__ void __launch_bounds__(bc3_nth<TILE>(), 3) k_bcol3(const BatchList l, const ColArgs b) {
+    constexpr int W = TILE == TILE_NARROW ? 1 : 0;
     extern __shared__ cf lds[];
     const ItemRange r = item_range(l.nitems);
     for (int it = r.it; it < r.end; it += r.step) {
@@ -235,9 +256,9 @@ __global__ void __launch_bounds__(BC3_NTH, 3) k_bcol3(const BatchList l, const C
         __syncthreads();
         const int tid = opaque_tid();
         switch (mb.py) {
-#define M(p)                         \
-    case p:                          \
-        col3_body<p>(a, blk, lds, tid);  \
+#define M(p)                                                                    \
+    case p:                                                                     \
+        if constexpr (tile_serves<p, TILE>()) col3_body<p, false, W>(a, blk, lds, tid);  \
         break;
             MB_XCASES(M)
 #undef M
@@ -368,27 +389,30 @@ constexpr size_t max2(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t BX_LDS = max2(max2(max2(x_lds<64>(), x_lds<128>()), max2(x_lds<256>(), x_lds<512>())), x_lds<1024>());
 constexpr size_t BC3_LDS =
     max2(max2(max2(col3_lds<64>(), col3_lds<128>()), max2(col3_lds<256>(), col3_lds<512>())), col3_lds<1024>());
+constexpr size_t BXN_LDS = max2(max2(x_lds<64, 1>(), x_lds<128, 1>()), max2(x_lds<256, 1>(), x_lds<512, 1>()));
+constexpr size_t BC3N_LDS =
+    max2(max2(col3_lds<64, 1>(), col3_lds<128, 1>()), max2(col3_lds<256, 1>(), col3_lds<512, 1>()));
 constexpr size_t BY_LDS = max2(max2(max2(col_lds<64, COL_FWD, 4>(), col_lds<128, COL_FWD, 4>()),
                                     max2(col_lds<256, COL_FWD, 4>(), col_lds<512, COL_FWD, 4>())),
                                col_lds<1024, COL_FWD, 4>());
 
-// host-side tile counts per padded length
-int x_gi(int p) {
+// host-side tile counts per padded length (0: a length the shape does not serve)
+int x_gi(int p, int tile = TILE_WIDE) {
     switch (p) {
 #define M(q) \
     case q:  \
-        return XCfg<q>::GI;
+        return tile == TILE_WIDE ? XCfg<q>::GI : (q <= NARROW_MAX ? XCfg<q, 1>::GI : 0);
         MB_XCASES(M)
 #undef M
         default:
             return 0;
     }
 }
-int col3_t(int p) {
+int col3_t(int p, int tile = TILE_WIDE) {
     switch (p) {
 #define M(q) \
     case q:  \
-        return Col3Cfg<q>::T;
+        return tile == TILE_WIDE ? Col3Cfg<q>::T : (q <= NARROW_MAX ? Col3Cfg<q, 1>::T : 0);
         MB_XCASES(M)
 #undef M
         default:
@@ -443,12 +467,15 @@ struct PassShape {
     size_t lds;
 };
 
-PassShape pass_shape(int pass) {
+PassShape pass_shape(int pass, int tile = TILE_WIDE) {
+    const bool nar = tile == TILE_NARROW;
     switch (pass) {
         case BP_X:
-            return {(const void*)k_bx<BX_ROW>, BX_NTH, BX_LDS};
+            return nar ? PassShape{(const void*)k_bx<BX_ROW, TILE_NARROW>, BXN_NTH, BXN_LDS}
+                       : PassShape{(const void*)k_bx<BX_ROW, TILE_WIDE>, BX_NTH, BX_LDS};
         case BP_C3:
-            return {(const void*)k_bcol3, BC3_NTH, BC3_LDS};
+            return nar ? PassShape{(const void*)k_bcol3<TILE_NARROW>, BC3N_NTH, BC3N_LDS}
+                       : PassShape{(const void*)k_bcol3<TILE_WIDE>, BC3_NTH, BC3_LDS};
         case BP_Y:
             return {(const void*)k_bcoly<BC_YFWD>, BX_NTH, BY_LDS};
         case BP_Z4:
@@ -478,12 +505,21 @@ bool batch_supported(int px, int py, int pz) {
     return x_gi(px) > 0 && x_gi(py) > 0 && (pz == 1 || pz == 4 || pz == 8 || pz == 16);
 }
 
-int batch_tiles(int pass, const BMember& m) {
+bool batch_tile_serves(int pass, int tile, const BMember& m) {
+    if (tile == TILE_WIDE) return true;
+    if (tile != TILE_NARROW) return false;
+    if (pass == BP_X) return x_gi(m.px, tile) > 0;
+    if (pass == BP_C3) return m.pz != 1 || col3_t(m.py, tile) > 0;
+    return false;
+}
+
+int batch_tiles(int pass, const BMember& m, int tile) {
+    if (!batch_tile_serves(pass, tile, m)) return 0;
     switch (pass) {
         case BP_X:
-            return cdiv((m.nrows + 1) / 2, x_gi(m.px));
+            return cdiv((m.nrows + 1) / 2, x_gi(m.px, tile));
         case BP_C3:
-            return m.pz == 1 ? cdiv(m.px / 2, col3_t(m.py)) : 0;
+            return m.pz == 1 ? cdiv(m.px / 2, col3_t(m.py, tile)) : 0;
         case BP_Y:
             return m.pz > 1 && !yz_supported(m.py, m.pz) ? cdiv(m.nz, col_t(m.py)) * m.kx : 0;
         case BP_Z4:
@@ -504,21 +540,26 @@ int batch_tiles(int pass, const BMember& m) {
     }
 }
 
-hipError_t batch_resident(int pass, int* per_cu) {
-    const PassShape ps = pass_shape(pass);
+hipError_t batch_resident(int pass, int tile, int* per_cu) {
+    const PassShape ps = pass_shape(pass, tile);
     if (!ps.fn) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, ps.fn, ps.nth, ps.lds);
 }
 
 hipError_t configure_batch_kernels(void) {
-    const PassShape extra[] = {{(const void*)k_bx<BX_FWD>, BX_NTH, BX_LDS},
-                               {(const void*)k_bx<BX_INV>, BX_NTH, BX_LDS},
+    const PassShape extra[] = {{(const void*)k_bx<BX_FWD, TILE_WIDE>, BX_NTH, BX_LDS},
+                               {(const void*)k_bx<BX_INV, TILE_WIDE>, BX_NTH, BX_LDS},
+                               {(const void*)k_bx<BX_FWD, TILE_NARROW>, BXN_NTH, BXN_LDS},
+                               {(const void*)k_bx<BX_INV, TILE_NARROW>, BXN_NTH, BXN_LDS},
                                {(const void*)k_bcoly<BC_YINV>, BX_NTH, BY_LDS}};
     for (int p = 0; p < BP_N; ++p) {
-        const PassShape ps = pass_shape(p);
-        if (ps.lds == 0) continue;
-        const hipError_t e = hipFuncSetAttribute(ps.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ps.lds);
-        if (e != hipSuccess) return e;
+        for (int tile : {TILE_WIDE, TILE_NARROW}) {
+            if (tile == TILE_NARROW && p != BP_X && p != BP_C3) continue;
+            const PassShape ps = pass_shape(p, tile);
+            if (ps.lds == 0) continue;
+            const hipError_t e = hipFuncSetAttribute(ps.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ps.lds);
+            if (e != hipSuccess) return e;
+        }
     }
     for (const PassShape& ps : extra) {
         const hipError_t e = hipFuncSetAttribute(ps.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ps.lds);
@@ -527,19 +568,20 @@ hipError_t configure_batch_kernels(void) {
     return hipSuccess;
 }
 
-hipError_t launch_bx(int kind, const BatchList& l, int grid, const FieldArgs& fi, const FieldArgs& ff, float a_last,
-                     hipStream_t s) {
-    if (l.nitems <= 0) return hipSuccess;
-    if (check_grid(l, grid) != hipSuccess) return hipErrorInvalidValue;
+template <int TILE>
+static hipError_t launch_bx_t(int kind, const BatchList& l, int grid, const FieldArgs& fi, const FieldArgs& ff,
+                              float a_last, hipStream_t s) {
+    constexpr int NTH = bx_nth<TILE>();
+    constexpr size_t LDS = TILE == TILE_NARROW ? BXN_LDS : BX_LDS;
     switch (kind) {
         case BX_FWD:
-            hipLaunchKernelGGL(k_bx<BX_FWD>, dim3(grid), dim3(BX_NTH), BX_LDS, s, l, fi, ff, a_last);
+            hipLaunchKernelGGL((k_bx<BX_FWD, TILE>), dim3(grid), dim3(NTH), LDS, s, l, fi, ff, a_last);
             break;
         case BX_ROW:
-            hipLaunchKernelGGL(k_bx<BX_ROW>, dim3(grid), dim3(BX_NTH), BX_LDS, s, l, fi, ff, a_last);
+            hipLaunchKernelGGL((k_bx<BX_ROW, TILE>), dim3(grid), dim3(NTH), LDS, s, l, fi, ff, a_last);
             break;
         case BX_INV:
-            hipLaunchKernelGGL(k_bx<BX_INV>, dim3(grid), dim3(BX_NTH), BX_LDS, s, l, fi, ff, a_last);
+            hipLaunchKernelGGL((k_bx<BX_INV, TILE>), dim3(grid), dim3(NTH), LDS, s, l, fi, ff, a_last);
             break;
         default:
             return hipErrorInvalidValue;
@@ -547,10 +589,24 @@ hipError_t launch_bx(int kind, const BatchList& l, int grid, const FieldArgs& fi
     return hipGetLastError();
 }
 
-hipError_t launch_bcol3(const BatchList& l, int grid, const ColArgs& base, hipStream_t s) {
+hipError_t launch_bx(int kind, const BatchList& l, int grid, const FieldArgs& fi, const FieldArgs& ff, float a_last,
+                     hipStream_t s, int tile) {
     if (l.nitems <= 0) return hipSuccess;
     if (check_grid(l, grid) != hipSuccess) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_bcol3, dim3(grid), dim3(BC3_NTH), BC3_LDS, s, l, base);
+    if (tile == TILE_NARROW) return launch_bx_t<TILE_NARROW>(kind, l, grid, fi, ff, a_last, s);
+    if (tile == TILE_WIDE) return launch_bx_t<TILE_WIDE>(kind, l, grid, fi, ff, a_last, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bcol3(const BatchList& l, int grid, const ColArgs& base, hipStream_t s, int tile) {
+    if (l.nitems <= 0) return hipSuccess;
+    if (check_grid(l, grid) != hipSuccess) return hipErrorInvalidValue;
+    if (tile == TILE_NARROW)
+        hipLaunchKernelGGL(k_bcol3<TILE_NARROW>, dim3(grid), dim3(BC3N_NTH), BC3N_LDS, s, l, base);
+    else if (tile == TILE_WIDE)
+        hipLaunchKernelGGL(k_bcol3<TILE_WIDE>, dim3(grid), dim3(BC3_NTH), BC3_LDS, s, l, base);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

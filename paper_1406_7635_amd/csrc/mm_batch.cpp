@@ -28,8 +28,13 @@ struct mm_batch {
     int pt = 1, twshift = 0;
     // device buffers
     BMember* mem = nullptr;
-    unsigned int* items[BP_N] = {};
-    int nitems[BP_N] = {};
+    // work lists per pass and tile shape (TILE_WIDE, TILE_NARROW); a narrow
+    // list exists only for the x passes and the 2D column pass, and only when
+    // the narrow shape serves every member
+    unsigned int* items[BP_N][2] = {};
+    int nitems[BP_N][2] = {};
+    bool tile_ok[BP_N][2] = {};
+    int tile[BP_N] = {};  // the shape in use
     int grid[BP_N] = {};
     uint8_t* region = nullptr;
     double* params64 = nullptr;
@@ -69,8 +74,9 @@ void free_batch(mm_batch* b) {
                     b->khat, b->zker, b->kbuf,  b->ms,       b->ms2, b->st, b->active};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    for (unsigned int* p : b->items)
-        if (p) (void)hipFree(p);
+    for (auto& pl : b->items)
+        for (unsigned int* p : pl)
+            if (p) (void)hipFree(p);
     if (b->hst) (void)hipHostFree(b->hst);
     if (b->hactive) (void)hipHostFree(b->hactive);
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
@@ -92,11 +98,14 @@ int leave(mm_batch* b) {
     return MM_OK;
 }
 
+// work items of pass p in its current tile shape (0: no member uses the pass)
+int nitems_of(const mm_batch* b, int pass) { return b->nitems[pass][b->tile[pass]]; }
+
 BatchList list(const mm_batch* b, int pass) {
     BatchList l;
     l.mem = b->mem;
-    l.items = b->items[pass];
-    l.nitems = b->nitems[pass];
+    l.items = b->items[pass][b->tile[pass]];
+    l.nitems = nitems_of(b, pass);
     return l;
 }
 
@@ -104,7 +113,7 @@ BatchList list(const mm_batch* b, int pass) {
 int full_grid(int nitems) { return ((nitems + 7) / 8) * 8; }
 
 int grid_of(const mm_batch* b, int pass) {
-    return b->grid[pass] > 0 ? b->grid[pass] : full_grid(b->nitems[pass]);
+    return b->grid[pass] > 0 ? b->grid[pass] : full_grid(nitems_of(b, pass));
 }
 
 // Base field arguments: the ensemble's buffers; the kernels add each member's offsets.
@@ -142,13 +151,13 @@ ColArgs base_col(const mm_batch* b, bool check_done) {
 int run_cols(mm_batch* b, bool check_done) {
     const ColArgs c = base_col(b, check_done);
     hipStream_t s = b->stream;
-    if (b->has2d) MM_TRY(launch_bcol3(list(b, BP_C3), grid_of(b, BP_C3), c, s));
+    if (b->has2d) MM_TRY(launch_bcol3(list(b, BP_C3), grid_of(b, BP_C3), c, s, b->tile[BP_C3]));
     for (int p : {BP_YZ4, BP_YZ8})
-        if (b->nitems[p] > 0) MM_TRY(launch_byz(p, list(b, p), grid_of(b, p), c, s));
-    if (b->nitems[BP_Y] > 0) {
+        if (nitems_of(b, p) > 0) MM_TRY(launch_byz(p, list(b, p), grid_of(b, p), c, s));
+    if (nitems_of(b, BP_Y) > 0) {
         MM_TRY(launch_bcoly(0, list(b, BP_Y), grid_of(b, BP_Y), c, s));
         for (int p : {BP_Z4, BP_Z8, BP_Z16})
-            if (b->nitems[p] > 0) MM_TRY(launch_bzconv(p, list(b, p), grid_of(b, p), c, s));
+            if (nitems_of(b, p) > 0) MM_TRY(launch_bzconv(p, list(b, p), grid_of(b, p), c, s));
         MM_TRY(launch_bcoly(1, list(b, BP_Y), grid_of(b, BP_Y), c, s));
     }
     return MM_OK;
@@ -159,9 +168,10 @@ int run_field(mm_batch* b, FieldArgs& a) {
     if (!b->khat_ready) return MM_ESTATE;
     a.flags |= EPI_HAS_DEMAG;
     const bool cd = (a.flags & EPI_CHECK_DONE) != 0;
-    MM_TRY(launch_bx(BX_FWD, list(b, BP_X), grid_of(b, BP_X), a, a, 0.f, b->stream));
+    const int tx = b->tile[BP_X];
+    MM_TRY(launch_bx(BX_FWD, list(b, BP_X), grid_of(b, BP_X), a, a, 0.f, b->stream, tx));
     MM_CHECK(run_cols(b, cd));
-    MM_TRY(launch_bx(BX_INV, list(b, BP_X), grid_of(b, BP_X), a, a, 0.f, b->stream));
+    MM_TRY(launch_bx(BX_INV, list(b, BP_X), grid_of(b, BP_X), a, a, 0.f, b->stream, tx));
     return MM_OK;
 }
 
@@ -181,12 +191,12 @@ int enqueue_attempt(mm_batch* b, float* m) {
     const int S = tb.stages;
     hipStream_t s = b->stream;
     const BatchList lx = list(b, BP_X);
-    const int gx = grid_of(b, BP_X);
+    const int gx = grid_of(b, BP_X), tx = b->tile[BP_X];
     float* buf[2] = {b->ms, b->ms2};
     int cur = 0;
     FieldArgs a = stage_field(b, m, 1);
     a.ms = buf[cur];
-    MM_TRY(launch_bx(BX_FWD, lx, gx, a, a, 0.f, s));
+    MM_TRY(launch_bx(BX_FWD, lx, gx, a, a, 0.f, s, tx));
     MM_CHECK(run_cols(b, true));
     for (int st = 1; st < S - 1; ++st) {
         FieldArgs ai = stage_field(b, m, st);
@@ -199,13 +209,13 @@ int enqueue_attempt(mm_batch* b, float* m) {
             a_last = af.sd.a[af.sd.nk - 1];
             --af.sd.nk;
         }
-        MM_TRY(launch_bx(BX_ROW, lx, gx, ai, af, a_last, s));
+        MM_TRY(launch_bx(BX_ROW, lx, gx, ai, af, a_last, s, tx));
         cur ^= 1;
         MM_CHECK(run_cols(b, true));
     }
     FieldArgs al = stage_field(b, m, S - 1);
     al.ms = buf[cur];
-    MM_TRY(launch_bx(BX_INV, lx, gx, al, al, 0.f, s));
+    MM_TRY(launch_bx(BX_INV, lx, gx, al, al, 0.f, s, tx));
     MM_TRY(launch_bcontroller(b->st, b->n, S - 1, S - 1, 1, b->active, s));
     MM_TRY(launch_bfinalize(list(b, BP_F), grid_of(b, BP_F), buf[cur], m, b->st, s));
     return MM_OK;
@@ -333,14 +343,22 @@ int mm_batch_create(mm_batch** out, int32_t n, const mm_grid* grids, const mm_pa
         return MM_EUNSUPPORTED;
     }
     b->twshift = ilog2(b->pt);
-    std::vector<std::vector<unsigned int>> items(BP_N);
+    std::vector<std::vector<unsigned int>> items[2] = {std::vector<std::vector<unsigned int>>(BP_N),
+                                                       std::vector<std::vector<unsigned int>>(BP_N)};
     for (int p = 0; p < BP_N; ++p) {
-        for (int i = 0; i < n; ++i) {
-            const int t = batch_tiles(p, b->hmem[i]);
-            if (t > 65536) st = MM_EUNSUPPORTED;
-            for (int k = 0; k < t && k < 65536; ++k) items[p].push_back(((unsigned int)i << 16) | (unsigned int)k);
+        for (int tl : {TILE_WIDE, TILE_NARROW}) {
+            bool ok = tl == TILE_WIDE || p == BP_X || p == BP_C3;
+            for (int i = 0; i < n && ok; ++i) ok = batch_tile_serves(p, tl, b->hmem[i]);
+            b->tile_ok[p][tl] = ok;
+            if (!ok) continue;
+            for (int i = 0; i < n; ++i) {
+                const int t = batch_tiles(p, b->hmem[i], tl);
+                if (t > 65536) st = MM_EUNSUPPORTED;
+                for (int k = 0; k < t && k < 65536; ++k)
+                    items[tl][p].push_back(((unsigned int)i << 16) | (unsigned int)k);
+            }
+            b->nitems[p][tl] = (int)items[tl][p].size();
         }
-        b->nitems[p] = (int)items[p].size();
     }
     if (st != MM_OK) {
         delete b;
@@ -353,7 +371,8 @@ int mm_batch_create(mm_batch** out, int32_t n, const mm_grid* grids, const mm_pa
     };
     const size_t nc = (size_t)b->ncell;
     A((void**)&b->mem, (size_t)n * sizeof(BMember));
-    for (int p = 0; p < BP_N; ++p) A((void**)&b->items[p], items[p].size() * sizeof(unsigned int));
+    for (int tl : {TILE_WIDE, TILE_NARROW})
+        for (int p = 0; p < BP_N; ++p) A((void**)&b->items[p][tl], items[tl][p].size() * sizeof(unsigned int));
     A((void**)&b->region, nc);
     A((void**)&b->params64, (size_t)n * sizeof(mm_params));
     A((void**)&b->lut, (size_t)n * NREG * sizeof(RegionLut));
@@ -380,10 +399,11 @@ int mm_batch_create(mm_batch** out, int32_t n, const mm_grid* grids, const mm_pa
         if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_in, 0);
         // host arrays are copied synchronously (they are the caller's, pageable)
         if (e == hipSuccess) e = hipMemcpy(b->mem, b->hmem.data(), (size_t)n * sizeof(BMember), hipMemcpyHostToDevice);
-        for (int p = 0; p < BP_N && e == hipSuccess; ++p)
-            if (!items[p].empty())
-                e = hipMemcpy(b->items[p], items[p].data(), items[p].size() * sizeof(unsigned int),
-                              hipMemcpyHostToDevice);
+        for (int tl : {TILE_WIDE, TILE_NARROW})
+            for (int p = 0; p < BP_N && e == hipSuccess; ++p)
+                if (!items[tl][p].empty())
+                    e = hipMemcpy(b->items[p][tl], items[tl][p].data(), items[tl][p].size() * sizeof(unsigned int),
+                                  hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(b->params64, params, (size_t)n * sizeof(mm_params), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpyAsync(b->region, region_dev, nc, hipMemcpyDeviceToDevice, b->stream);
         for (int i = 0; i < n && e == hipSuccess; ++i)
@@ -562,7 +582,24 @@ int mm_batch_set_grid(mm_batch* b, int32_t pass, int32_t grid) {
 
 int mm_batch_get_grid(mm_batch* b, int32_t pass, int32_t* grid) {
     if (!b || pass < 0 || pass >= BP_N || !grid) return MM_EINVAL;
-    *grid = grid_of(b, pass);
+    *grid = nitems_of(b, pass) > 0 ? grid_of(b, pass) : 0;
+    return MM_OK;
+}
+
+int mm_batch_set_tile(mm_batch* b, int32_t pass, int32_t tile) {
+    if (!b || pass < 0 || pass >= BP_N || (tile != TILE_WIDE && tile != TILE_NARROW)) return MM_EINVAL;
+    if (!b->tile_ok[pass][tile]) return MM_EUNSUPPORTED;
+    if (b->tile[pass] != tile) {
+        b->tile[pass] = tile;
+        b->grid[pass] = 0;  // the persistent grid was chosen for the other list
+    }
+    drop_graph(b);
+    return MM_OK;
+}
+
+int mm_batch_get_tile(mm_batch* b, int32_t pass, int32_t* tile) {
+    if (!b || pass < 0 || pass >= BP_N || !tile) return MM_EINVAL;
+    *tile = b->tile[pass];
     return MM_OK;
 }
 
@@ -589,55 +626,66 @@ int mm_batch_autotune(mm_batch* b, const float* m_dev) {
     const float a_last = af.sd.nk > 0 ? af.sd.a[af.sd.nk - 1] : 0.f;
     if (af.sd.nk > 0) --af.sd.nk;
     const ColArgs c = base_col(b, false);
-    auto launch = [&](int p, int g) -> hipError_t {
+    auto launch = [&](int p, int tl, int g) -> hipError_t {
+        BatchList l = list(b, p);
+        l.items = b->items[p][tl];
+        l.nitems = b->nitems[p][tl];
         switch (p) {
             case BP_X:
-                return launch_bx(BX_ROW, list(b, BP_X), g, ai, af, a_last, b->stream);
+                return launch_bx(BX_ROW, l, g, ai, af, a_last, b->stream, tl);
             case BP_C3:
-                return launch_bcol3(list(b, BP_C3), g, c, b->stream);
+                return launch_bcol3(l, g, c, b->stream, tl);
             case BP_Y:
-                return launch_bcoly(0, list(b, BP_Y), g, c, b->stream);
+                return launch_bcoly(0, l, g, c, b->stream);
             case BP_Z4:
             case BP_Z8:
             case BP_Z16:
-                return launch_bzconv(p, list(b, p), g, c, b->stream);
+                return launch_bzconv(p, l, g, c, b->stream);
             case BP_YZ4:
             case BP_YZ8:
-                return launch_byz(p, list(b, p), g, c, b->stream);
+                return launch_byz(p, l, g, c, b->stream);
             default:
                 return hipSuccess;
         }
     };
+    // candidates per pass: every tile shape that serves all members, each
+    // with one workgroup per tile and 1, 2, 4 x its resident workgroups per
+    // CU on every CU
     for (int p = 0; p < BP_N && status == MM_OK; ++p) {
-        if (p == BP_F || b->nitems[p] == 0) continue;
-        int res = 0;
-        if (batch_resident(p, &res) != hipSuccess || res < 1) res = 1;
-        const int full = full_grid(b->nitems[p]);
-        std::vector<int> cand = {full};
-        for (int k : {1, 2, 4}) {
-            const int g = ((k * res * b->ncu + 7) / 8) * 8;
-            if (g < full) cand.push_back(g);
-        }
+        if (p == BP_F || b->nitems[p][TILE_WIDE] == 0) continue;
         float best = INFINITY;
-        int best_g = full;
-        for (int g : cand) {
-            hipError_t e = launch(p, g);  // warm-up
-            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch(p, g);
-            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                status = map_err(e);
-                break;
+        int best_g = 0, best_t = TILE_WIDE;
+        for (int tl : {TILE_WIDE, TILE_NARROW}) {
+            if (!b->tile_ok[p][tl] || status != MM_OK) continue;
+            int res = 0;
+            if (batch_resident(p, tl, &res) != hipSuccess || res < 1) res = 1;
+            const int full = full_grid(b->nitems[p][tl]);
+            std::vector<int> cand = {full};
+            for (int k : {1, 2, 4}) {
+                const int g = ((k * res * b->ncu + 7) / 8) * 8;
+                if (g < full) cand.push_back(g);
             }
-            if (ms < best) {
-                best = ms;
-                best_g = g;
+            for (int g : cand) {
+                hipError_t e = launch(p, tl, g);  // warm-up
+                if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+                for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch(p, tl, g);
+                if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    status = map_err(e);
+                    break;
+                }
+                if (ms < best) {
+                    best = ms;
+                    best_g = g == full ? 0 : g;
+                    best_t = tl;
+                }
             }
         }
-        b->grid[p] = best_g == full ? 0 : best_g;
+        b->tile[p] = best_t;
+        b->grid[p] = best_g;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

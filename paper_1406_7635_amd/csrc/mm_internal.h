@@ -208,21 +208,30 @@ enum BatchPass {
 };
 enum BatchXKind { BX_FWD = 0, BX_ROW = 1, BX_INV = 2 };
 enum BatchColKind { BC_CONV2 = 0, BC_YFWD = 1, BC_YINV = 2, BC_ZCONV = 3, BC_YZ = 4 };
+// Tile shapes of the x passes and the 2D column pass: wide (the single-grid
+// wide workgroups: 768 / 256 threads) or narrow (192 / 64 threads, a quarter
+// of the row pairs or columns per item; padded lengths <= 512 only).
+enum BatchTile { TILE_WIDE = 0, TILE_NARROW = 1 };
 // Padded lengths the batched passes serve: 64 <= px, py <= 1024, pz in {1, 4, 8, 16}.
 bool batch_supported(int px, int py, int pz);
-// Tiles (work items) of member m in pass p; 0 when the pass does not apply to it.
-int batch_tiles(int pass, const BMember& m);
-// Workgroups of pass p that fit on one compute unit at once.
-hipError_t batch_resident(int pass, int* per_cu);
+// Whether tile shape `tile` of pass p serves member m (every shape but the
+// narrow x / 2D column shapes serves every member).
+bool batch_tile_serves(int pass, int tile, const BMember& m);
+// Tiles (work items) of member m in pass p with tile shape `tile`; 0 when the
+// pass does not apply to it (or the shape does not serve it).
+int batch_tiles(int pass, const BMember& m, int tile = TILE_WIDE);
+// Workgroups of pass p (tile shape `tile`) that fit on one compute unit at once.
+hipError_t batch_resident(int pass, int tile, int* per_cu);
 hipError_t configure_batch_kernels(void);
 // Every launcher takes the pass's work list and its number of persistent
 // workgroups (a multiple of 8).  x passes: fi (and ff for the fused pass)
-// hold the base pointers, stage descriptor and flags.
+// hold the base pointers, stage descriptor and flags; the work list must be
+// the one built for the tile shape.
 hipError_t launch_bx(int kind, const BatchList& l, int grid, const FieldArgs& fi, const FieldArgs& ff, float a_last,
-                     hipStream_t s);
+                     hipStream_t s, int tile);
 // Column passes; base holds the spectrum, kernel and state base pointers, the
 // twiddles and check_done.  2D y convolution of the members with nz = 1:
-hipError_t launch_bcol3(const BatchList& l, int grid, const ColArgs& base, hipStream_t s);
+hipError_t launch_bcol3(const BatchList& l, int grid, const ColArgs& base, hipStream_t s, int tile);
 // y transforms (forward, or inverse) of the members with nz > 1:
 hipError_t launch_bcoly(int inverse, const BatchList& l, int grid, const ColArgs& base, hipStream_t s);
 // z convolution of the members of one padded z length (pass BP_Z4 / BP_Z8 / BP_Z16):

@@ -99,6 +99,8 @@ EXPORTS = {
     "mm_batch_set_graph": (c_int32, [c_void_p, c_int32]),
     "mm_batch_set_grid": (c_int32, [c_void_p, c_int32, c_int32]),
     "mm_batch_get_grid": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int32)]),
+    "mm_batch_set_tile": (c_int32, [c_void_p, c_int32, c_int32]),
+    "mm_batch_get_tile": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int32)]),
     "mm_batch_autotune": (c_int32, [c_void_p, c_void_p]),
     "mm_batch_destroy": (None, [c_void_p]),
     "mm_sno_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, c_int32, c_void_p, c_int64, c_double,
@@ -440,6 +442,7 @@ class Context:
 
 
 BATCH_PASSES = ("x", "conv2d", "y", "z4", "z8", "z16", "yz4", "yz8", "finalize")  # mm_batch_set_grid pass ids
+BATCH_TILES = ("wide", "narrow")  # mm_batch_set_tile shapes
 
 
 class Batch:
@@ -566,7 +569,22 @@ class Batch:
         _check(load().mm_batch_get_grid(self._h, p, ctypes.byref(g)), "mm_batch_get_grid")
         return g.value
 
+    def set_tile(self, pass_, tile):
+        """Tile shape of the x passes ("x") or the 2D y convolution
+        ("conv2d"): "wide" or "narrow"."""
+        p = BATCH_PASSES.index(pass_) if isinstance(pass_, str) else int(pass_)
+        t = BATCH_TILES.index(tile) if isinstance(tile, str) else int(tile)
+        _check(load().mm_batch_set_tile(self._h, p, t), "mm_batch_set_tile")
+
+    def get_tile(self, pass_):
+        p = BATCH_PASSES.index(pass_) if isinstance(pass_, str) else int(pass_)
+        t = c_int32()
+        _check(load().mm_batch_get_tile(self._h, p, ctypes.byref(t)), "mm_batch_get_tile")
+        return BATCH_TILES[t.value]
+
     def autotune(self, m):
+        """Tuned persistent grids per pass (0: a pass no member uses); the
+        tuned tile shapes are read with get_tile."""
         _check(load().mm_batch_autotune(self._h, _ptr(self._vec(m))), "mm_batch_autotune")
         return {name: self.get_grid(i) for i, name in enumerate(BATCH_PASSES)}
 

@@ -6,7 +6,7 @@ schedule, so every member is checked against its own single-grid context
 also directly against the oracle, and the ensemble at its full size (512
 members, about 1e7 cells) on sampled members.  Graph replays are checked
 against direct launches with eager work between the replays, and tuned
-persistent grids against one workgroup per tile.
+persistent grids and tile shapes against one wide workgroup per tile.
 """
 import math
 
@@ -153,6 +153,48 @@ def test_batch_tuned_grids_same_result(gpu):
     b.start(45, 0.0, 1e-14, float("inf"))
     b.run(m2, 6)
     assert np.array_equal(to_np(m2), ref)
+    b.close()
+
+
+def test_batch_tile_shapes_same_result(gpu):
+    """The narrow tile shapes of the x passes and of the 2D y convolution (a
+    quarter of the row pairs or columns per work item) run the same
+    arithmetic per row and column as the wide ones: bit-identical states in
+    every combination, also on a small persistent grid and after the
+    autotuner's choice of shape and grid; the narrow shape is refused when a
+    member's padded length exceeds 512."""
+    members = mixed_members(seed=43, shapes=SHAPES[:8])
+    log("batch: tile shapes")
+    b = mm.Batch(members)
+
+    def run():
+        m = b.pack([c["m0"] for c in members])
+        b.start(45, 0.0, 1e-14, float("inf"))
+        b.run(m, 6)
+        return to_np(m)
+
+    ref = run()
+    for tx, tc in (("narrow", "wide"), ("wide", "narrow"), ("narrow", "narrow")):
+        b.set_tile("x", tx)
+        b.set_tile("conv2d", tc)
+        assert (b.get_tile("x"), b.get_tile("conv2d")) == (tx, tc)
+        assert np.array_equal(run(), ref), (tx, tc)
+    b.set_grid("x", 8)
+    b.set_grid("conv2d", 16)
+    assert np.array_equal(run(), ref)
+    m = b.pack([c["m0"] for c in members])
+    grids = b.autotune(m)
+    tiles = {p: b.get_tile(p) for p in ("x", "conv2d")}
+    log("  tuned", grids, tiles)
+    assert np.array_equal(run(), ref)
+    with pytest.raises(mm.MMError):
+        b.set_tile("y", "narrow")
+    b.close()
+    big = mixed_members(seed=44, shapes=[(17, 33, 1), (512, 24, 1)])  # px 1024
+    b = mm.Batch(big)
+    with pytest.raises(mm.MMError):
+        b.set_tile("x", "narrow")
+    b.set_tile("conv2d", "narrow")  # py 64 and 128: served
     b.close()
 
 
