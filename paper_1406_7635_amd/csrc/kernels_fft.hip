@@ -8,6 +8,20 @@
 namespace mm {
 
 
+// Tile order of the passes that evaluate the exchange field (x-inverse and
+// fused), for grids of several layers: the tiles of one y block over all z
+// planes follow each other, so the z neighbours of a row (a plane apart) are
+// in tiles that run in the same round and come from L2; in plane-major order
+// they are a plane's worth of tiles away and are fetched from HBM again.  A
+// bijection on the tiles whenever no tile straddles two planes (else the
+// natural order).  Partial sums stay indexed by tile, so results do not change.
+__device__ inline int x_tile_order(int t, const FieldArgs& a, int rows_per_tile) {
+    if (a.nz <= 1 || a.ny % rows_per_tile) return t;
+    const int tpp = a.ny / rows_per_tile;  // tiles per plane
+    const int yb = t / a.nz, z = t - yb * a.nz;
+    return z * tpp + yb;
+}
+
 // FULL: x is a periodic axis transformed at its own length (P = nx).
 // W: workgroup width (XCfg): 0 wide, 1 narrow (grids with few rows).
 template <int P, bool FULL, int W>
@@ -34,7 +48,7 @@ k_xinv(const FieldArgs a) {
     __shared__ long long rbs[2 * GI];
     const Resolved rs = resolve(a);
     if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int blk = x_tile_order(xcd_remap(blockIdx.x, gridDim.x), a, 2 * GI);
     row_bases<GI>(a, blk * GI, rbs, threadIdx.x);
     __syncthreads();
     xinv_part<P, false, DMI, FULL, W>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), red, blk,
@@ -56,7 +70,7 @@ k_xrow(const FieldArgs ai, const FieldArgs af, float a_last) {
     __shared__ long long rbs[2 * GI];
     const Resolved rsi = resolve(ai);
     if ((ai.flags & EPI_CHECK_DONE) && rsi.done) return;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int blk = x_tile_order(xcd_remap(blockIdx.x, gridDim.x), ai, 2 * GI);
     row_bases<GI>(ai, blk * GI, rbs, threadIdx.x);
     __syncthreads();
     RegionLut* lut_l = reinterpret_cast<RegionLut*>(lds + GI * GL);

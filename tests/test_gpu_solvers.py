@@ -66,6 +66,33 @@ def test_single_steps_match_run(gpu):
     assert np.max(np.abs(to_np(m) - to_np(m2))) == 0.0
 
 
+@pytest.mark.parametrize("grid", [(32, 32, 8), (64, 48, 6), (20, 64, 5)])
+def test_dp45_attempts_multilayer_tile_order(gpu, grid):
+    """Grids of several layers whose x tiles never straddle two planes, where
+    the x-inverse and fused passes take their tiles y block by y block over
+    all planes: B_eff at the start, three accepted Dormand-Prince attempts at
+    a fixed step against the oracle's embedded steps (m within 2e-6), and the
+    torque of the result."""
+    case = synth.random_problem(grid, (2e-9, 2.5e-9, 3e-9), seed=sum(grid) + 7, nregions=3)
+    ctx, prob, m = make_pair(case)
+    f = prob.torque
+    m_ref = case["m0"].astype(np.float64)
+    assert rel_inf(to_np(ctx.beff(m)), prob.beff(m_ref)) < 1e-5
+    k1 = f(m_ref)
+    t, dt = 0.0, 2e-14
+    opts = mm.solver_opts(max_err=1.0)
+    for _ in range(3):
+        acc, t, _, err = ctx.rk45_step(m, t, dt, opts)
+        assert acc
+        ms, k1, eps = ointegrate.embedded_step(f, m_ref, k1, dt, ointegrate.DP45)
+        m_ref = ointegrate.normalize(ms)
+        d = float(np.max(np.abs(to_np(m) - m_ref)))
+        log("multilayer DP45", grid, "|dm| %.2e err %.3e / %.3e" % (d, err, eps))
+        assert d < 2e-6
+    assert rel_inf(to_np(ctx.torque(m)), prob.torque(to_np(m).astype(np.float64))) < 1e-5
+    ctx.close()
+
+
 def _macrospin(alpha, b, msat=1.0 / MU0):
     p = synth.material(msat, 1e-11, alpha=alpha, bext=b)
     return {"grid": (1, 1, 1), "cell": (1e-9, 1e-9, 1e-9), "region": np.zeros((1, 1, 1), np.uint8),
