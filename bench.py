@@ -32,6 +32,7 @@ HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_1406_7635_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "film1024_rk45_hbm_traffic.txt")
 DEVICE_WARMUP_S = 0.3  # untimed attempts on a scratch state before the warm-up attempts
+REPEAT_WINDOWS = 5     # timed windows of the film (the first one is `value`)
 
 
 # the sources the single-grid field kernels are compiled from (kernels,
@@ -156,6 +157,22 @@ def cpu_baseline(case, reps=5):
             "sample": "median of %d FP64 B_eff+torque evaluations of the %dx%dx%d vortex state (scipy.fft with "
                       "%d workers); the oracle's demag tensor set-up (%.1f s) not included"
                       % (reps, case["grid"][0], case["grid"][1], case["grid"][2], threads, t_init)}
+
+
+def oracle_timing(reps=5):
+    """The FP64 oracle timed on this host for the three parity states: the
+    32x32x4 RK4 film, the 1024x1024x1 vortex film and the 256x256x64 grains
+    (median of `reps` B_eff + torque evaluations each, tensor set-up apart)."""
+    from paper_1406_7635_amd import synth
+
+    out = {"kind": "oracle", "unit": "Beff evals*cells/s", "cores": os.cpu_count(), "cpu_model": cpu_model()}
+    for name, case in (("film32x32x4", synth.parity_cube(seed=1)), ("vortex1024", synth.vortex_film(seed=2, n=1024)),
+                       ("grains256x256x64", synth.grains(seed=3))):
+        r = cpu_baseline(case, reps)
+        out[name] = {k: r[k] for k in ("value", "median_eval_s", "eval_s", "kernel_init_s")}
+        print("oracle %s: %.3g cell evals/s, median %.3f s, set-up %.1f s" % (name, r["value"], r["median_eval_s"],
+                                                                            r["kernel_init_s"]), flush=True)
+    return out
 
 
 def periodic_variant(n, steps, warmup):
@@ -544,6 +561,8 @@ def main():
                     help="only the 3D grain-workload variant (one JSON line; for profiling)")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the surrogate variant (one JSON line; for profiling)")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only the FP64 oracle's host timing on the 32x32x4, 1024^2 and 256x256x64 states")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the batched-ensemble variant (one JSON line; for profiling)")
     ap.add_argument("--traffic", default=TRAFFIC_FILE,
@@ -571,6 +590,9 @@ def main():
         return
     if args.ensemble_only:
         print(json.dumps(ensemble_variant(max(4, args.steps // 10), max(2, args.warmup // 5))))
+        return
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing()))
         return
     if args.grains_only:
         print(json.dumps(grains_variant(max(5, args.steps // 20), max(2, args.warmup // 10))))
@@ -620,6 +642,15 @@ def main():
         if n:
             per[name] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms": ms}
     dominant = max(per, key=lambda k: per[k]["total_ms"])
+    # four more uninstrumented windows of `steps` attempts: the spread of the
+    # timed figure (value itself is the first window)
+    windows = [value]
+    for _ in range(REPEAT_WINDOWS - 1):
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        t, dt, st3 = ctx.run(m, float("inf"), t=t, dt=dt, max_attempts=args.steps, opts=opts)
+        torch.cuda.synchronize()
+        windows.append(ncell * st3["evals"] / (time.perf_counter() - r0))
     copy_gbs = copy_bandwidth()
     bytes_per_launch = {"x_forward": xfwd_pass_bytes(ctx, 1), "column_conv": column_pass_bytes(ctx),
                         "x_inverse": xinv_pass_bytes(ctx, 5), "x_row": xrow_pass_bytes(ctx, DP45_XROW_K)}
@@ -645,7 +676,10 @@ def main():
                    "evals_per_step": 6, "gpu_event_ms": gpu_ms,
                    "kernel_timing": "second pass of %d attempts, dispatch-recorded HIP events" % args.steps,
                    "device_warmup": "%.1f s of untimed attempts on a scratch copy of m before the %d warm-up "
-                                    "attempts" % (DEVICE_WARMUP_S, args.warmup)},
+                                    "attempts" % (DEVICE_WARMUP_S, args.warmup),
+                   "repeats": {"windows": REPEAT_WINDOWS, "values": windows,
+                               "median": float(np.median(windows)),
+                               "note": "value is the first window; the others follow the kernel-timing pass"}},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
                      "copy_GBs": copy_gbs, "frac_of_copy": ach / copy_gbs,
