@@ -300,9 +300,12 @@ __device__ inline void xfwd_part(const FieldArgs& a, const Resolved& rs, cf* lds
 // Inverse x pass of one workgroup: staged coalesced spectrum read, Hermitian
 // extension, inverse FFT, crop, per-cell epilogue (FUSED: the torque also to
 // LDS for the next stage's combine), reductions.  The region table goes to
-// LDS at lut_l.
+// LDS at lut_l.  A run that already reached its end (EPI_CHECK_DONE) stops
+// once the staged spectrum is in LDS, before anything is written to global
+// memory, and the call returns false: the solver-state read behind the test
+// then overlaps the spectrum loads instead of preceding them.
 template <int P, bool FUSED, bool DMI = false, bool FULL = false, int XW = 0>
-__device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
+__device__ inline bool xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds, const long long* rbs,
                                  RegionLut* lut_l, double* red, int blk, int tid) {
     constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, GI = XCfg<P, XW>::GI, NTH = XCfg<P, XW>::NTH;
     constexpr int SEQ = seq_len(P), GL = XCfg<P, XW>::GL;
@@ -331,6 +334,7 @@ __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds
         if (i < NIT - 1 || sc.kq0 + Staged<P, XW>::KS * i < Staged<P, XW>::GI * XCfg<P, XW>::KH) lds[li[i]] = tmp[i];
     lut.store(lut_l, tid);
     __syncthreads();
+    if ((a.flags & EPI_CHECK_DONE) && rs.done) return false;
     // slot s = u + i w (slot 0: x, y of row a; slot 1: x, y of row b; slot 2: z of
     // rows a and b); the DC and Nyquist bins of a real signal are real
     const int iu = slot == 2 ? 2 : slot * 3, iw = slot == 2 ? 5 : slot * 3 + 1;
@@ -409,6 +413,7 @@ __device__ inline void xinv_part(const FieldArgs& a, const Resolved& rs, cf* lds
     // the fused pass serves inner stages only (no error norm, no reductions)
     if constexpr (!FUSED)
         if (a.flags & (EPI_ERR | EPI_MAXTQ | EPI_ENERGY)) epi_reduce<NTH>(a, acc, red, blk);
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -861,7 +866,9 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
     constexpr int PPT = Cfg<P>::PPT, TPF = Cfg<P>::TPF, T = Col3Cfg<P, W>::T;
     constexpr int SEQ = Col3Cfg<P, W>::SEQ, KHP = Col3Cfg<P, W>::KHP, CL = Col3Cfg<P, W>::CL;
     constexpr int MH = FULL ? PPT : PPT / 2;  // registers that load and store rows
-    if (a.check_done && a.st->done) return;
+    // a finished run is tested once the column is loaded and transformed
+    // (nothing is written before), so the state read overlaps the loads
+    const int done = a.check_done ? a.st->done : 0;
     const int t = tid % TPF, ci = tid / TPF;
     const int c = blk * T + ci;
     const bool valid = c < a.ncol;
@@ -887,6 +894,7 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
         }
     }
     RegFft<P, TPF, 3, false, !FULL>::run(v, buf, a.tw, a.twshift, t);
+    if (done) return;
 
     // B^ = K^ M^ (2D: K^ = [[xx, xy, 0], [xy, yy, 0], [0, 0, zz]], xy odd in y);
     // row q of column kx is (xx, yy, zz, xy) at K^[kx][min(q, P - q)]

@@ -208,7 +208,7 @@ __device__ inline void bx_item(const FieldArgs& fi, const FieldArgs& ff, float a
         xinv_part<P, false, false, false, XW>(a, rs, lds, rbs, lut_l, red, blk, tid);
     } else {
         __syncthreads();
-        xinv_part<P, true, false, false, XW>(a, rs, lds, rbs, lut_l, red, blk, tid);
+        if (!xinv_part<P, true, false, false, XW>(a, rs, lds, rbs, lut_l, red, blk, tid)) return;
         __syncthreads();
         const FieldArgs af = member_field(ff, mb, i);
         const Resolved rsf = resolve(af);

@@ -46,11 +46,12 @@ k_xinv(const FieldArgs a) {
     extern __shared__ cf lds[];
     __shared__ double red[(NTH / 64 > 0 ? NTH / 64 : 1) * 6];
     __shared__ long long rbs[2 * GI];
-    const Resolved rs = resolve(a);
-    if ((a.flags & EPI_CHECK_DONE) && rs.done) return;
     const int blk = x_tile_order(xcd_remap(blockIdx.x, gridDim.x), a, 2 * GI);
     row_bases<GI>(a, blk * GI, rbs, threadIdx.x);
     __syncthreads();
+    // the solver state only now: its read overlaps the spectrum loads (the
+    // finished-run test is inside, after them)
+    const Resolved rs = resolve(a);
     xinv_part<P, false, DMI, FULL, W>(a, rs, lds, rbs, reinterpret_cast<RegionLut*>(lds + GI * GL), red, blk,
                                       threadIdx.x);
 }
@@ -68,13 +69,12 @@ k_xrow(const FieldArgs ai, const FieldArgs af, float a_last) {
     extern __shared__ cf lds[];
     __shared__ double red[(NTH / 64 > 0 ? NTH / 64 : 1) * 6];
     __shared__ long long rbs[2 * GI];
-    const Resolved rsi = resolve(ai);
-    if ((ai.flags & EPI_CHECK_DONE) && rsi.done) return;
     const int blk = x_tile_order(xcd_remap(blockIdx.x, gridDim.x), ai, 2 * GI);
     row_bases<GI>(ai, blk * GI, rbs, threadIdx.x);
     __syncthreads();
+    const Resolved rsi = resolve(ai);  // read overlaps the spectrum loads
     RegionLut* lut_l = reinterpret_cast<RegionLut*>(lds + GI * GL);
-    xinv_part<P, true, DMI, FULL, W>(ai, rsi, lds, rbs, lut_l, red, blk, threadIdx.x);
+    if (!xinv_part<P, true, DMI, FULL, W>(ai, rsi, lds, rbs, lut_l, red, blk, threadIdx.x)) return;
     __syncthreads();
     // the next stage's pointers only now (short live ranges across the first part)
     const Resolved rsf = resolve(af);
