@@ -106,7 +106,19 @@ int main() {
     mm_grid gb[1] = {g};
     gb[0].nx = 1024;
     expect("batch member too large", mm_batch_create(&b, 1, gb, ps, region.data(), nullptr), MM_EUNSUPPORTED);
+    int32_t gv = 0, tv = 0;
+    expect("batch set grid null", mm_batch_set_grid(nullptr, 0, 8), MM_EINVAL);
+    expect("batch get grid null", mm_batch_get_grid(nullptr, 0, &gv), MM_EINVAL);
+    expect("batch set tile null", mm_batch_set_tile(nullptr, 0, 1), MM_EINVAL);
+    expect("batch get tile null", mm_batch_get_tile(nullptr, 0, &tv), MM_EINVAL);
+    expect("batch autotune null", mm_batch_autotune(nullptr, &dummy), MM_EINVAL);
     mm_batch_destroy(nullptr);
+
+    // checkpoint calls
+    int64_t sz = 0;
+    expect("state size null ctx", mm_state_size(nullptr, &sz), MM_EINVAL);
+    expect("state save null ctx", mm_state_save(nullptr, &dummy, 4), MM_EINVAL);
+    expect("state load null ctx", mm_state_load(nullptr, &dummy, 4, &dummy), MM_EINVAL);
 
     // surrogate and its trainer
     std::vector<float> w(MM_SNO_NWEIGHTS, 0.f);
