@@ -23,13 +23,19 @@ __device__ inline void st3(float* __restrict__ p, long long n, long long i, floa
 }
 // Loads and stores through a uniform base and a 32-bit byte offset: an array
 // of 3 ncell floats (ncell <= 2^28) stays below 2^32 bytes, so every offset
-// fits, and the access takes the scalar-base + vector-offset form with no
-// 64-bit address arithmetic per lane.
+// fits.  They go through a raw buffer resource (base, no stride, 2^32 - 1
+// bytes; the third word is the gfx9 family's untyped 32-bit format), so the
+// base stays in scalar registers and each lane supplies only its 32-bit
+// offset: no 64-bit address arithmetic per lane.  Every base passed here is
+// uniform over the workgroup.
+__device__ inline __amdgpu_buffer_rsrc_t buffer_of(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)0xffffffffu, 0x00020000);
+}
 __device__ inline float ldo(const float* base, unsigned int off) {
-    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + off);
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(buffer_of(base), (int)off, 0, 0));
 }
 __device__ inline void sto(float* base, unsigned int off, float v) {
-    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + off) = v;
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), buffer_of(base), (int)off, 0, 0);
 }
 // components at byte offsets off, off + n4, off + 2 n4 from one base (n4 =
 // 4 ncell; 3 ncell < 2^30 floats): one scalar base per array
