@@ -450,7 +450,9 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
     constexpr int SEQ = col_seq<P, CFAST>();
     constexpr bool PAIR = col_pairs<P, MODE, NC>();
     constexpr int TH = PAIR ? T / 2 : T;  // K^ blocks per tile
-    if (a.check_done && a.st->done) return;
+    // a finished run is tested after the forward transform (nothing is
+    // written before), so the state read overlaps the column loads
+    const int done = a.check_done ? a.st->done : 0;
     int ci, s, t;
     if (CFAST) {
         s = tid % 3;
@@ -476,8 +478,12 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
     }
     // 2D convolution: column 0 carries kx = 0 (real part) and kx = px/2 (imaginary part)
     const bool packed = MODE == COL_CONV && NC == 4 && a.pack_col > 0 && c == 0;
-    cf* base = a.spec + (long long)o * a.outer_stride + (long long)(valid ? c : 0) * a.col_stride;
-    cf* baseN = a.spec + (long long)a.pack_col * a.col_stride;
+    // the workgroup's outer slab (uniform) and 32-bit element offsets within
+    // it: a slab of the spectrum (at most 2048 x 4096 x 3 complex for the
+    // largest grids) stays far below 2^32 bytes
+    cf* obase = a.spec + (long long)o * a.outer_stride;
+    const unsigned int coff = (unsigned int)(valid ? c : 0) * (unsigned int)a.col_stride;
+    const unsigned int noff = (unsigned int)a.pack_col * (unsigned int)a.col_stride;  // from a.spec
     cf* bufs = lds + ci * 3 * SEQ;
     cf* buf = bufs + s * SEQ;
 
@@ -491,9 +497,9 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
     for (int m = 0; m < PPT; ++m) {
         const int q = t + TPF * m;
         const bool ld = m < MIN && valid && q < a.n_in;
-        const long long off = (long long)q * a.pos_stride + s;
-        cf x = ld ? base[off] : mkc(0.f, 0.f);
-        if (packed) x = mkc(x.x, ld ? baseN[off].x : 0.f);
+        const unsigned int off = (unsigned int)q * (unsigned int)a.pos_stride + (unsigned int)s;
+        cf x = ld ? ld_cf(obase, (coff + off) * 8u) : mkc(0.f, 0.f);
+        if (packed) x = mkc(x.x, ld ? ld_cf(a.spec, (noff + off) * 8u).x : 0.f);
         v[0][m] = x;
     }
     // 2D convolution: the K^ rows of the workgroup's columns go to LDS now, so
@@ -525,6 +531,8 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
     if constexpr (MODE == COL_CONV && NC == 6) {
         constexpr int BL = KHP * 3;  // float2 per column block
         constexpr int TOT = TH * BL, NTH = ColCfg<P>::NTH, NIT = (TOT + NTH - 1) / NTH;
+        // the kx slab of K^ (uniform) and 32-bit offsets within it
+        const cf* kslab = reinterpret_cast<const cf*>(a.khat + (long long)o * a.kyh * (KHP * 6));
         float2 kt[NIT];
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
@@ -540,8 +548,8 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
                 in = (i < NIT - 1 || e < TOT) && cy < a.ncol;
                 kyh = 2 * cy > a.pa ? a.pa - cy : cy;
             }
-            const float2* src = reinterpret_cast<const float2*>(a.khat + ((long long)o * a.kyh + kyh) * (KHP * 6));
-            kt[i] = in ? src[r] : make_float2(0.f, 0.f);
+            const cf kv = in ? ld_cf(kslab, (unsigned int)(kyh * BL + r) * 8u) : mkc(0.f, 0.f);
+            kt[i] = make_float2(kv.x, kv.y);
         }
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
@@ -550,6 +558,7 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
         }
     }
     RegFft<P, TPF, 1, MODE == COL_INV, HIN>::run(v, buf, a.tw, a.twshift, t);
+    if (done) return;
 
     if (MODE == COL_CONV) {
         // all three components of this column through LDS
@@ -684,12 +693,12 @@ __device__ inline void col_body(const ColArgs& a, int blk, cf* lds, int tid) {
     for (int m = 0; m < MOUT; ++m) {
         const int q = t2 + TPF * m;
         if (valid && q < a.n_out) {
-            const long long off = (long long)q * a.pos_stride + s;
+            const unsigned int off = (unsigned int)q * (unsigned int)a.pos_stride + (unsigned int)s;
             if (!packed) {
-                base[off] = v[0][m];
+                st_cf(obase, (coff + off) * 8u, v[0][m]);
             } else {
-                base[off] = mkc(v[0][m].x, 0.f);
-                baseN[off] = mkc(v[0][m].y, 0.f);
+                st_cf(obase, (coff + off) * 8u, mkc(v[0][m].x, 0.f));
+                st_cf(a.spec, (noff + off) * 8u, mkc(v[0][m].y, 0.f));
             }
         }
     }
