@@ -25,10 +25,11 @@ __host__ __device__ inline cf cmul(cf a, cf b) {
 }
 __host__ __device__ inline cf cconj(cf a) { return mkc(a.x, -a.y); }
 
-#ifdef __HIP_DEVICE_COMPILE__
 // Complex load and store through a raw buffer resource: uniform base in
 // scalar registers, 32-bit byte offset per lane (no 64-bit address
 // arithmetic); the third resource word is the gfx9 family's untyped format.
+// Device code only (declared in both compilation passes, as device code
+// that the host pass parses refers to them).
 __device__ inline __amdgpu_buffer_rsrc_t cf_buffer(const cf* base) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<cf*>(base), (short)0, (int)0xffffffffu, 0x00020000);
 }
@@ -39,7 +40,6 @@ __device__ inline void st_cf(cf* base, unsigned int byte_off, cf v) {
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), cf_buffer(base), (int)byte_off, 0, 0);
 }
-#endif
 
 // multiply by exp(+-i pi/2): forward (INV=false) by -i, inverse by +i
 template <bool INV>
