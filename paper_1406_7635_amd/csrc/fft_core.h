@@ -55,13 +55,14 @@ __host__ __device__ inline int ilog2_rt(int n) {
     return l;
 }
 
-// LDS position of sequence element i: three spare elements after every 32.
-// The contiguous reads of a wave then meet at most one spare run and the
-// Stockham writes of stride 1, 4 and 32 land on nearly disjoint banks; being
-// additive, the per-register offsets still fold into the instructions'
-// immediate offsets.
+// LDS position of sequence element i outside the transforms (staging,
+// separation, crop): three spare elements after every 32, so contiguous wave
+// accesses meet at most one spare run; being additive over 32-aligned
+// offsets, the per-register offsets fold into the instructions' immediate
+// offsets.  The exchanges inside a transform use their own padding
+// (RegFft::xpad), at most one spare per 8 elements.
 __host__ __device__ constexpr int lds_pad(int i) { return i + 3 * (i >> 5); }
-__host__ __device__ constexpr int seq_len(int P) { return P + 3 * (P >> 5); }
+__host__ __device__ constexpr int seq_len(int P) { return P + (P >> 3); }
 
 // R-point DFTs in registers -------------------------------------------------
 template <int R, bool INV>
@@ -263,6 +264,27 @@ struct RegFft {
         }
     }
 
+    // LDS position of element i in the exchange whose writes have radix RP
+    // and span lp (the exchange that feeds a stage).  Each wave writes its 16-lane
+    // groups (8 bytes a lane, 128 bytes a group) so that no two lanes share a
+    // bank: span 1 writes lanes RP elements apart, which one spare per 16
+    // elements spreads over all banks; spans 2 ... 8 write runs of lp elements
+    // RP lp apart, which lp spares per RP lp elements stagger; from span 16 on the
+    // runs are contiguous and need none.  Every form is additive over the
+    // thread's register offsets (r lp, r TPF for TPF a multiple of 8 lp), so
+    // they fold into immediate offsets, and stays below P + P/8.
+    __host__ __device__ static int xpad(int rp, int lp, int i) {
+        if (lp == 1) return i + (i >> 4);
+        if (lp < 16) {
+            const int sh = ilog2_rt(rp * lp), sl = ilog2_rt(lp);
+            return i + ((i >> sh) << sl);
+        }
+        return i;
+    }
+    // radix and span of the writes of the exchange that feeds stage s (>= 1)
+    __host__ __device__ static int xrp(int s) { return s == 1 ? R0 : PPT; }
+    __host__ __device__ static int xlp(int s) { return s == 1 ? 1 : span(s - 1); }
+
     // write the outputs of stage s-1 of sequence f at their positions
     template <int RP>
     __host__ __device__ static void write_r(int lp, const cf (&v)[NF][PPT], int f, cf* buf, int t) {
@@ -272,7 +294,7 @@ struct RegFft {
             const int k = j & (lp - 1);
             const int base = (j - k) * RP + k;
 #pragma unroll
-            for (int r = 0; r < RP; ++r) buf[lds_pad(base + r * lp)] = v[f][uu * RP + r];
+            for (int r = 0; r < RP; ++r) buf[xpad(RP, lp, base + r * lp)] = v[f][uu * RP + r];
         }
     }
     __host__ __device__ static void write(int s, const cf (&v)[NF][PPT], int f, cf* buf, int t) {
@@ -283,9 +305,10 @@ struct RegFft {
     }
 
     // read the inputs of stage s (>= 1) for sequence f
-    __host__ __device__ static void read(cf (&v)[NF][PPT], int f, const cf* buf, int t) {
+    __host__ __device__ static void read(int s, cf (&v)[NF][PPT], int f, const cf* buf, int t) {
+        const int rp = xrp(s), lp = xlp(s);
 #pragma unroll
-        for (int r = 0; r < PPT; ++r) v[f][r] = buf[lds_pad(t + r * TPF)];
+        for (int r = 0; r < PPT; ++r) v[f][r] = buf[xpad(rp, lp, t + r * TPF)];
     }
     // twiddle and butterfly of stage s (>= 1) for sequence f
     __host__ __device__ static void compute(cf (&v)[NF][PPT], int f, const cf (&wt)[PPT]) {
@@ -295,8 +318,7 @@ struct RegFft {
     }
     __host__ __device__ static void read_compute(int s, cf (&v)[NF][PPT], int f, const cf* buf, int t,
                                                  const cf (&wt)[PPT]) {
-        (void)s;
-        read(v, f, buf, t);
+        read(s, v, f, buf, t);
         compute(v, f, wt);
     }
 
@@ -335,7 +357,7 @@ struct RegFft {
                     write_r<PPT>(span(s - 1), v, f, buf, t);
                 if (f > 0) compute(v, f - 1, wt);
                 __syncthreads();
-                read(v, f, buf, t);
+                read(s, v, f, buf, t);
             }
             compute(v, NF - 1, wt);
         }
