@@ -890,16 +890,25 @@ __device__ inline void col3_body(const ColArgs& a, int blk, cf* lds, int tid) {
     const float4* kh = reinterpret_cast<const float4*>(a.khat);
 
     // rows y < ny <= P/2 hold data, the rest is zero padding (all P rows with FULL)
+    // (two loops, so no load waits on another: a select of the packed
+    // column's second half inside one loop makes every load wait for the last)
     cf v[3][PPT];
+    if (!packed) {
 #pragma unroll
-    for (int m = 0; m < PPT; ++m) {
-        const int q = t + TPF * m;
-        const bool ld = m < MH && valid && q < a.n_in;
+        for (int m = 0; m < PPT; ++m) {
+            const int q = t + TPF * m;
+            const bool ld = m < MH && valid && q < a.n_in;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            cf x = ld ? base[3LL * q + k] : mkc(0.f, 0.f);
-            if (packed) x = mkc(x.x, ld ? baseN[3LL * q + k].x : 0.f);
-            v[k][m] = x;
+            for (int k = 0; k < 3; ++k) v[k][m] = ld ? base[3LL * q + k] : mkc(0.f, 0.f);
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
+            const int q = t + TPF * m;
+            const bool ld = m < MH && valid && q < a.n_in;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                v[k][m] = ld ? mkc(base[3LL * q + k].x, baseN[3LL * q + k].x) : mkc(0.f, 0.f);
         }
     }
     RegFft<P, TPF, 3, false, !FULL>::run(v, buf, a.tw, a.twshift, t);
